@@ -1,0 +1,65 @@
+/* Internal declarations of the CPU oracle (test infrastructure). */
+#ifndef VCS_ORACLE_MACHINE_H
+#define VCS_ORACLE_MACHINE_H
+
+#include <stdint.h>
+
+/* status flags */
+#define FL_C 0x01
+#define FL_Z 0x02
+#define FL_I 0x04
+#define FL_D 0x08
+#define FL_B 0x10
+#define FL_U 0x20
+#define FL_V 0x40
+#define FL_N 0x80
+
+typedef struct {
+    /* cartridge */
+    const uint8_t* rom;
+    uint32_t rom_size;
+    uint32_t scheme;            /* 0 = 4 KB, 1 = F8 (2 x 4 KB) */
+    uint8_t bank;
+    /* 6507 */
+    uint8_t a, x, y, sp, p;
+    uint16_t pc;
+    uint64_t cycle;             /* start cycle of the next instruction */
+    uint64_t beam_cycle;        /* first cycle the beam and timer have not yet passed */
+    uint64_t instr_count;
+    /* RIOT */
+    uint8_t ram[128];
+    uint8_t tim_count;
+    uint8_t tim_expired;
+    uint16_t tim_sub;
+    uint16_t tim_interval;
+    /* TIA write registers (last byte written) and player positions */
+    uint8_t vsync, vblank, colup0, colup1, colupf, colubk, ctrlpf, refp0, refp1;
+    uint8_t pf0, pf1, pf2, grp0, grp1, hmp0, hmp1;
+    uint8_t p0x, p1x;
+    /* the frame being emulated */
+    uint64_t frame_line0;
+    uint8_t* fb;                /* 210 x 160 frame buffer, or NULL */
+    /* console inputs of the current frame */
+    uint8_t swcha, inpt4;
+    /* env bookkeeping */
+    uint32_t rom_id, step_idx, episode_idx;
+    uint8_t prev_action, err;
+    /* per-instruction scratch */
+    uint64_t access_cycle;
+    uint64_t end_cycle;         /* last cycle of the frame that just ended */
+    int timer_written, wsync_hit, vsync_on;
+} OMachine;
+
+/* frame end reasons */
+#define END_VSYNC 1
+#define END_CAP 2
+#define END_ILLEGAL 3
+
+void m_power_on(OMachine* m, const uint8_t* rom, uint32_t size, uint32_t scheme);
+int m_step_instruction(OMachine* m);      /* 0 or an END_* code */
+int m_run_frame(OMachine* m, uint8_t* fb, uint64_t* end_cycle);
+void m_set_action(OMachine* m, uint32_t action);
+void m_to_record(const OMachine* m, uint8_t* out);
+void m_from_record(OMachine* m, const uint8_t* in);
+
+#endif

@@ -1,0 +1,169 @@
+/*
+ * vcs355 -- batched Atari 2600 emulation on one MI355X (gfx950), C ABI.
+ *
+ * The operation (paper, Section 3 "CUDA Learning Environment" and the
+ * footnote on raw frames in Section 1): many independent consoles (6507 CPU,
+ * 128 B RAM, cartridge ROM, TIA video, RIOT timer) step in lockstep on the
+ * GPU; an env step emulates `frameskip` frames; frames are 160x210; the
+ * observation is the pixelwise maximum of the last two frames of the step,
+ * downsampled to 84x84 gray; episodes restart from a per-ROM cache of 30
+ * initial states built from 64 start-up frames and up to 30 random no-op
+ * frames.  Observations stay in device memory.
+ *
+ * Machine semantics the paper leaves open (6502 ISA, TIA/RIOT maps, timing,
+ * frame boundary, palette, preprocessing arithmetic, sticky actions) follow
+ * the conventions stated with each kernel in the library sources; they are
+ * the same conventions the test oracle implements independently.
+ *
+ * Conventions for every call:
+ *  - "_dev" pointers are device pointers on the context's device, owned by
+ *    the caller; "_host" pointers are host memory, read (or written) before
+ *    the call returns.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  vcs_reset and
+ *    vcs_step only enqueue work on it and never synchronise.
+ *  - Return values: VCS_OK or a negative VCS_E_* code; the message of the
+ *    last failure on the calling thread is in vcs_last_error().
+ *  - Argument errors the host can see (NULL pointers, n > max_batch, bad
+ *    sizes) are rejected before anything is enqueued.  Errors only the device
+ *    can see (an env id out of range or repeated in one call, an action >= 18,
+ *    an undocumented opcode, a frame that never ends) set per-env error bits
+ *    that vcs_poll_errors reports; such envs report done = 1 and restart from
+ *    the cache; out-of-range ids are skipped, never dereferenced.
+ *  - One context must not be used from two threads at once.
+ */
+#ifndef VCS355_H
+#define VCS355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VCS_STATE_BYTES 256      /* machine-state record, see vcs_get_state */
+#define VCS_FRAME_H 210
+#define VCS_FRAME_W 160
+#define VCS_OBS 84
+#define VCS_N_ACTIONS 18
+
+enum {
+    VCS_OK = 0,
+    VCS_E_INVAL = -1,   /* bad argument */
+    VCS_E_NOMEM = -2,   /* device or host allocation failed */
+    VCS_E_ROM = -3,     /* ROM size / bank scheme not supported */
+    VCS_E_HIP = -4,     /* a HIP runtime call failed */
+    VCS_E_STATE = -5,   /* call out of order (e.g. step before assign) */
+    VCS_E_BUDGET = -6   /* the allocation would exceed hbm_budget_bytes */
+};
+
+enum { VCS_BANK_4K = 0, VCS_BANK_F8 = 1 };
+enum { VCS_RENDER_ALL = 0, VCS_RENDER_LAST2 = 1 };
+
+/* per-env error bits (vcs_poll_errors) */
+enum {
+    VCS_ERR_ILLEGAL = 1,      /* undocumented opcode executed */
+    VCS_ERR_FRAME_CAP = 2,    /* no VSYNC within 320 scanlines */
+    VCS_ERR_BAD_ACTION = 4,   /* action >= 18 */
+    VCS_ERR_BAD_ID = 8,       /* env id out of range or repeated in one call */
+    VCS_ERR_LOG = 16          /* render log row capacity exceeded */
+};
+
+typedef struct {
+    uint32_t num_envs;          /* resident envs */
+    uint32_t frameskip;         /* frames per step, >= 1 (the paper uses 4) */
+    uint32_t sticky_threshold;  /* a frame repeats the previous frame's action
+                                   when (R(seed, env, 1, step*frameskip+f) >> 32)
+                                   < threshold; floor(p * 2^32); 0 = off   */
+    uint32_t reset_cache_k;     /* cached initial states per ROM (paper: 30) */
+    uint32_t noop_max;          /* no-op frames per cache entry: 0..noop_max (30) */
+    uint32_t startup_frames;    /* start-up frames per cache entry (paper: 64)   */
+    uint64_t seed;              /* seed of the counter-based RNG (SplitMix64)    */
+    uint32_t render_mode;       /* VCS_RENDER_ALL: every frame is rendered;
+                                   VCS_RENDER_LAST2: only frames frameskip-2 and
+                                   frameskip-1 of a step (the two the
+                                   observation needs)                           */
+    uint32_t max_batch;         /* largest n of one step/reset call (0 = num_envs) */
+    uint64_t hbm_budget_bytes;  /* cap on device memory the context allocates; 0 = none */
+    int32_t device;             /* HIP device ordinal */
+    uint8_t gray_lut[128];      /* gray level of colour index (colour >> 1)      */
+} vcs_config;
+
+typedef struct vcs_ctx vcs_ctx;
+
+/* Create a context: validates the config, allocates env state, render logs
+   and scratch on `device`.  VCS_E_BUDGET when they exceed the budget. */
+int vcs_create(const vcs_config* cfg, vcs_ctx** out);
+void vcs_destroy(vcs_ctx* ctx);
+
+/* Copy n_roms cartridges to the device.  rom_bytes[r] is 4096 (VCS_BANK_4K) or
+   8192 (VCS_BANK_F8, two 4 KB banks selected by accesses to $1FF8/$1FF9).
+   The host buffers are copied; the caller keeps ownership. */
+int vcs_load_roms(vcs_ctx* ctx, uint32_t n_roms, const uint8_t* const* rom_host,
+                  const uint32_t* rom_bytes, const uint32_t* scheme);
+
+/* env_rom_host[num_envs]: the ROM of every env.  Builds each ROM's reset cache
+   on the device (power-on, run to the first frame end, startup_frames NOOP
+   frames, n_k NOOP frames) and puts every env into a cache state
+   (as vcs_reset).  Synchronises the device. */
+int vcs_assign(vcs_ctx* ctx, const uint16_t* env_rom_host);
+
+/* Restart envs env_ids_dev[0..n) (NULL = envs 0..n-1) from a random cache
+   entry; obs_dev[n][84][84] (may be NULL) receives their observations. */
+int vcs_reset(vcs_ctx* ctx, const int32_t* env_ids_dev, uint32_t n, uint8_t* obs_dev, void* stream);
+
+/* One env step for envs env_ids_dev[0..n) (NULL = envs 0..n-1) with
+   actions_dev[n] in [0, 18).  Outputs, indexed like env_ids_dev:
+     obs_dev[n][84][84]    observation (the cache entry's for envs that ended)
+     reward_dev[n]         change of the BCD score byte at $D0 over the step
+     done_dev[n]           1 when RAM[$D1] became non-zero (or the env faulted);
+                           the env is then already restarted from the cache
+     frames_dev            NULL, or [n][F][210][160] palette-index frames with
+                           F = frameskip (RENDER_ALL) or 2 (RENDER_LAST2, the
+                           frames frameskip-2 and frameskip-1); frames that
+                           were not emulated (the step stopped early) are 0. */
+int vcs_step(vcs_ctx* ctx, const int32_t* env_ids_dev, const uint8_t* actions_dev, uint32_t n,
+             uint8_t* obs_dev, int32_t* reward_dev, uint8_t* done_dev, uint8_t* frames_dev,
+             void* stream);
+
+/* Machine-state record (256 bytes, little-endian) of one env:
+     0 A  1 X  2 Y  3 SP  4 P  5 bank  6..7 PC
+     8..15 cycle (start of the next instruction, since power-on)
+    16..23 scanline of the write that began the current frame
+    24 INTIM a read at `cycle` would return   25 timer expired (0/1)
+    26..27 timer interval (1, 8, 64, 1024)   28..29 cycles since the last
+           decrement (0 once expired)
+    32..159 RAM $80..$FF
+   160 VSYNC 161 VBLANK 162 COLUP0 163 COLUP1 164 COLUPF 165 COLUBK 166 CTRLPF
+   167 REFP0 168 REFP1 169 PF0 170 PF1 171 PF2 172 GRP0 173 GRP1 174 HMP0
+   175 HMP1 176 P0 position 177 P1 position
+   180..183 rom_id 184..187 step count 188..191 episode count 192 previous
+   action 194 error bits 200..207 instructions executed; other bytes 0.
+   get/set synchronise the device. */
+int vcs_get_state(vcs_ctx* ctx, uint32_t env_id, uint8_t* out_host);
+int vcs_set_state(vcs_ctx* ctx, uint32_t env_id, const uint8_t* in_host);
+
+/* Cache entry k of ROM `rom`: state record and 84x84 observation (host). */
+int vcs_get_cache(vcs_ctx* ctx, uint32_t rom, uint32_t k, uint8_t* state_host, uint8_t* obs_host);
+
+/* Error bits OR-ed over all envs since the last poll, and the smallest env id
+   that raised one (0xFFFFFFFF if none); clears them.  Synchronises. */
+int vcs_poll_errors(vcs_ctx* ctx, uint32_t* first_env, uint32_t* bits);
+
+/* Instructions emulated by the last vcs_step (sum over its envs); synchronises.
+   Used to report emulated-instruction throughput. */
+int vcs_last_step_instructions(vcs_ctx* ctx, uint64_t* out);
+
+/* Average device time of the named kernel over the timed region: the caller
+   brackets steps with vcs_timing(ctx, 1) ... vcs_timing(ctx, 0), then reads
+   the mean duration in ms and launch count of kernel `which`
+   (0 = interpreter, 1 = render, 2 = render+preprocess, 3 = reset).
+   Events are recorded on the stream each kernel is launched on. */
+int vcs_timing(vcs_ctx* ctx, int enable);
+int vcs_kernel_time(vcs_ctx* ctx, int which, double* mean_ms, uint32_t* launches);
+
+const char* vcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -18,6 +18,9 @@
  *    dec(b) = 10*(b >> 4) + (b & 15);
  *  - obs = 84x84 exact-area resize of max(gray(F_{k-1}), gray(F_k)) over the
  *    last two frames the step emulated (gray(F_1) when it emulated one);
+ *  - frames output: every frame of the step (render mode ALL) or frames
+ *    frameskip-2 and frameskip-1 (mode LAST2, the two the paper renders);
+ *    frames not emulated because the step stopped early are 0;
  *  - a done env is reset at the end of the same step (eager reset): the
  *    returned obs is that of the cache entry, the returned reward and done
  *    are those of the terminal step;
@@ -328,8 +331,11 @@ static uint32_t step_env(oracle_ctx* c, uint32_t e, uint8_t action, uint8_t* obs
         if (c->cfg.render_mode == ORC_RENDER_ALL) {
             memcpy(out, fb, (size_t)k * fsz);
         } else {
-            if (k >= 1) memcpy(out + fsz, fb + (size_t)(k - 1) * fsz, fsz);
-            if (k >= 2) memcpy(out, fb + (size_t)(k - 2) * fsz, fsz);
+            /* the two frames selective rendering keeps: fs-2 and fs-1 (0 if not emulated) */
+            for (int s = 0; s < 2; s++) {
+                int f = (int)fs - 2 + s;
+                if (f >= 0 && (uint32_t)f < k) memcpy(out + (size_t)s * fsz, fb + (size_t)f * fsz, fsz);
+            }
         }
     }
     if (render && obs && k >= 1)

@@ -186,3 +186,14 @@ def test_last2_frames_mode():
     ob, rb, db, fb = b.step(acts, want_frames=True)
     assert fb.shape == (3, 2, 210, 160)
     assert np.array_equal(fa[:, 2:], fb) and np.array_equal(oa, ob)
+
+
+def test_last2_frames_of_an_early_stop_are_zero():
+    o = make(2, seed=9, render_mode=oracle.RENDER_LAST2)
+    T = ROM.manifest["T"]
+    st = o.get_state(0)
+    st[32 + 0x54], st[32 + 0x55] = (T - 3) & 0xFF, (T - 3) >> 8    # ends after frame 3 of 4
+    o.set_state(0, st)
+    _, _, done, fr = o.step(np.array([0, 0], np.uint8), want_frames=True)
+    assert done[0] == 1 and fr[0][0].any() and not fr[0][1].any()
+    assert fr[1][0].any() and fr[1][1].any()

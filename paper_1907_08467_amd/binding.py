@@ -1,0 +1,177 @@
+"""ctypes binding of libvcs355.so (include/vcs355.h): argument marshalling only.
+
+Every step of the emulation runs in the library's HIP kernels.  Importing this
+module loads the library and fails loudly if it has not been built; there is
+no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch  # noqa: F401  -- loads the HIP runtime the library links against
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvcs355.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vcs355.h")
+
+VCS_OK, VCS_E_INVAL, VCS_E_NOMEM, VCS_E_ROM, VCS_E_HIP, VCS_E_STATE, VCS_E_BUDGET = 0, -1, -2, -3, -4, -5, -6
+VCS_BANK_4K, VCS_BANK_F8 = 0, 1
+VCS_RENDER_ALL, VCS_RENDER_LAST2 = 0, 1
+ERR_ILLEGAL, ERR_FRAME_CAP, ERR_BAD_ACTION, ERR_BAD_ID, ERR_LOG = 1, 2, 4, 8, 16
+STATE_BYTES = 256
+
+
+class VcsConfig(ctypes.Structure):
+    _fields_ = [
+        ("num_envs", ctypes.c_uint32),
+        ("frameskip", ctypes.c_uint32),
+        ("sticky_threshold", ctypes.c_uint32),
+        ("reset_cache_k", ctypes.c_uint32),
+        ("noop_max", ctypes.c_uint32),
+        ("startup_frames", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("render_mode", ctypes.c_uint32),
+        ("max_batch", ctypes.c_uint32),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("device", ctypes.c_int32),
+        ("gray_lut", ctypes.c_uint8 * 128),
+    ]
+
+
+class VcsError(RuntimeError):
+    def __init__(self, code, what, msg):
+        super().__init__(f"{what} failed ({code}): {msg}")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _declare(L):
+    L.vcs_create.argtypes = [ctypes.POINTER(VcsConfig), ctypes.POINTER(_vp)]
+    L.vcs_destroy.argtypes = [_vp]
+    L.vcs_destroy.restype = None
+    L.vcs_load_roms.argtypes = [_vp, ctypes.c_uint32, ctypes.POINTER(_u8p), _vp, _vp]
+    L.vcs_assign.argtypes = [_vp, _vp]
+    L.vcs_reset.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp]
+    L.vcs_step.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp]
+    L.vcs_get_state.argtypes = [_vp, ctypes.c_uint32, _vp]
+    L.vcs_set_state.argtypes = [_vp, ctypes.c_uint32, _vp]
+    L.vcs_get_cache.argtypes = [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp]
+    L.vcs_poll_errors.argtypes = [_vp, _vp, _vp]
+    L.vcs_last_step_instructions.argtypes = [_vp, _vp]
+    L.vcs_timing.argtypes = [_vp, ctypes.c_int]
+    L.vcs_kernel_time.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+    L.vcs_last_error.argtypes = []
+    L.vcs_last_error.restype = ctypes.c_char_p
+    for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_get_state",
+                 "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions",
+                 "vcs_timing", "vcs_kernel_time"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    _declare(L)
+    return L
+
+
+lib = load()
+
+
+def header_functions():
+    """Names of the functions include/vcs355.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(vcs_\w+)\s*\(", text, re.M)))
+
+
+def check(rc, what):
+    if rc != VCS_OK:
+        raise VcsError(rc, what, lib.vcs_last_error().decode(errors="replace"))
+    return rc
+
+
+# thin wrappers with the C names -------------------------------------------
+
+def vcs_create(cfg: VcsConfig):
+    h = _vp()
+    check(lib.vcs_create(ctypes.byref(cfg), ctypes.byref(h)), "vcs_create")
+    return h
+
+
+def vcs_destroy(h):
+    lib.vcs_destroy(h)
+
+
+def vcs_load_roms(h, roms, schemes):
+    keep = [ctypes.create_string_buffer(bytes(r), len(r)) for r in roms]
+    arr = (_u8p * len(roms))(*[ctypes.cast(k, _u8p) for k in keep])
+    sizes = (ctypes.c_uint32 * len(roms))(*[len(r) for r in roms])
+    sch = (ctypes.c_uint32 * len(roms))(*schemes)
+    check(lib.vcs_load_roms(h, len(roms), arr, sizes, sch), "vcs_load_roms")
+
+
+def vcs_assign(h, env_rom):
+    import numpy as np
+    er = np.ascontiguousarray(env_rom, dtype=np.uint16)
+    check(lib.vcs_assign(h, er.ctypes.data_as(_vp)), "vcs_assign")
+
+
+def vcs_reset(h, ids_ptr, n, obs_ptr, stream):
+    check(lib.vcs_reset(h, ids_ptr, n, obs_ptr, stream), "vcs_reset")
+
+
+def vcs_step(h, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_ptr, stream):
+    check(lib.vcs_step(h, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_ptr, stream), "vcs_step")
+
+
+def vcs_get_state(h, env):
+    buf = (ctypes.c_uint8 * STATE_BYTES)()
+    check(lib.vcs_get_state(h, env, buf), "vcs_get_state")
+    return bytes(buf)
+
+
+def vcs_set_state(h, env, rec):
+    buf = (ctypes.c_uint8 * STATE_BYTES).from_buffer_copy(bytes(rec))
+    check(lib.vcs_set_state(h, env, buf), "vcs_set_state")
+
+
+def vcs_get_cache(h, rom, k):
+    st = (ctypes.c_uint8 * STATE_BYTES)()
+    ob = (ctypes.c_uint8 * (84 * 84))()
+    check(lib.vcs_get_cache(h, rom, k, st, ob), "vcs_get_cache")
+    return bytes(st), bytes(ob)
+
+
+def vcs_poll_errors(h):
+    first = ctypes.c_uint32()
+    bits = ctypes.c_uint32()
+    check(lib.vcs_poll_errors(h, ctypes.byref(first), ctypes.byref(bits)), "vcs_poll_errors")
+    return first.value, bits.value
+
+
+def vcs_last_step_instructions(h):
+    v = ctypes.c_uint64()
+    check(lib.vcs_last_step_instructions(h, ctypes.byref(v)), "vcs_last_step_instructions")
+    return v.value
+
+
+def vcs_timing(h, enable):
+    check(lib.vcs_timing(h, int(enable)), "vcs_timing")
+
+
+def vcs_kernel_time(h, which):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_uint32()
+    check(lib.vcs_kernel_time(h, which, ctypes.byref(ms), ctypes.byref(cnt)), "vcs_kernel_time")
+    return ms.value, cnt.value
+
+
+def vcs_last_error():
+    return lib.vcs_last_error().decode(errors="replace")

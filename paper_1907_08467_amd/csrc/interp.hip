@@ -1,0 +1,792 @@
+// 6507 interpreter kernel: one lane per env, one wave per ROM-homogeneous tile.
+//
+// What it computes (paper, Section 3): the "Atari CPU kernel" -- each env's
+// CPU runs the cartridge code, updates its 128 B of RAM and the CPU state, and
+// passes every TIA register write on to the renderer instead of drawing.
+// Here the TIA writes go into a row log (vcs_device.h) only for the frames
+// that will be rendered (all frames, or the last two of the step).
+//
+// Machine conventions (the paper gives none; the public 6502/TIA/RIOT
+// definitions plus these readings):
+//  * bus: a = addr & $1FFF; a & $1000 cartridge, else a & $80 == 0 TIA,
+//    else a & $200 == 0 RAM[a & $7F], else RIOT;
+//  * an instruction that starts at cycle t and lasts n cycles performs all its
+//    data accesses at cycle t+n-1; opcode/operand fetches happen at t and have
+//    no side effects; RMW writes once; no dummy reads;
+//  * a TIA write at cycle c takes effect at colour clock 3(c+1); WSYNC written
+//    at c resumes the CPU at 76*(c/76+1); a frame ends after the instruction
+//    that turns VSYNC bit 1 on; 320 scanlines without that end the frame
+//    (FRAME_CAP), as does an undocumented opcode (ILLEGAL);
+//  * RIOT timer in closed form: after TIMnT <- v written at cycle w, a read at
+//    t sees e = t-w-1: INTIM = v - e/n while e < (v+1)n, then
+//    ($FF - (e - (v+1)n)) & $FF with TIMINT bit 7 set;
+//  * decimal ADC/SBC follow the NMOS behaviour described by B. Clark
+//    ("Decimal Mode", 6502.org, Appendix A).
+//
+// Dispatch: each loop iteration every running lane fetches its next opcode;
+// the wave then executes one opcode at a time for all lanes that share it
+// (readfirstlane + compare), so the opcode is a scalar and the handler is a
+// branch-free specialisation picked by a scalar jump table.  In lockstep (the
+// common case for envs of one ROM) that is a single pass.  TIA writes are
+// queued during the handler and applied in one shared block afterwards.
+#include "vcs_device.h"
+
+namespace vcs {
+
+enum Mn : int {
+    ADC, AND, ASL, BCC, BCS, BEQ, BIT, BMI, BNE, BPL, BRK, BVC, BVS, CLC, CLD, CLI, CLV, CMP,
+    CPX, CPY, DEC, DEX, DEY, EOR, INC, INX, INY, JMP, JSR, LDA, LDX, LDY, LSR, NOP, ORA, PHA,
+    PHP, PLA, PLP, ROL, ROR, RTI, RTS, SBC, SEC, SED, SEI, STA, STX, STY, TAX, TAY, TSX, TXA,
+    TXS, TYA, ILL
+};
+enum Md : int { IMP, ACC, IMM, ZP, ZPX, ZPY, ABS, ABX, ABY, IZX, IZY, IND, REL };
+
+struct OpInfo {
+    int mn, md, cyc;
+    bool pen;   // +1 cycle on an indexed page cross
+};
+
+// Decode from the opcode's aaabbbcc structure (documented opcodes only).
+constexpr OpInfo decode(int op) {
+    const int a = op >> 5, b = (op >> 2) & 7, cc = op & 3;
+    OpInfo ill{ILL, IMP, 2, false};
+    if (cc == 1) {
+        const int mns[8] = {ORA, AND, EOR, ADC, STA, LDA, CMP, SBC};
+        const int mds[8] = {IZX, ZP, IMM, ABS, IZY, ZPX, ABY, ABX};
+        const int rd_cyc[8] = {6, 3, 2, 4, 5, 4, 4, 4};
+        const int st_cyc[8] = {6, 3, 0, 4, 6, 4, 5, 5};
+        if (mns[a] == STA) {
+            if (b == 2) return ill;
+            return OpInfo{STA, mds[b], st_cyc[b], false};
+        }
+        return OpInfo{mns[a], mds[b], rd_cyc[b], b == 4 || b == 6 || b == 7};
+    }
+    if (cc == 2) {
+        const int mns[8] = {ASL, ROL, LSR, ROR, STX, LDX, DEC, INC};
+        const int mn = mns[a];
+        const bool rmw = (a < 4) || (a >= 6);
+        switch (b) {
+        case 0: return a == 5 ? OpInfo{LDX, IMM, 2, false} : ill;
+        case 1: return OpInfo{mn, ZP, rmw ? 5 : 3, false};
+        case 2:
+            if (a < 4) return OpInfo{mn, ACC, 2, false};
+            if (a == 4) return OpInfo{TXA, IMP, 2, false};
+            if (a == 5) return OpInfo{TAX, IMP, 2, false};
+            if (a == 6) return OpInfo{DEX, IMP, 2, false};
+            return OpInfo{NOP, IMP, 2, false};
+        case 3: return OpInfo{mn, ABS, rmw ? 6 : 4, false};
+        case 5: return OpInfo{mn, (a == 4 || a == 5) ? ZPY : ZPX, rmw ? 6 : 4, false};
+        case 6:
+            if (a == 4) return OpInfo{TXS, IMP, 2, false};
+            if (a == 5) return OpInfo{TSX, IMP, 2, false};
+            return ill;
+        case 7:
+            if (a == 4) return ill;
+            if (a == 5) return OpInfo{LDX, ABY, 4, true};
+            return OpInfo{mn, ABX, 7, false};
+        default: return ill;
+        }
+    }
+    if (cc == 0) {
+        if (b == 4) {
+            const int br[8] = {BPL, BMI, BVC, BVS, BCC, BCS, BNE, BEQ};
+            return OpInfo{br[a], REL, 2, false};
+        }
+        if (b == 6) {
+            const int fl[8] = {CLC, SEC, CLI, SEI, TYA, CLV, CLD, SED};
+            return OpInfo{fl[a], IMP, 2, false};
+        }
+        if (b == 2) {
+            const int st[8] = {PHP, PLP, PHA, PLA, DEY, TAY, INY, INX};
+            const int cy[8] = {3, 4, 3, 4, 2, 2, 2, 2};
+            return OpInfo{st[a], IMP, cy[a], false};
+        }
+        if (b == 0) {
+            switch (a) {
+            case 0: return OpInfo{BRK, IMP, 7, false};
+            case 1: return OpInfo{JSR, ABS, 6, false};
+            case 2: return OpInfo{RTI, IMP, 6, false};
+            case 3: return OpInfo{RTS, IMP, 6, false};
+            case 5: return OpInfo{LDY, IMM, 2, false};
+            case 6: return OpInfo{CPY, IMM, 2, false};
+            case 7: return OpInfo{CPX, IMM, 2, false};
+            default: return ill;
+            }
+        }
+        const int mns[8] = {ILL, BIT, JMP, JMP, STY, LDY, CPY, CPX};
+        if (b == 1) return (a == 1 || a >= 4) ? OpInfo{mns[a], ZP, 3, false} : ill;
+        if (b == 3) {
+            if (a == 0) return ill;
+            if (a == 2) return OpInfo{JMP, ABS, 3, false};
+            if (a == 3) return OpInfo{JMP, IND, 5, false};
+            return OpInfo{mns[a], ABS, 4, false};
+        }
+        if (b == 5) return (a == 4 || a == 5) ? OpInfo{mns[a], ZPX, 4, false} : ill;
+        if (b == 7) return a == 5 ? OpInfo{LDY, ABX, 4, true} : ill;
+        return ill;
+    }
+    return ill;
+}
+
+constexpr int op_len(int md) {
+    return (md == IMP || md == ACC) ? 1 : (md == ABS || md == ABX || md == ABY || md == IND) ? 3 : 2;
+}
+
+// status flags
+constexpr uint32_t FC = 0x01, FZ = 0x02, FI = 0x04, FD = 0x08, FB = 0x10, FU = 0x20, FV = 0x40, FN = 0x80;
+// per-instruction events
+constexpr uint32_t EV_WSYNC = 1, EV_VSYNC = 2;
+
+// SWCHA high nibble (active low: D7 right, D6 left, D5 down, D4 up) and
+// fire, for the 18 actions in ALE order.
+__constant__ uint8_t kJoy[18] = {0x00, 0x00, 0x10, 0x80, 0x40, 0x20, 0x90, 0x50, 0xA0, 0x60,
+                                 0x10, 0x80, 0x40, 0x20, 0x90, 0x50, 0xA0, 0x60};
+__constant__ uint8_t kFire[18] = {0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1};
+
+struct Wave {                 // per-workgroup (uniform) data
+    uint8_t* rom;             // LDS copy of the tile's cartridge
+    uint8_t* ram;             // LDS, kRamStride bytes per lane
+    uint8_t* tia;             // LDS, kTiaStride bytes per lane
+    uint32_t f8;              // 1 = F8 bank switching
+};
+constexpr int kRamStride = 132;   // 33 dwords: bank-conflict free for equal offsets
+constexpr int kTiaStride = 20;    // 5 dwords
+
+struct Cpu {
+    uint32_t a, x, y, sp, p, pc, bank;
+    uint64_t base;            // absolute cycle of the start of the lane's base line
+    uint32_t cyc;             // cycles since `base`
+    int32_t fl;               // scanline of the frame's start write, relative to the base line
+    uint32_t cap;             // an instruction starting at or after this cycle ends the frame
+    uint32_t swcha, inpt4;
+    uint32_t vsync, hmp0, hmp1;
+    int64_t tbase;            // absolute
+    uint32_t tv, tshift;
+    uint32_t ev, err;
+    uint32_t ac;              // access cycle of the current instruction
+    uint32_t tq0, tq1, tq2, tqm;   // queued TIA writes (reg | value << 8) and their mask
+    uint32_t ram_off, tia_off;
+    uint8_t* log;             // current frame's row log, or nullptr
+    uint32_t slot, slots;     // its slot; slots completed so far
+    int32_t open_row;
+    uint32_t open_cnt;
+    uint32_t icount;
+};
+
+__device__ __forceinline__ uint32_t nz(uint32_t p, uint32_t v) {
+    return (p & ~(FN | FZ)) | (v & FN) | (v == 0 ? FZ : 0);
+}
+
+__device__ __forceinline__ uint32_t tia_read(const Cpu& c, uint32_t a) {
+    const uint32_t r = a & 0x0F;
+    return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);
+}
+
+__device__ __forceinline__ uint32_t riot_read(const Cpu& c, const Wave& W, uint32_t a, uint32_t t) {
+    if (!(a & 4)) {
+        const uint32_t r = a & 3;
+        return r == 0 ? c.swcha : (r == 2 ? 0x0Bu : 0u);
+    }
+    const int64_t e = (int64_t)(c.base + t) - c.tbase;
+    const int64_t lim = (int64_t)(c.tv + 1) << c.tshift;
+    const bool expired = e >= lim;
+    if (a & 1) return expired ? 0x80u : 0u;
+    return expired ? (uint32_t)((0xFF - (e - lim)) & 0xFF) : (uint32_t)(c.tv - (uint32_t)(e >> c.tshift)) & 0xFF;
+}
+
+__device__ __forceinline__ void cart_touch(Cpu& c, const Wave& W, uint32_t a) {
+    if (W.f8) {
+        const uint32_t lo = a & 0xFFF;
+        if (lo == 0xFF8) c.bank = 0;
+        else if (lo == 0xFF9) c.bank = 1;
+    }
+}
+
+// data read at cycle t (side effects: F8 hotspots)
+__device__ __forceinline__ uint32_t rd(Cpu& c, const Wave& W, uint32_t addr, uint32_t t) {
+    const uint32_t a = addr & 0x1FFF;
+    if (a & 0x1000) {
+        cart_touch(c, W, a);
+        return W.rom[(c.bank << 12) | (a & 0xFFF)];
+    }
+    if (!(a & 0x80)) return tia_read(c, a);
+    if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
+    return riot_read(c, W, a, t);
+}
+
+// read without side effects (instruction fetch, zero-page pointers)
+__device__ __forceinline__ uint32_t peek(const Cpu& c, const Wave& W, uint32_t addr, uint32_t t) {
+    const uint32_t a = addr & 0x1FFF;
+    if (a & 0x1000) return W.rom[(c.bank << 12) | (a & 0xFFF)];
+    if (!(a & 0x80)) return tia_read(c, a);
+    if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
+    return riot_read(c, W, a, t);
+}
+
+__device__ __forceinline__ uint32_t zp_peek(const Cpu& c, const Wave& W, uint32_t z) {
+    return (z & 0x80) ? (uint32_t)W.ram[c.ram_off + (z & 0x7F)] : tia_read(c, z);
+}
+
+// data write at cycle t; TIA writes are queued in slot K of the instruction
+template <int K>
+__device__ __forceinline__ void wr(Cpu& c, const Wave& W, uint32_t addr, uint32_t v, uint32_t t) {
+    const uint32_t a = addr & 0x1FFF;
+    if (a & 0x1000) {
+        cart_touch(c, W, a);
+    } else if (!(a & 0x80)) {
+        const uint32_t q = (a & 0x3F) | ((v & 0xFF) << 8);
+        if (K == 0) c.tq0 = q;
+        if (K == 1) c.tq1 = q;
+        if (K == 2) c.tq2 = q;
+        c.tqm |= 1u << K;
+    } else if (!(a & 0x200)) {
+        W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
+    } else if ((a & 0x14) == 0x14) {     // TIM1T / TIM8T / TIM64T / T1024T
+        const uint32_t sh[4] = {0, 3, 6, 10};
+        c.tv = v & 0xFF;
+        c.tshift = sh[a & 3];
+        c.tbase = (int64_t)(c.base + t) + 1;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void push(Cpu& c, const Wave& W, uint32_t v, uint32_t t) {
+    wr<K>(c, W, 0x100 | c.sp, v, t);
+    c.sp = (c.sp - 1) & 0xFF;
+}
+__device__ __forceinline__ uint32_t pull(Cpu& c, const Wave& W, uint32_t t) {
+    c.sp = (c.sp + 1) & 0xFF;
+    return rd(c, W, 0x100 | c.sp, t);
+}
+
+__device__ __forceinline__ int32_t sext8(uint32_t v) { return (int32_t)(int8_t)(uint8_t)v; }
+
+__device__ __forceinline__ void do_adc(Cpu& c, uint32_t v) {
+    const uint32_t cin = c.p & FC;
+    const uint32_t bin = c.a + v + cin;
+    if (!(c.p & FD)) {
+        const uint32_t ovf = (c.a ^ bin) & (v ^ bin) & 0x80;
+        c.p = (c.p & ~(FC | FV)) | (bin > 0xFF ? FC : 0) | (ovf ? FV : 0);
+        c.a = bin & 0xFF;
+        c.p = nz(c.p, c.a);
+        return;
+    }
+    int32_t lo = (int32_t)((c.a & 0x0F) + (v & 0x0F) + cin);
+    if (lo > 9) lo = ((lo + 6) & 0x0F) + 0x10;
+    int32_t s = (int32_t)(c.a & 0xF0) + (int32_t)(v & 0xF0) + lo;
+    const int32_t ss = sext8(c.a & 0xF0) + sext8(v & 0xF0) + lo;
+    if (s >= 0xA0) s += 0x60;
+    c.p &= ~(FC | FV | FN | FZ);
+    c.p |= (s >= 0x100 ? FC : 0) | ((ss < -128 || ss > 127) ? FV : 0) | (ss & 0x80 ? FN : 0) |
+           ((bin & 0xFF) == 0 ? FZ : 0);
+    c.a = (uint32_t)s & 0xFF;
+}
+
+__device__ __forceinline__ void do_sbc(Cpu& c, uint32_t v) {
+    const uint32_t cin = c.p & FC;
+    const uint32_t inv = (~v) & 0xFF;
+    const uint32_t bin = c.a + inv + cin;
+    const uint32_t ovf = (c.a ^ bin) & (inv ^ bin) & 0x80;
+    uint32_t res = bin & 0xFF;
+    if (c.p & FD) {
+        int32_t lo = (int32_t)(c.a & 0x0F) - (int32_t)(v & 0x0F) + (int32_t)cin - 1;
+        if (lo < 0) lo = ((lo - 6) & 0x0F) - 0x10;
+        int32_t s = (int32_t)(c.a & 0xF0) - (int32_t)(v & 0xF0) + lo;
+        if (s < 0) s -= 0x60;
+        res = (uint32_t)s & 0xFF;
+    }
+    c.p = (c.p & ~(FC | FV)) | (bin > 0xFF ? FC : 0) | (ovf ? FV : 0);
+    c.p = nz(c.p, bin & 0xFF);
+    c.a = res;
+}
+
+__device__ __forceinline__ void do_cmp(Cpu& c, uint32_t r, uint32_t v) {
+    c.p = (c.p & ~FC) | (r >= v ? FC : 0);
+    c.p = nz(c.p, (r - v) & 0xFF);
+}
+
+template <int MN>
+__device__ __forceinline__ uint32_t rmw_op(Cpu& c, uint32_t v) {
+    uint32_t r;
+    if constexpr (MN == ASL) { c.p = (c.p & ~FC) | (v >> 7); r = (v << 1) & 0xFF; }
+    else if constexpr (MN == LSR) { c.p = (c.p & ~FC) | (v & 1); r = v >> 1; }
+    else if constexpr (MN == ROL) { const uint32_t ci = c.p & FC; c.p = (c.p & ~FC) | (v >> 7); r = ((v << 1) | ci) & 0xFF; }
+    else if constexpr (MN == ROR) { const uint32_t ci = c.p & FC; c.p = (c.p & ~FC) | (v & 1); r = (v >> 1) | (ci << 7); }
+    else if constexpr (MN == INC) { r = (v + 1) & 0xFF; }
+    else { r = (v - 1) & 0xFF; }
+    c.p = nz(c.p, r);
+    return r;
+}
+
+template <int MN>
+__device__ __forceinline__ bool branch_cond(uint32_t p) {
+    if constexpr (MN == BPL) return !(p & FN);
+    else if constexpr (MN == BMI) return (p & FN) != 0;
+    else if constexpr (MN == BVC) return !(p & FV);
+    else if constexpr (MN == BVS) return (p & FV) != 0;
+    else if constexpr (MN == BCC) return !(p & FC);
+    else if constexpr (MN == BCS) return (p & FC) != 0;
+    else if constexpr (MN == BNE) return !(p & FZ);
+    else return (p & FZ) != 0;
+}
+
+// Execute opcode OP for the lanes that fetched it.  Sets c.ac, c.pc, c.cyc
+// (before any WSYNC stall) and queues TIA writes.
+template <int OP>
+__device__ __forceinline__ void exec(Cpu& c, const Wave& W, uint32_t b1, uint32_t b2) {
+    constexpr OpInfo I = decode(OP);
+    if constexpr (I.mn == ILL) {
+        c.err |= ERR_ILLEGAL;
+        return;
+    } else {
+        uint32_t n = I.cyc;
+        uint32_t ea = 0;
+        if constexpr (I.md == ZP) ea = b1;
+        else if constexpr (I.md == ZPX) ea = (b1 + c.x) & 0xFF;
+        else if constexpr (I.md == ZPY) ea = (b1 + c.y) & 0xFF;
+        else if constexpr (I.md == ABS || I.md == IND) ea = b1 | (b2 << 8);
+        else if constexpr (I.md == ABX || I.md == ABY) {
+            const uint32_t base = b1 | (b2 << 8);
+            ea = (base + (I.md == ABX ? c.x : c.y)) & 0xFFFF;
+            if constexpr (I.pen) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
+        } else if constexpr (I.md == IZX) {
+            const uint32_t z = (b1 + c.x) & 0xFF;
+            ea = zp_peek(c, W, z) | (zp_peek(c, W, (z + 1) & 0xFF) << 8);
+        } else if constexpr (I.md == IZY) {
+            const uint32_t base = zp_peek(c, W, b1) | (zp_peek(c, W, (b1 + 1) & 0xFF) << 8);
+            ea = (base + c.y) & 0xFFFF;
+            if constexpr (I.pen) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
+        }
+        const uint32_t next = (c.pc + op_len(I.md)) & 0xFFFF;
+        uint32_t npc = next;
+
+        if constexpr (I.md == REL) {
+            if (branch_cond<I.mn>(c.p)) {
+                const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
+                n += 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0);
+                npc = tgt;
+            }
+        }
+        const uint32_t t = c.cyc + n - 1;     // access cycle
+        c.ac = t;
+
+        auto operand = [&]() -> uint32_t {
+            if constexpr (I.md == IMM) return b1;
+            else return rd(c, W, ea, t);
+        };
+
+        if constexpr (I.mn == LDA) { c.a = operand(); c.p = nz(c.p, c.a); }
+        else if constexpr (I.mn == LDX) { c.x = operand(); c.p = nz(c.p, c.x); }
+        else if constexpr (I.mn == LDY) { c.y = operand(); c.p = nz(c.p, c.y); }
+        else if constexpr (I.mn == STA) { wr<0>(c, W, ea, c.a, t); }
+        else if constexpr (I.mn == STX) { wr<0>(c, W, ea, c.x, t); }
+        else if constexpr (I.mn == STY) { wr<0>(c, W, ea, c.y, t); }
+        else if constexpr (I.mn == ADC) { do_adc(c, operand()); }
+        else if constexpr (I.mn == SBC) { do_sbc(c, operand()); }
+        else if constexpr (I.mn == AND) { c.a &= operand(); c.p = nz(c.p, c.a); }
+        else if constexpr (I.mn == ORA) { c.a |= operand(); c.p = nz(c.p, c.a); }
+        else if constexpr (I.mn == EOR) { c.a ^= operand(); c.p = nz(c.p, c.a); }
+        else if constexpr (I.mn == CMP) { do_cmp(c, c.a, operand()); }
+        else if constexpr (I.mn == CPX) { do_cmp(c, c.x, operand()); }
+        else if constexpr (I.mn == CPY) { do_cmp(c, c.y, operand()); }
+        else if constexpr (I.mn == BIT) {
+            const uint32_t v = operand();
+            c.p = (c.p & ~(FN | FV | FZ)) | (v & (FN | FV)) | ((c.a & v) == 0 ? FZ : 0);
+        }
+        else if constexpr (I.mn == ASL || I.mn == LSR || I.mn == ROL || I.mn == ROR || I.mn == INC ||
+                           I.mn == DEC) {
+            if constexpr (I.md == ACC) c.a = rmw_op<I.mn>(c, c.a);
+            else {
+                const uint32_t v = rd(c, W, ea, t);
+                wr<0>(c, W, ea, rmw_op<I.mn>(c, v), t);
+            }
+        }
+        else if constexpr (I.mn == INX) { c.x = (c.x + 1) & 0xFF; c.p = nz(c.p, c.x); }
+        else if constexpr (I.mn == INY) { c.y = (c.y + 1) & 0xFF; c.p = nz(c.p, c.y); }
+        else if constexpr (I.mn == DEX) { c.x = (c.x - 1) & 0xFF; c.p = nz(c.p, c.x); }
+        else if constexpr (I.mn == DEY) { c.y = (c.y - 1) & 0xFF; c.p = nz(c.p, c.y); }
+        else if constexpr (I.mn == TAX) { c.x = c.a; c.p = nz(c.p, c.x); }
+        else if constexpr (I.mn == TAY) { c.y = c.a; c.p = nz(c.p, c.y); }
+        else if constexpr (I.mn == TXA) { c.a = c.x; c.p = nz(c.p, c.a); }
+        else if constexpr (I.mn == TYA) { c.a = c.y; c.p = nz(c.p, c.a); }
+        else if constexpr (I.mn == TSX) { c.x = c.sp; c.p = nz(c.p, c.x); }
+        else if constexpr (I.mn == TXS) { c.sp = c.x; }
+        else if constexpr (I.mn == CLC) { c.p &= ~FC; }
+        else if constexpr (I.mn == SEC) { c.p |= FC; }
+        else if constexpr (I.mn == CLI) { c.p &= ~FI; }
+        else if constexpr (I.mn == SEI) { c.p |= FI; }
+        else if constexpr (I.mn == CLV) { c.p &= ~FV; }
+        else if constexpr (I.mn == CLD) { c.p &= ~FD; }
+        else if constexpr (I.mn == SED) { c.p |= FD; }
+        else if constexpr (I.mn == NOP) { }
+        else if constexpr (I.mn == PHA) { push<0>(c, W, c.a, t); }
+        else if constexpr (I.mn == PHP) { push<0>(c, W, c.p | FB | FU, t); }
+        else if constexpr (I.mn == PLA) { c.a = pull(c, W, t); c.p = nz(c.p, c.a); }
+        else if constexpr (I.mn == PLP) { c.p = (pull(c, W, t) & ~FB) | FU; }
+        else if constexpr (I.mn == JMP) {
+            if constexpr (I.md == ABS) npc = ea;
+            else {
+                const uint32_t lo = rd(c, W, ea, t);
+                const uint32_t hi = rd(c, W, (ea & 0xFF00) | ((ea + 1) & 0xFF), t);
+                npc = lo | (hi << 8);
+            }
+        }
+        else if constexpr (I.mn == JSR) {
+            const uint32_t ret = (next - 1) & 0xFFFF;
+            push<0>(c, W, ret >> 8, t);
+            push<1>(c, W, ret & 0xFF, t);
+            npc = ea;
+        }
+        else if constexpr (I.mn == RTS) {
+            const uint32_t lo = pull(c, W, t);
+            const uint32_t hi = pull(c, W, t);
+            npc = ((lo | (hi << 8)) + 1) & 0xFFFF;
+        }
+        else if constexpr (I.mn == RTI) {
+            c.p = (pull(c, W, t) & ~FB) | FU;
+            const uint32_t lo = pull(c, W, t);
+            const uint32_t hi = pull(c, W, t);
+            npc = lo | (hi << 8);
+        }
+        else if constexpr (I.mn == BRK) {
+            const uint32_t ret = (c.pc + 2) & 0xFFFF;
+            push<0>(c, W, ret >> 8, t);
+            push<1>(c, W, ret & 0xFF, t);
+            push<2>(c, W, c.p | FB | FU, t);
+            c.p |= FI;
+            const uint32_t lo = rd(c, W, 0xFFFE, t);
+            const uint32_t hi = rd(c, W, 0xFFFF, t);
+            npc = lo | (hi << 8);
+        }
+        c.pc = npc;
+        c.cyc = t + 1;
+    }
+}
+
+// ------------------------------------------------------------ row log
+
+__device__ __forceinline__ void log_finalize(Cpu& c) {
+    if (c.open_row >= 0 && c.open_cnt) c.log[c.open_row * kRowBytes + 15] = (uint8_t)c.open_cnt;
+}
+
+// Take the snapshots of every row up to `target` (inclusive) from the
+// registers as they are now.
+__device__ __forceinline__ void log_advance(Cpu& c, const Wave& W, int32_t target) {
+    if (target > kRows - 1) target = kRows - 1;
+    while (c.open_row < target) {
+        log_finalize(c);
+        c.open_row++;
+        c.open_cnt = 0;
+        const uint32_t* s = reinterpret_cast<const uint32_t*>(W.tia + c.tia_off);
+        uint4 q = make_uint4(s[0], s[1], s[2], s[3] & 0x00FFFFFFu);
+        *reinterpret_cast<uint4*>(c.log + c.open_row * kRowBytes) = q;
+    }
+}
+
+__device__ __forceinline__ void log_entry(Cpu& c, int32_t row, uint32_t x, uint32_t code, uint32_t v0, uint32_t v1) {
+    if (row < 0 || row >= kRows) return;
+    if (c.open_cnt >= (uint32_t)kRowEntries) {
+        c.err |= ERR_LOG;
+        return;
+    }
+    *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * c.open_cnt) = x | (code << 8) | (v0 << 16) | (v1 << 24);
+    c.open_cnt++;
+}
+
+// A render-visible event with effect at colour clock 3(t+1): bring the
+// snapshots up to date; if it lands in a row's visible part, log it there.
+__device__ __forceinline__ void log_event(Cpu& c, const Wave& W, uint32_t t, uint32_t code, uint32_t v0,
+                                          uint32_t v1) {
+    const uint32_t ln = (t + 1) / 76;
+    const uint32_t h = 3 * (t + 1 - 76 * ln);
+    const int32_t row = (int32_t)ln - c.fl - kFirstRow;
+    log_advance(c, W, h >= 68 ? row : row - 1);
+    if (h >= 68) log_entry(c, row, h - 68, code, v0, v1);
+}
+
+// the frame ends with its last cycle at t: rows after it are outside
+__device__ __forceinline__ void log_close(Cpu& c, const Wave& W, uint32_t t) {
+    log_event(c, W, t, R_END, 0, 0);
+    log_finalize(c);
+    for (int32_t r = c.open_row + 1; r < kRows; ++r)
+        *reinterpret_cast<uint4*>(c.log + r * kRowBytes) = make_uint4(0, 0, 0, kRowOutside << 24);
+    c.log = nullptr;
+    c.slots |= 1u << c.slot;
+}
+
+// Apply one queued TIA write (reg | value << 8) made at cycle t.
+__device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t q, uint32_t t) {
+    const uint32_t reg = q & 0x3F, v = q >> 8;
+    uint8_t* R = W.tia + c.tia_off;
+    switch (reg) {
+    case 0x00:
+        if ((v & 2) && !(c.vsync & 2)) c.ev |= EV_VSYNC;
+        c.vsync = v;
+        return;
+    case 0x02: c.ev |= EV_WSYNC; return;
+    case 0x20: c.hmp0 = v; return;
+    case 0x21: c.hmp1 = v; return;
+    case 0x2B: c.hmp0 = 0; c.hmp1 = 0; return;
+    default: break;
+    }
+    uint32_t code, v0 = v, v1 = 0;
+    if (reg >= 0x06 && reg <= 0x0F) code = reg - 0x06;
+    else if (reg == 0x01) code = R_VBLANK;
+    else if (reg == 0x1B) code = R_GRP0;
+    else if (reg == 0x1C) code = R_GRP1;
+    else if (reg == 0x10 || reg == 0x11) {
+        const uint32_t h = 3 * ((t + 1) % 76);
+        code = reg == 0x10 ? R_P0X : R_P1X;
+        v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
+    } else if (reg == 0x2A) {
+        code = R_HMOVE;
+        const int32_t d0 = sext8(c.hmp0 & 0xF0) >> 4, d1 = sext8(c.hmp1 & 0xF0) >> 4;
+        v0 = (uint32_t)(((int32_t)R[R_P0X] - d0 + 160) % 160);
+        v1 = (uint32_t)(((int32_t)R[R_P1X] - d1 + 160) % 160);
+    } else {
+        return;   // audio, missiles, ball, NUSIZ, VDEL, ... are not rendered
+    }
+    if (c.log) log_event(c, W, t, code, v0, v1);
+    if (code == R_HMOVE) {
+        R[R_P0X] = (uint8_t)v0;
+        R[R_P1X] = (uint8_t)v1;
+    } else {
+        R[code] = (uint8_t)v0;
+    }
+}
+
+#define VCS_CASE1(n) case n: exec<n>(c, W, b1, b2); break;
+#define VCS_CASE4(n) VCS_CASE1(n) VCS_CASE1(n + 1) VCS_CASE1(n + 2) VCS_CASE1(n + 3)
+#define VCS_CASE16(n) VCS_CASE4(n) VCS_CASE4(n + 4) VCS_CASE4(n + 8) VCS_CASE4(n + 12)
+#define VCS_CASE64(n) VCS_CASE16(n) VCS_CASE16(n + 16) VCS_CASE16(n + 32) VCS_CASE16(n + 48)
+
+__device__ __forceinline__ void dispatch(uint32_t sop, Cpu& c, const Wave& W, uint32_t b1, uint32_t b2) {
+    switch (sop) {
+        VCS_CASE64(0) VCS_CASE64(64) VCS_CASE64(128) VCS_CASE64(192)
+    default: break;
+    }
+}
+
+__device__ __forceinline__ uint32_t bcd_value(uint32_t b) { return 10 * (b >> 4) + (b & 15); }
+
+__global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
+    __shared__ uint32_t s_rom[kRomSlot / 4 + 4];
+    __shared__ uint32_t s_ram[kLanes * kRamStride / 4];
+    __shared__ uint32_t s_tia[kLanes * kTiaStride / 4];
+
+    const uint32_t tile_id = blockIdx.x;
+    if (tile_id >= *A.n_tiles) return;
+    const Tile& T = A.tiles[tile_id];
+    const int lane = threadIdx.x;
+    const int rom_id = T.rom;
+
+    // stage the cartridge in LDS
+    const uint4* rsrc = reinterpret_cast<const uint4*>(A.roms + (size_t)rom_id * kRomSlot);
+    for (int i = lane; i < kRomSlot / 16; i += kLanes) reinterpret_cast<uint4*>(s_rom)[i] = rsrc[i];
+    if (lane < 4) s_rom[kRomSlot / 4 + lane] = 0;
+
+    Wave W;
+    W.rom = reinterpret_cast<uint8_t*>(s_rom);
+    W.ram = reinterpret_cast<uint8_t*>(s_ram);
+    W.tia = reinterpret_cast<uint8_t*>(s_tia);
+    W.f8 = A.schemes[rom_id];
+
+    const int env = lane < T.count ? T.env[lane] : -1;
+    const int out = lane < T.count ? T.out[lane] : 0;
+    bool active = env >= 0;
+
+    Cpu c;
+    c.ram_off = lane * kRamStride;
+    c.tia_off = lane * kTiaStride;
+    DevEnv* E = active ? &A.envs[env] : nullptr;
+    uint64_t base_line = 0;
+    uint32_t prev_action = 0, act = 0, step_idx = 0, score0 = 0, nfr = A.nframes;
+    uint64_t sticky_prefix = 0;
+    if (active) {
+        const uint4* src = reinterpret_cast<const uint4*>(E->ram);
+        for (int i = 0; i < 8; ++i) {
+            const uint4 q = src[i];
+            uint32_t* d = s_ram + (c.ram_off >> 2) + 4 * i;
+            d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+        }
+        const uint4 qt = reinterpret_cast<const uint4*>(E->tia)[0];
+        uint32_t* dt = s_tia + (c.tia_off >> 2);
+        dt[0] = qt.x; dt[1] = qt.y; dt[2] = qt.z; dt[3] = qt.w; dt[4] = 0;
+        c.a = E->a; c.x = E->x; c.y = E->y; c.sp = E->sp; c.p = E->p; c.bank = E->bank;
+        c.vsync = E->vsync; c.hmp0 = E->hmp0; c.hmp1 = E->hmp1;
+        c.tv = E->tv; c.tshift = E->tshift; c.tbase = E->tbase;
+        c.pc = E->pc;
+        const uint64_t cyc = E->cycle;
+        base_line = cyc / 76;
+        c.cyc = (uint32_t)(cyc - base_line * 76);
+        c.fl = (int32_t)((int64_t)E->frame_line0 - (int64_t)base_line);
+        prev_action = E->prev_action;
+        step_idx = E->step_idx;
+        c.err = E->err;
+        act = A.actions ? A.actions[out] : 0;
+        if (A.nframes_per_out) nfr = A.nframes_per_out[out];
+        sticky_prefix = rng_prefix(A.seed, (uint64_t)env, kStickyPurpose);
+    }
+    __syncthreads();
+    score0 = active ? W.ram[c.ram_off + 0x50] : 0;
+    c.base = base_line * 76;
+    c.icount = 0;
+    c.slots = 0;
+    c.slot = 0;
+    c.log = nullptr;
+    c.open_row = -1;
+    c.open_cnt = 0;
+    c.tqm = 0;
+    c.ev = 0;
+    uint32_t k = 0, done = 0;
+    uint32_t f = 0;
+
+    auto begin_frame = [&]() {
+        uint32_t eff = act;
+        if (A.sticky_thr) {
+            const uint64_t ctr = (uint64_t)step_idx * A.frameskip + f;
+            if ((uint32_t)(rng_draw(sticky_prefix, ctr) >> 32) < A.sticky_thr) eff = prev_action;
+        }
+        prev_action = eff;
+        c.swcha = (0xF0u & ~(uint32_t)kJoy[eff]) | 0x0Fu;
+        c.inpt4 = kFire[eff] ? 0x00u : 0x80u;
+        c.cap = 76u * (uint32_t)(320 + c.fl);
+        const int32_t slot = A.render_all ? (int32_t)f : (int32_t)f - ((int32_t)nfr - 2);
+        c.log = (A.log_enabled && slot >= 0 && slot < (int32_t)A.n_slots)
+                    ? A.logs + ((size_t)out * A.n_slots + slot) * kFrameLogBytes
+                    : nullptr;
+        c.slot = (uint32_t)slot;
+        c.open_row = -1;
+        c.open_cnt = 0;
+    };
+
+    if (active) {
+        if (act >= 18) {
+            c.err |= ERR_BAD_ACTION;
+            done = 1;
+            active = false;
+        } else if (nfr == 0) {
+            active = false;
+        } else {
+            begin_frame();
+        }
+    }
+
+    // ---------------------------------------------------------- main loop
+    while (__any(active)) {
+        uint32_t op = 0, b1 = 0, b2 = 0;
+        bool want = false, ended = false;
+        uint32_t end_t = 0;
+        if (active) {
+            if (c.cyc >= c.cap) {
+                c.err |= ERR_FRAME_CAP;
+                ended = true;
+                end_t = c.cyc - 1;
+            } else {
+                const uint32_t pc = c.pc;
+                const uint32_t off = pc & 0xFFF;
+                if ((pc & 0x1000) && off <= 0xFFD) {
+                    const uint32_t boff = (c.bank << 12) | off;
+                    const uint32_t w0 = s_rom[boff >> 2], w1 = s_rom[(boff >> 2) + 1];
+                    const uint32_t v = __builtin_amdgcn_alignbyte(w1, w0, boff & 3);
+                    op = v & 0xFF;
+                    b1 = (v >> 8) & 0xFF;
+                    b2 = (v >> 16) & 0xFF;
+                } else {
+                    op = peek(c, W, pc, c.cyc);
+                    b1 = peek(c, W, pc + 1, c.cyc);
+                    b2 = peek(c, W, pc + 2, c.cyc);
+                }
+                want = true;
+                c.ev = 0;
+                c.tqm = 0;
+            }
+        }
+        // one pass per distinct opcode among the lanes that fetched one
+        bool todo = want;
+        while (__any(todo)) {
+            if (todo) {
+                const uint32_t sop = __builtin_amdgcn_readfirstlane(op);
+                if (op == sop) {
+                    dispatch(sop, c, W, b1, b2);
+                    todo = false;
+                }
+            }
+        }
+        if (want) {
+            if (c.err & ERR_ILLEGAL) {
+                ended = true;
+                end_t = c.cyc - 1;
+            } else {
+                c.icount++;
+                const uint32_t t = c.ac;
+                if (c.tqm) {
+                    if (c.tqm & 1) tia_apply(c, W, c.tq0, t);
+                    if (c.tqm & 2) tia_apply(c, W, c.tq1, t);
+                    if (c.tqm & 4) tia_apply(c, W, c.tq2, t);
+                }
+                if (c.ev & EV_WSYNC) c.cyc = 76 * (t / 76 + 1);
+                if (c.ev & EV_VSYNC) {
+                    ended = true;
+                    end_t = t;
+                }
+            }
+        }
+        if (ended) {
+            if (c.log) log_close(c, W, end_t);
+            c.fl = (int32_t)(end_t / 76);
+            ++k;
+            ++f;
+            const bool term = A.early_stop && W.ram[c.ram_off + 0x51] != 0;
+            if (c.err || term) {
+                done = 1;
+                active = false;
+            } else if (f >= nfr) {
+                active = false;
+            } else {
+                begin_frame();
+            }
+        }
+    }
+
+    // ---------------------------------------------------------- write back
+    if (env >= 0) {
+        const uint32_t* sr = s_ram + (c.ram_off >> 2);
+        uint4* dst = reinterpret_cast<uint4*>(E->ram);
+        for (int i = 0; i < 8; ++i) dst[i] = make_uint4(sr[4 * i], sr[4 * i + 1], sr[4 * i + 2], sr[4 * i + 3]);
+        const uint32_t* st = s_tia + (c.tia_off >> 2);
+        reinterpret_cast<uint4*>(E->tia)[0] = make_uint4(st[0], st[1], st[2], st[3]);
+        E->a = c.a; E->x = c.x; E->y = c.y; E->sp = c.sp; E->p = c.p; E->bank = c.bank;
+        E->vsync = c.vsync; E->hmp0 = c.hmp0; E->hmp1 = c.hmp1;
+        E->tv = c.tv; E->tshift = c.tshift; E->tbase = c.tbase;
+        E->pc = c.pc;
+        E->cycle = c.base + c.cyc;
+        E->frame_line0 = (uint64_t)((int64_t)base_line + c.fl);
+        E->instr += c.icount;
+        E->prev_action = prev_action;
+        E->err = c.err;
+        E->step_idx = step_idx + 1;
+        StepInfo si;
+        si.k = (uint8_t)k;
+        si.done = (uint8_t)done;
+        si.err = (uint8_t)c.err;
+        si.slots = (uint8_t)c.slots;
+        A.info[out] = si;
+        if (A.done) A.done[out] = (uint8_t)done;
+        if (A.reward) {
+            const uint32_t s1 = W.ram[c.ram_off + 0x50];
+            A.reward[out] = (int32_t)bcd_value(s1) - (int32_t)bcd_value(score0);
+        }
+        if (c.err) {
+            atomicOr(&A.err_word[0], c.err);
+            atomicMin(&A.err_word[1], (uint32_t)env);
+        }
+        if (A.instr_total) atomicAdd(A.instr_total, (unsigned long long)c.icount);
+    }
+}
+
+void launch_interp(const InterpArgs& a, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_interp, dim3(grid), dim3(kLanes), 0, s, a);
+}
+
+}  // namespace vcs

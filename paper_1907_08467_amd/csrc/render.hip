@@ -1,0 +1,224 @@
+// TIA render and observation kernels.
+//
+// What they compute (paper, Section 3): the "TIA kernel" that turns the
+// logged register writes into the 160x210 frame, run only for frames that are
+// needed -- the observation is the pixelwise maximum of the last two frames
+// of the step.  Unlike the paper's one-thread-per-game TIA kernel, rows and
+// pixels are drawn in parallel (the paper names this as future work): each
+// thread draws a 16-pixel segment of one row from the row's snapshot and the
+// writes logged inside it.
+//
+// Pixel rule (TIA register semantics): VBLANK bit 1 or a pixel outside the
+// frame -> 0; playfield bit p of the 20-bit sequence PF0 D4..D7, PF1 D7..D0,
+// PF2 D0..D7 with p = x/4 on the left half and, on the right half,
+// (x-80)/4 or (reflect) 19-(x-80)/4; player i covers x = pos..pos+7 (mod 160)
+// with bit 7-d of GRPi (bit d when REFPi D3 is set); the playfield colour is
+// COLUPF, or in score mode COLUP0/COLUP1 by half; priority P0 > P1 > PF > BK,
+// or PF > P0 > P1 > BK with CTRLPF D2; the stored value is the colour & $FE.
+//
+// Observation: gray = lut[colour >> 1]; m = max over the two frames;
+// obs[i][j] = floor((sum_r sum_c wr*wc*m[r][c] + 100) / 200), the exact-area
+// average of 210x160 -> 84x84 with row weights in half rows (2,2,1 / 1,2,2)
+// and column weights |[40j, 40j+40) & [21c, 21c+21)|, rounded half up.
+#include "vcs_device.h"
+
+namespace vcs {
+
+
+
+struct Regs {
+    uint32_t colup0, colup1, colupf, colubk, ctrlpf, refp0, refp1, pf0, pf1, pf2, grp0, grp1, p0x, p1x, vblank;
+    uint32_t pfm;             // playfield bits 0..19
+    bool outside;
+};
+
+__device__ __forceinline__ uint32_t pf_mask(uint32_t pf0, uint32_t pf1, uint32_t pf2) {
+    return ((pf0 >> 4) & 0xF) | ((__builtin_bitreverse32(pf1) >> 24) << 4) | ((pf2 & 0xFF) << 12);
+}
+
+__device__ __forceinline__ void unpack(Regs& r, uint4 s) {
+    r.colup0 = s.x & 0xFF; r.colup1 = (s.x >> 8) & 0xFF; r.colupf = (s.x >> 16) & 0xFF; r.colubk = s.x >> 24;
+    r.ctrlpf = s.y & 0xFF; r.refp0 = (s.y >> 8) & 0xFF; r.refp1 = (s.y >> 16) & 0xFF; r.pf0 = s.y >> 24;
+    r.pf1 = s.z & 0xFF; r.pf2 = (s.z >> 8) & 0xFF; r.grp0 = (s.z >> 16) & 0xFF; r.grp1 = s.z >> 24;
+    r.p0x = s.w & 0xFF; r.p1x = (s.w >> 8) & 0xFF; r.vblank = (s.w >> 16) & 0xFF;
+    r.outside = ((s.w >> 24) & kRowOutside) != 0;
+    r.pfm = pf_mask(r.pf0, r.pf1, r.pf2);
+}
+
+__device__ __forceinline__ void apply(Regs& r, uint32_t e) {
+    const uint32_t code = (e >> 8) & 0xFF, v0 = (e >> 16) & 0xFF, v1 = e >> 24;
+    switch (code) {
+    case R_COLUP0: r.colup0 = v0; break;
+    case R_COLUP1: r.colup1 = v0; break;
+    case R_COLUPF: r.colupf = v0; break;
+    case R_COLUBK: r.colubk = v0; break;
+    case R_CTRLPF: r.ctrlpf = v0; break;
+    case R_REFP0: r.refp0 = v0; break;
+    case R_REFP1: r.refp1 = v0; break;
+    case R_PF0: r.pf0 = v0; r.pfm = pf_mask(r.pf0, r.pf1, r.pf2); break;
+    case R_PF1: r.pf1 = v0; r.pfm = pf_mask(r.pf0, r.pf1, r.pf2); break;
+    case R_PF2: r.pf2 = v0; r.pfm = pf_mask(r.pf0, r.pf1, r.pf2); break;
+    case R_GRP0: r.grp0 = v0; break;
+    case R_GRP1: r.grp1 = v0; break;
+    case R_P0X: r.p0x = v0; break;
+    case R_P1X: r.p1x = v0; break;
+    case R_VBLANK: r.vblank = v0; break;
+    case R_HMOVE: r.p0x = v0; r.p1x = v1; break;
+    default: r.outside = true; break;   // R_END
+    }
+}
+
+__device__ __forceinline__ uint32_t player_bit(uint32_t pos, uint32_t grp, uint32_t refp, uint32_t x) {
+    int32_t d = (int32_t)x - (int32_t)pos;
+    if (d < 0) d += 160;
+    if (d >= 8) return 0;
+    const uint32_t bit = (refp & 8) ? (uint32_t)d : 7u - (uint32_t)d;
+    return (grp >> bit) & 1;
+}
+
+__device__ __forceinline__ uint32_t pixel(const Regs& r, uint32_t x) {
+    if (r.outside || (r.vblank & 2)) return 0;
+    const uint32_t right = x >= 80;
+    const uint32_t q = right ? ((r.ctrlpf & 1) ? 19 - ((x - 80) >> 2) : (x - 80) >> 2) : (x >> 2);
+    const uint32_t pf = (r.pfm >> q) & 1;
+    const uint32_t p0 = player_bit(r.p0x, r.grp0, r.refp0, x);
+    const uint32_t p1 = player_bit(r.p1x, r.grp1, r.refp1, x);
+    const uint32_t pfc = (r.ctrlpf & 2) ? (right ? r.colup1 : r.colup0) : r.colupf;
+    uint32_t c;
+    if (r.ctrlpf & 4) c = pf ? pfc : (p0 ? r.colup0 : (p1 ? r.colup1 : r.colubk));
+    else c = p0 ? r.colup0 : (p1 ? r.colup1 : (pf ? pfc : r.colubk));
+    return c & 0xFE;
+}
+
+// 16 pixels of row `row` starting at x0, packed little-endian into a uint4
+__device__ __forceinline__ uint4 render_segment(const uint8_t* frame_log, int row, uint32_t x0) {
+    const uint8_t* rec = frame_log + row * kRowBytes;
+    const uint4 s = *reinterpret_cast<const uint4*>(rec);
+    Regs r;
+    unpack(r, s);
+    const uint32_t cnt = (s.w >> 24) & 0x1F;
+    const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + 16);
+    uint32_t ei = 0;
+    uint32_t w[4] = {0, 0, 0, 0};
+    if (r.outside && cnt == 0) return make_uint4(0, 0, 0, 0);
+    uint32_t e = cnt ? ents[0] : 0;
+    // entries before the segment
+    while (ei < cnt && (e & 0xFF) <= x0) {
+        apply(r, e);
+        ++ei;
+        e = ei < cnt ? ents[ei] : 0;
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i) {
+        const uint32_t x = x0 + i;
+        while (ei < cnt && (e & 0xFF) <= x) {
+            apply(r, e);
+            ++ei;
+            e = ei < cnt ? ents[ei] : 0;
+        }
+        w[i >> 2] |= pixel(r, x) << (8 * (i & 3));
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// bytewise maximum of two packed 4 x u8 words
+__device__ __forceinline__ uint32_t max4u8(uint32_t a, uint32_t b) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t x = (a >> (8 * k)) & 0xFF, y = (b >> (8 * k)) & 0xFF;
+        r |= (x > y ? x : y) << (8 * k);
+    }
+    return r;
+}
+
+constexpr int kSegs = kCols / 16;            // 10 segments per row
+constexpr int kFrameSegs = kRows * kSegs;    // 2100
+
+// Frames that only go to the frames output (render mode ALL, slots before the
+// last two).  grid = (n, n_slots - 2), block 256.
+__global__ void __launch_bounds__(256) k_render_frames(RenderArgs A) {
+    const uint32_t i = blockIdx.x;
+    const int slot = blockIdx.y;
+    const StepInfo si = A.info[i];
+    const bool valid = (si.slots >> slot) & 1;
+    const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
+    uint8_t* dst = A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes;
+    for (int sidx = threadIdx.x; sidx < kFrameSegs; sidx += blockDim.x) {
+        const int row = sidx / kSegs, seg = sidx - row * kSegs;
+        const uint4 q = valid ? render_segment(lg, row, seg * 16) : make_uint4(0, 0, 0, 0);
+        *reinterpret_cast<uint4*>(dst + row * kCols + seg * 16) = q;
+    }
+}
+
+// The last two frame slots: frames output (optional) and the observation.
+// grid = n, block 256.
+__global__ void __launch_bounds__(256) k_render_obs(RenderArgs A) {
+    __shared__ uint32_t s_m[kFrameBytes / 4];   // max gray of the two frames
+    __shared__ uint8_t s_lut[128];
+    const uint32_t i = blockIdx.x;
+    const StepInfo si = A.info[i];
+    const bool bad = (si.err & ERR_BAD_ID) != 0;
+    const bool want_obs = A.obs && !bad && (A.force_obs || !si.done);
+    if (threadIdx.x < 128) s_lut[threadIdx.x] = A.gray[threadIdx.x];
+    uint8_t* m = reinterpret_cast<uint8_t*>(s_m);
+    __syncthreads();
+    const int s0 = (int)A.n_slots - 2;
+    bool first = true;
+    for (int slot = s0 < 0 ? 0 : s0; slot < (int)A.n_slots; ++slot) {
+        const bool valid = !bad && ((si.slots >> slot) & 1);
+        const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
+        uint8_t* dst = A.frames ? A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes : nullptr;
+        if (!valid && !dst) continue;
+        for (int sidx = threadIdx.x; sidx < kFrameSegs; sidx += blockDim.x) {
+            const int row = sidx / kSegs, seg = sidx - row * kSegs;
+            const uint4 q = valid ? render_segment(lg, row, seg * 16) : make_uint4(0, 0, 0, 0);
+            if (dst) *reinterpret_cast<uint4*>(dst + row * kCols + seg * 16) = q;
+            if (want_obs && valid) {
+                const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+                uint32_t* mrow = s_m + (row * kCols + seg * 16) / 4;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t g = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) g |= (uint32_t)s_lut[((wv[j] >> (8 * b)) & 0xFF) >> 1] << (8 * b);
+                    mrow[j] = first ? g : max4u8(mrow[j], g);
+                }
+            }
+        }
+        if (want_obs && valid) first = false;
+        __syncthreads();
+    }
+    if (!A.obs) return;
+    if (bad || (want_obs && first)) {     // no frame to show
+        for (int o = threadIdx.x; o < kObsBytes; o += blockDim.x) A.obs[(size_t)i * kObsBytes + o] = 0;
+        return;
+    }
+    if (!want_obs) return;                // the reset kernel writes the cache observation
+    // exact-area 210x160 -> 84x84
+    for (int o = threadIdx.x; o < kObsBytes; o += blockDim.x) {
+        const int oi = o / kObs, oj = o - oi * kObs;
+        const int mrow = oi >> 1;
+        const int r0 = (oi & 1) ? 5 * mrow + 2 : 5 * mrow;
+        const uint32_t wr0 = (oi & 1) ? 1 : 2, wr1 = 2, wr2 = (oi & 1) ? 2 : 1;
+        const int c0 = (40 * oj) / 21, c1 = (40 * oj + 39) / 21;
+        uint32_t sum = 0;
+        for (int cc = c0; cc <= c1; ++cc) {
+            const int lo = max(40 * oj, 21 * cc), hi = min(40 * oj + 40, 21 * cc + 21);
+            const uint32_t wc = (uint32_t)(hi - lo);
+            const uint32_t col = wr0 * m[r0 * kCols + cc] + wr1 * m[(r0 + 1) * kCols + cc] +
+                                 wr2 * m[(r0 + 2) * kCols + cc];
+            sum += wc * col;
+        }
+        A.obs[(size_t)i * kObsBytes + o] = (uint8_t)((sum + 100) / 200);
+    }
+}
+
+void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, hipStream_t s) {
+    hipLaunchKernelGGL(k_render_frames, dim3(a.n, n_front_slots), dim3(256), 0, s, a);
+}
+void launch_render_obs(const RenderArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_render_obs, dim3(a.n), dim3(256), 0, s, a);
+}
+
+}  // namespace vcs

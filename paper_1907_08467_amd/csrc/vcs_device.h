@@ -1,0 +1,148 @@
+// Device-side layouts shared by the vcs355 kernels and the host library.
+//
+// Env state lives in HBM as one 256-byte record per env (DevEnv).  A step
+// loads a tile of 64 envs into one wave: RAM into LDS, CPU registers into
+// VGPRs.  The interpreter writes, for each frame it renders, a row log: per
+// scanline row a 16-byte snapshot of the render registers at the row's first
+// visible pixel plus the register writes that land inside the row, so the
+// render kernel can draw every row and pixel independently.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vcs {
+
+constexpr int kLanes = 64;             // envs per tile = one wave64
+constexpr int kRows = 210;             // frame rows
+constexpr int kCols = 160;             // frame columns
+constexpr int kFirstRow = 34;          // frame row 0 = scanline 34 of the frame
+constexpr int kObs = 84;
+constexpr int kObsBytes = kObs * kObs;
+constexpr int kFrameBytes = kRows * kCols;
+constexpr int kRowEntries = 24;        // max register writes inside one row's visible part
+constexpr int kRowBytes = 16 + 4 * kRowEntries;   // snapshot + entries = 112
+constexpr int kFrameLogBytes = kRows * kRowBytes; // 23,520
+constexpr int kRomSlot = 8192;         // bytes per ROM slot (4 KB ROMs use the first half)
+
+// render register order inside a snapshot (TIA $06..$0F map to 0..9)
+enum : int {
+    R_COLUP0 = 0, R_COLUP1, R_COLUPF, R_COLUBK, R_CTRLPF, R_REFP0, R_REFP1, R_PF0, R_PF1, R_PF2,
+    R_GRP0 = 10, R_GRP1 = 11, R_P0X = 12, R_P1X = 13, R_VBLANK = 14, R_HMOVE = 15, R_END = 16
+};
+// snapshot byte 15: number of entries in the row, bit 7 = row outside the frame
+constexpr uint32_t kRowOutside = 0x80;
+
+// error bits (same values as the C header)
+constexpr uint32_t ERR_ILLEGAL = 1, ERR_FRAME_CAP = 2, ERR_BAD_ACTION = 4, ERR_BAD_ID = 8, ERR_LOG = 16;
+
+struct alignas(16) DevEnv {
+    uint8_t ram[128];        //   0  RAM $80..$FF
+    uint8_t tia[16];         // 128  render registers (snapshot order); [15] = 0
+    uint8_t a, x, y, sp;     // 144
+    uint8_t p, bank, vsync, hmp0;              // 148
+    uint8_t hmp1, tv, tshift, prev_action;     // 152  timer value / log2 interval
+    uint8_t err, pad0;                         // 156
+    uint16_t pc;                               // 158
+    uint64_t cycle;          // 160  start cycle of the next instruction
+    uint64_t frame_line0;    // 168  scanline of the write that began the frame
+    int64_t tbase;           // 176  first cycle at which the last timer write is visible
+    uint64_t instr;          // 184  instructions executed
+    uint32_t rom_id, step_idx, episode_idx, pad1;   // 192
+    uint8_t reserved[48];    // 208
+};
+static_assert(sizeof(DevEnv) == 256, "DevEnv is 256 bytes");
+
+struct Tile {                 // 64 lanes of one ROM
+    int32_t rom;
+    int32_t count;
+    int32_t env[kLanes];      // env id per lane (-1 = idle lane)
+    int32_t out[kLanes];      // output position per lane
+};
+
+struct StepInfo {             // per output position
+    uint8_t k;                // frames emulated this step
+    uint8_t done;
+    uint8_t err;
+    uint8_t slots;            // bit s: row-log slot s holds a complete frame
+};
+
+struct InterpArgs {
+    const Tile* tiles;
+    const uint32_t* n_tiles;  // device count of valid tiles (grid may be larger)
+    DevEnv* envs;
+    const uint8_t* roms;      // [n_roms][kRomSlot]
+    const uint32_t* schemes;  // [n_roms]
+    const uint8_t* actions;   // [n outputs]; NULL = NOOP
+    const uint16_t* nframes_per_out;  // [n outputs] or NULL
+    uint32_t nframes;         // frames per step when nframes_per_out is NULL
+    uint32_t render_all;      // 1: log every frame (slot = f); 0: the last two (slot = f - (nfr - 2))
+    uint32_t log_enabled;
+    uint32_t early_stop;      // stop after the frame in which RAM[$D1] != 0
+    uint32_t sticky_thr;
+    uint32_t frameskip;       // for the sticky counter
+    uint64_t seed;
+    uint8_t* logs;            // [n outputs][n_slots][kFrameLogBytes]
+    uint32_t n_slots;
+    StepInfo* info;
+    int32_t* reward;          // [n outputs] or NULL
+    uint8_t* done;            // [n outputs] or NULL
+    uint32_t* err_word;       // [0] bits, [1] smallest env id with an error
+    unsigned long long* instr_total;
+};
+
+// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014)
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+// counter-based draw R(seed, id, purpose, n), split into a per-(env, purpose)
+// prefix and the counter step
+__host__ __device__ inline uint64_t rng_prefix(uint64_t seed, uint64_t id, uint64_t purpose) {
+    return mix64(mix64(mix64(seed + kGamma) ^ id) ^ (purpose << 48));
+}
+__host__ __device__ inline uint64_t rng_draw(uint64_t prefix, uint64_t n) { return mix64(prefix ^ n); }
+constexpr uint64_t kStickyPurpose = 1, kResetPurpose = 2, kNoopPurpose = 3;
+
+struct RenderArgs {
+    const uint8_t* logs;      // [n][n_slots][kFrameLogBytes]
+    uint32_t n_slots;
+    const StepInfo* info;     // [n]
+    uint8_t* frames;          // [n][n_slots][210][160] or NULL
+    uint8_t* obs;             // [n][84][84] or NULL
+    const uint8_t* gray;      // [128]
+    uint32_t n;
+    uint32_t force_obs;       // also for envs that ended (cache build)
+};
+
+struct ResetArgs {
+    DevEnv* envs;
+    const int32_t* ids;          // NULL = position i is env i
+    uint32_t n;
+    uint32_t num_envs;
+    const StepInfo* info;        // NULL: reset every listed env; else only done ones
+    const uint8_t* valid;        // NULL or per-position validity
+    const DevEnv* cache_state;   // [n_roms][K]
+    const uint8_t* cache_obs;    // [n_roms][K][84*84]
+    uint32_t K;
+    uint64_t seed;
+    uint8_t* obs;                // [n][84][84] or NULL
+};
+
+// host launchers (one per kernel)
+void launch_interp(const InterpArgs& a, uint32_t grid, hipStream_t s);
+void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, hipStream_t s);
+void launch_render_obs(const RenderArgs& a, hipStream_t s);
+void launch_reset(const ResetArgs& a, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+void launch_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, const uint16_t* env_rom,
+                     uint32_t* claim, uint32_t tag, uint32_t* counts, uint8_t* valid, StepInfo* info,
+                     int32_t* reward, uint8_t* done, uint32_t* err_word, hipStream_t s);
+void launch_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t* offsets, uint32_t* fill,
+                        Tile* tiles, uint32_t* n_tiles, hipStream_t s);
+void launch_tile_fill(const int32_t* ids, uint32_t n, const uint16_t* env_rom, const uint8_t* valid,
+                      const uint32_t* offsets, uint32_t* fill, Tile* tiles, hipStream_t s);
+
+}  // namespace vcs

@@ -1,0 +1,115 @@
+"""Batched Atari 2600 envs on one GPU: a thin torch-facing wrapper of the C ABI.
+
+Device memory comes from torch tensors and work is enqueued on torch's
+current stream; every computation happens in the HIP library.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class VcsEnv:
+    """`num_envs` consoles, each running one of `roms` ([(bytes, scheme)])."""
+
+    def __init__(self, roms, env_rom, gray_lut, frameskip=4, sticky_threshold=0, reset_cache_k=30,
+                 noop_max=30, startup_frames=64, seed=0, render_mode=B.VCS_RENDER_ALL, max_batch=0,
+                 hbm_budget_bytes=0, device=0):
+        env_rom = np.ascontiguousarray(env_rom, dtype=np.uint16)
+        cfg = B.VcsConfig()
+        cfg.num_envs = int(env_rom.shape[0])
+        cfg.frameskip = frameskip
+        cfg.sticky_threshold = sticky_threshold
+        cfg.reset_cache_k = reset_cache_k
+        cfg.noop_max = noop_max
+        cfg.startup_frames = startup_frames
+        cfg.seed = seed
+        cfg.render_mode = render_mode
+        cfg.max_batch = max_batch
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        cfg.device = device
+        for i, g in enumerate(bytes(gray_lut)):
+            cfg.gray_lut[i] = g
+        self.num_envs = cfg.num_envs
+        self.frameskip = frameskip
+        self.render_mode = render_mode
+        self.max_batch = max_batch or cfg.num_envs
+        self.device = torch.device("cuda", device)
+        self._h = B.vcs_create(cfg)
+        B.vcs_load_roms(self._h, [r for r, _ in roms], [s for _, s in roms])
+        B.vcs_assign(self._h, env_rom)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            B.vcs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_slots(self):
+        return self.frameskip if self.render_mode == B.VCS_RENDER_ALL else 2
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _ids(self, env_ids):
+        if env_ids is None:
+            return None, None
+        ids = torch.as_tensor(env_ids, dtype=torch.int32, device=self.device).contiguous()
+        return ids, ids.data_ptr()
+
+    def reset(self, env_ids=None, n=None, obs=None):
+        ids, ids_ptr = self._ids(env_ids)
+        n = ids.numel() if ids is not None else (self.num_envs if n is None else n)
+        if obs is None:
+            obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=self.device)
+        B.vcs_reset(self._h, ids_ptr, n, obs.data_ptr(), self._stream())
+        return obs
+
+    def step(self, actions, env_ids=None, want_frames=False, want_obs=True, out=None):
+        """actions: uint8 cuda tensor [n].  Returns (obs, reward, done, frames)."""
+        actions = torch.as_tensor(actions, dtype=torch.uint8, device=self.device).contiguous()
+        n = actions.numel()
+        ids, ids_ptr = self._ids(env_ids)
+        if out is None:
+            obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=self.device) if want_obs else None
+            reward = torch.empty(n, dtype=torch.int32, device=self.device)
+            done = torch.empty(n, dtype=torch.uint8, device=self.device)
+            frames = (torch.empty((n, self.n_slots, 210, 160), dtype=torch.uint8, device=self.device)
+                      if want_frames else None)
+        else:
+            obs, reward, done, frames = out
+        B.vcs_step(self._h, ids_ptr, actions.data_ptr(), n, obs.data_ptr() if obs is not None else None,
+                   reward.data_ptr(), done.data_ptr(), frames.data_ptr() if frames is not None else None,
+                   self._stream())
+        return obs, reward, done, frames
+
+    def get_state(self, env):
+        return np.frombuffer(B.vcs_get_state(self._h, env), dtype=np.uint8).copy()
+
+    def set_state(self, env, rec):
+        B.vcs_set_state(self._h, env, bytes(np.asarray(rec, dtype=np.uint8)))
+
+    def get_cache(self, rom, k):
+        st, ob = B.vcs_get_cache(self._h, rom, k)
+        return np.frombuffer(st, np.uint8).copy(), np.frombuffer(ob, np.uint8).reshape(84, 84).copy()
+
+    def poll_errors(self):
+        return B.vcs_poll_errors(self._h)
+
+    def last_step_instructions(self):
+        return B.vcs_last_step_instructions(self._h)
+
+    def timing(self, enable):
+        B.vcs_timing(self._h, enable)
+
+    def kernel_time(self, which):
+        return B.vcs_kernel_time(self._h, which)

@@ -80,7 +80,7 @@ def _gen_shape(rng, divergent: bool, f8: bool):
     """Item kinds of a band body.  The shape is shared by both F8 banks so that
     every instruction sits at the same offset in both; operands differ."""
     if divergent:
-        n_ops = int(rng.integers(2, 6))
+        n_ops = int(rng.integers(2, 5))
         n_st = 5
     else:
         n_ops = int(rng.integers(3, 9))
@@ -95,7 +95,7 @@ def _gen_shape(rng, divergent: bool, f8: bool):
     shape = dict(items=items)
     if divergent:
         shape["thr"] = int(np.floor(rng.uniform(0.1, 0.9) * 256))
-        shape["path_a"] = int(rng.integers(1, 4))
+        shape["path_a"] = int(rng.integers(1, 3))
         shape["path_b"] = int(rng.integers(1, 3))
         shape["swap"] = f8 and bool(rng.integers(0, 2))
         shape["where"] = int(rng.integers(0, len(items) + 1))
@@ -139,7 +139,8 @@ def _fill_body(rng, shape, label: str, bank: int) -> _Body:
     b.lines += [f"    lda ${LFSR:02X}", "    lsr", f"    bcc {label}_nf",
                 "    eor #$B8", f"{label}_nf:", f"    sta ${LFSR:02X}",
                 f"    cmp #${shape['thr']:02X}", f"    bcc {label}_b"]
-    b.cycles += 3 + 2 + 3 + 2 + 3 + 2 + 4
+    # lda 3, lsr 2, max(bcc taken across a page 4, not taken 2 + eor 2), sta 3, cmp 2, bcc 4
+    b.cycles += 3 + 2 + 4 + 3 + 2 + 4
     ca = 0
     for _ in range(shape["path_a"]):
         b.lines.append(op_line())

@@ -256,3 +256,20 @@ def test_preprocess_constant_and_max():
     b = r.integers(0, 256, (210, 160)).astype(np.uint8)
     assert np.array_equal(oracle.preprocess(a, a, GRAY), oracle.preprocess(None, a, GRAY))
     assert np.array_equal(oracle.preprocess(a, b, GRAY), oracle.preprocess(b, a, GRAY))
+
+
+def test_all_workload_cartridges_keep_ntsc_frames():
+    """Every cartridge of the five workloads: 262-line frames, no faults."""
+    from paper_1907_08467_amd.inputs.workloads import config
+    seen = set()
+    for c in (1, 2, 3, 4):
+        for spec in config(c).rom_specs:
+            if spec.seed in seen:
+                continue
+            seen.add(spec.seed)
+            rom = generate(spec)
+            st = oracle.power_on(rom.data, rom.scheme)
+            acts = np.random.default_rng(spec.seed).integers(0, 18, 12).astype(np.uint8)
+            st, _, ends, got = oracle.run_frames(st, rom.data, 12, rom.scheme, actions=acts, render=False)
+            assert got == 12 and decode(st)["err"] == 0
+            assert (np.diff(ends.astype(np.int64))[1:] == 19912).all(), spec

@@ -541,9 +541,9 @@ int vcs_step(vcs_ctx* c, const int32_t* ids, const uint8_t* actions, uint32_t n,
              uint8_t* done, uint8_t* frames, void* stream) {
     if (!c) return fail(VCS_E_INVAL, "null context");
     if (!c->assigned) return fail(VCS_E_STATE, "vcs_assign first");
-    if (!actions || !reward || !done) return fail(VCS_E_INVAL, "actions, reward and done are required");
     if (n > c->max_batch) return fail(VCS_E_INVAL, "n exceeds max_batch");
     if (n == 0) return VCS_OK;
+    if (!actions || !reward || !done) return fail(VCS_E_INVAL, "actions, reward and done are required");
     hipStream_t s = (hipStream_t)stream;
     const Tile* tiles = c->d_tiles_all;
     const uint32_t* n_tiles = c->d_n_tiles_all;

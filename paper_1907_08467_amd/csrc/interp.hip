@@ -569,6 +569,24 @@ __device__ __forceinline__ void dispatch(uint32_t sop, Cpu& c, const Wave& W, ui
 
 __device__ __forceinline__ uint32_t bcd_value(uint32_t b) { return 10 * (b >> 4) + (b & 15); }
 
+// Minimum of v over the 64 lanes (call with every lane active): DPP swaps
+// within quads, 8- and 16-lane mirrors, then row broadcasts; lane 63 ends up
+// with the minimum.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Lanes whose next instruction starts within this many cycles of the wave's
+// earliest lane run together; the others wait.  Lanes of one ROM then meet
+// again at every WSYNC line start and share one dispatch pass per instruction.
+constexpr uint32_t kSchedWindow = 6;
+
 __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
     __shared__ uint32_t s_rom[kRomSlot / 4 + 4];
     __shared__ uint32_t s_ram[kLanes * kRamStride / 4];
@@ -677,7 +695,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
         uint32_t op = 0, b1 = 0, b2 = 0;
         bool want = false, ended = false;
         uint32_t end_t = 0;
-        if (active) {
+        const uint32_t tmin = wave_min(active ? c.cyc : 0xFFFFFFFFu);
+        const bool go = active && c.cyc <= tmin + kSchedWindow;
+        if (go) {
             if (c.cyc >= c.cap) {
                 c.err |= ERR_FRAME_CAP;
                 ended = true;

@@ -36,7 +36,19 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     return p.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    a = torch.ones(mib << 18, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": mib << 20, "bytes_written": mib << 20}))
 
 
 def cpu_baseline(w, roms, env_rom, steps):
@@ -59,6 +71,9 @@ def cpu_baseline(w, roms, env_rom, steps):
 
 def main():
     args = parse()
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the envs are independent and "
               "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)

@@ -25,10 +25,11 @@
 //
 // Dispatch: each loop iteration every running lane fetches its next opcode;
 // the wave then executes one opcode at a time for all lanes that share it
-// (readfirstlane + compare), so the opcode is a scalar and the handler is a
-// branch-free specialisation picked by a scalar jump table.  In lockstep (the
-// common case for envs of one ROM) that is a single pass.  TIA writes are
-// queued during the handler and applied in one shared block afterwards.
+// (readfirstlane + compare), so the opcode's decode word is a scalar and the
+// addressing-mode and operation switches of the one generic executor are
+// scalar branches.  In lockstep (the common case for envs of one ROM) that is
+// a single pass.  TIA writes are queued during the pass and applied in one
+// shared block afterwards.
 #include "vcs_device.h"
 
 namespace vcs {
@@ -137,11 +138,16 @@ constexpr uint32_t FC = 0x01, FZ = 0x02, FI = 0x04, FD = 0x08, FB = 0x10, FU = 0
 // per-instruction events
 constexpr uint32_t EV_WSYNC = 1, EV_VSYNC = 2;
 
-// SWCHA high nibble (active low: D7 right, D6 left, D5 down, D4 up) and
-// fire, for the 18 actions in ALE order.
-__constant__ uint8_t kJoy[18] = {0x00, 0x00, 0x10, 0x80, 0x40, 0x20, 0x90, 0x50, 0xA0, 0x60,
-                                 0x10, 0x80, 0x40, 0x20, 0x90, 0x50, 0xA0, 0x60};
-__constant__ uint8_t kFire[18] = {0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1};
+// Joystick of the 18 actions (ALE order): actions 2..9 and 10..17 are the
+// directions UP, RIGHT, LEFT, DOWN, UPRIGHT, UPLEFT, DOWNRIGHT, DOWNLEFT;
+// their pressed bits in SWCHA's high nibble (D7 right, D6 left, D5 down,
+// D4 up) are packed one byte per direction; 1 and 10..17 hold fire.
+constexpr uint64_t kDirBits = 0x60A0509020408010ull;
+__device__ __forceinline__ uint32_t joy_pressed(uint32_t a) {
+    const uint32_t dir = a >= 10 ? a - 8 : a;
+    return dir >= 2 ? (uint32_t)(kDirBits >> (8 * (dir - 2))) & 0xF0u : 0u;
+}
+__device__ __forceinline__ bool fire_pressed(uint32_t a) { return a == 1 || a >= 10; }
 
 struct Wave {                 // per-workgroup (uniform) data
     uint8_t* rom;             // LDS copy of the tile's cartridge
@@ -242,9 +248,8 @@ __device__ __forceinline__ void wr(Cpu& c, const Wave& W, uint32_t addr, uint32_
     } else if (!(a & 0x200)) {
         W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
     } else if ((a & 0x14) == 0x14) {     // TIM1T / TIM8T / TIM64T / T1024T
-        const uint32_t sh[4] = {0, 3, 6, 10};
         c.tv = v & 0xFF;
-        c.tshift = sh[a & 3];
+        c.tshift = (0x0A060300u >> (8 * (a & 3))) & 0xFF;   // intervals 1, 8, 64, 1024
         c.tbase = (int64_t)(c.base + t) + 1;
     }
 }
@@ -305,162 +310,184 @@ __device__ __forceinline__ void do_cmp(Cpu& c, uint32_t r, uint32_t v) {
     c.p = nz(c.p, (r - v) & 0xFF);
 }
 
-template <int MN>
-__device__ __forceinline__ uint32_t rmw_op(Cpu& c, uint32_t v) {
-    uint32_t r;
-    if constexpr (MN == ASL) { c.p = (c.p & ~FC) | (v >> 7); r = (v << 1) & 0xFF; }
-    else if constexpr (MN == LSR) { c.p = (c.p & ~FC) | (v & 1); r = v >> 1; }
-    else if constexpr (MN == ROL) { const uint32_t ci = c.p & FC; c.p = (c.p & ~FC) | (v >> 7); r = ((v << 1) | ci) & 0xFF; }
-    else if constexpr (MN == ROR) { const uint32_t ci = c.p & FC; c.p = (c.p & ~FC) | (v & 1); r = (v >> 1) | (ci << 7); }
-    else if constexpr (MN == INC) { r = (v + 1) & 0xFF; }
-    else { r = (v - 1) & 0xFF; }
-    c.p = nz(c.p, r);
-    return r;
+// Decode word of an opcode: mode | mnemonic << 4 | base cycles << 10 |
+// page penalty << 13 | length << 14 | reads operand << 16 | writes to ea << 17.
+constexpr uint32_t encode(int op) {
+    const OpInfo I = decode(op);
+    const bool rmw = I.mn == ASL || I.mn == LSR || I.mn == ROL || I.mn == ROR || I.mn == INC || I.mn == DEC;
+    const bool mem = I.md != IMP && I.md != ACC && I.md != REL && I.md != IMM;
+    const bool reads = (I.mn == LDA || I.mn == LDX || I.mn == LDY || I.mn == ADC || I.mn == SBC || I.mn == AND ||
+                        I.mn == ORA || I.mn == EOR || I.mn == CMP || I.mn == CPX || I.mn == CPY || I.mn == BIT ||
+                        rmw) && mem;
+    const bool writes = (I.mn == STA || I.mn == STX || I.mn == STY || rmw) && mem;
+    return (uint32_t)I.md | ((uint32_t)I.mn << 4) | ((uint32_t)I.cyc << 10) | ((uint32_t)I.pen << 13) |
+           ((uint32_t)op_len(I.md) << 14) | ((uint32_t)reads << 16) | ((uint32_t)writes << 17);
 }
+struct DecodeTable {
+    uint32_t w[256];
+    constexpr DecodeTable() : w() {
+        for (int i = 0; i < 256; ++i) w[i] = encode(i);
+    }
+};
+__constant__ DecodeTable kDecode = DecodeTable();
 
-template <int MN>
-__device__ __forceinline__ bool branch_cond(uint32_t p) {
-    if constexpr (MN == BPL) return !(p & FN);
-    else if constexpr (MN == BMI) return (p & FN) != 0;
-    else if constexpr (MN == BVC) return !(p & FV);
-    else if constexpr (MN == BVS) return (p & FV) != 0;
-    else if constexpr (MN == BCC) return !(p & FC);
-    else if constexpr (MN == BCS) return (p & FC) != 0;
-    else if constexpr (MN == BNE) return !(p & FZ);
-    else return (p & FZ) != 0;
-}
-
-// Execute opcode OP for the lanes that fetched it.  Sets c.ac, c.pc, c.cyc
-// (before any WSYNC stall) and queues TIA writes.
-template <int OP>
-__device__ __forceinline__ void exec(Cpu& c, const Wave& W, uint32_t b1, uint32_t b2) {
-    constexpr OpInfo I = decode(OP);
-    if constexpr (I.mn == ILL) {
+// Execute one instruction with decode word `d` (wave-uniform) for the lanes
+// that fetched it.  Sets c.ac, c.pc, c.cyc (before a WSYNC stall) and queues
+// TIA writes.
+__device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, uint32_t b1, uint32_t b2) {
+    const uint32_t md = d & 15, mn = (d >> 4) & 63;
+    uint32_t n = (d >> 10) & 7;
+    if (mn == ILL) {
         c.err |= ERR_ILLEGAL;
         return;
-    } else {
-        uint32_t n = I.cyc;
-        uint32_t ea = 0;
-        if constexpr (I.md == ZP) ea = b1;
-        else if constexpr (I.md == ZPX) ea = (b1 + c.x) & 0xFF;
-        else if constexpr (I.md == ZPY) ea = (b1 + c.y) & 0xFF;
-        else if constexpr (I.md == ABS || I.md == IND) ea = b1 | (b2 << 8);
-        else if constexpr (I.md == ABX || I.md == ABY) {
-            const uint32_t base = b1 | (b2 << 8);
-            ea = (base + (I.md == ABX ? c.x : c.y)) & 0xFFFF;
-            if constexpr (I.pen) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
-        } else if constexpr (I.md == IZX) {
-            const uint32_t z = (b1 + c.x) & 0xFF;
-            ea = zp_peek(c, W, z) | (zp_peek(c, W, (z + 1) & 0xFF) << 8);
-        } else if constexpr (I.md == IZY) {
-            const uint32_t base = zp_peek(c, W, b1) | (zp_peek(c, W, (b1 + 1) & 0xFF) << 8);
-            ea = (base + c.y) & 0xFFFF;
-            if constexpr (I.pen) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
-        }
-        const uint32_t next = (c.pc + op_len(I.md)) & 0xFFFF;
-        uint32_t npc = next;
-
-        if constexpr (I.md == REL) {
-            if (branch_cond<I.mn>(c.p)) {
-                const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
-                n += 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0);
-                npc = tgt;
-            }
-        }
-        const uint32_t t = c.cyc + n - 1;     // access cycle
-        c.ac = t;
-
-        auto operand = [&]() -> uint32_t {
-            if constexpr (I.md == IMM) return b1;
-            else return rd(c, W, ea, t);
-        };
-
-        if constexpr (I.mn == LDA) { c.a = operand(); c.p = nz(c.p, c.a); }
-        else if constexpr (I.mn == LDX) { c.x = operand(); c.p = nz(c.p, c.x); }
-        else if constexpr (I.mn == LDY) { c.y = operand(); c.p = nz(c.p, c.y); }
-        else if constexpr (I.mn == STA) { wr<0>(c, W, ea, c.a, t); }
-        else if constexpr (I.mn == STX) { wr<0>(c, W, ea, c.x, t); }
-        else if constexpr (I.mn == STY) { wr<0>(c, W, ea, c.y, t); }
-        else if constexpr (I.mn == ADC) { do_adc(c, operand()); }
-        else if constexpr (I.mn == SBC) { do_sbc(c, operand()); }
-        else if constexpr (I.mn == AND) { c.a &= operand(); c.p = nz(c.p, c.a); }
-        else if constexpr (I.mn == ORA) { c.a |= operand(); c.p = nz(c.p, c.a); }
-        else if constexpr (I.mn == EOR) { c.a ^= operand(); c.p = nz(c.p, c.a); }
-        else if constexpr (I.mn == CMP) { do_cmp(c, c.a, operand()); }
-        else if constexpr (I.mn == CPX) { do_cmp(c, c.x, operand()); }
-        else if constexpr (I.mn == CPY) { do_cmp(c, c.y, operand()); }
-        else if constexpr (I.mn == BIT) {
-            const uint32_t v = operand();
-            c.p = (c.p & ~(FN | FV | FZ)) | (v & (FN | FV)) | ((c.a & v) == 0 ? FZ : 0);
-        }
-        else if constexpr (I.mn == ASL || I.mn == LSR || I.mn == ROL || I.mn == ROR || I.mn == INC ||
-                           I.mn == DEC) {
-            if constexpr (I.md == ACC) c.a = rmw_op<I.mn>(c, c.a);
-            else {
-                const uint32_t v = rd(c, W, ea, t);
-                wr<0>(c, W, ea, rmw_op<I.mn>(c, v), t);
-            }
-        }
-        else if constexpr (I.mn == INX) { c.x = (c.x + 1) & 0xFF; c.p = nz(c.p, c.x); }
-        else if constexpr (I.mn == INY) { c.y = (c.y + 1) & 0xFF; c.p = nz(c.p, c.y); }
-        else if constexpr (I.mn == DEX) { c.x = (c.x - 1) & 0xFF; c.p = nz(c.p, c.x); }
-        else if constexpr (I.mn == DEY) { c.y = (c.y - 1) & 0xFF; c.p = nz(c.p, c.y); }
-        else if constexpr (I.mn == TAX) { c.x = c.a; c.p = nz(c.p, c.x); }
-        else if constexpr (I.mn == TAY) { c.y = c.a; c.p = nz(c.p, c.y); }
-        else if constexpr (I.mn == TXA) { c.a = c.x; c.p = nz(c.p, c.a); }
-        else if constexpr (I.mn == TYA) { c.a = c.y; c.p = nz(c.p, c.a); }
-        else if constexpr (I.mn == TSX) { c.x = c.sp; c.p = nz(c.p, c.x); }
-        else if constexpr (I.mn == TXS) { c.sp = c.x; }
-        else if constexpr (I.mn == CLC) { c.p &= ~FC; }
-        else if constexpr (I.mn == SEC) { c.p |= FC; }
-        else if constexpr (I.mn == CLI) { c.p &= ~FI; }
-        else if constexpr (I.mn == SEI) { c.p |= FI; }
-        else if constexpr (I.mn == CLV) { c.p &= ~FV; }
-        else if constexpr (I.mn == CLD) { c.p &= ~FD; }
-        else if constexpr (I.mn == SED) { c.p |= FD; }
-        else if constexpr (I.mn == NOP) { }
-        else if constexpr (I.mn == PHA) { push<0>(c, W, c.a, t); }
-        else if constexpr (I.mn == PHP) { push<0>(c, W, c.p | FB | FU, t); }
-        else if constexpr (I.mn == PLA) { c.a = pull(c, W, t); c.p = nz(c.p, c.a); }
-        else if constexpr (I.mn == PLP) { c.p = (pull(c, W, t) & ~FB) | FU; }
-        else if constexpr (I.mn == JMP) {
-            if constexpr (I.md == ABS) npc = ea;
-            else {
-                const uint32_t lo = rd(c, W, ea, t);
-                const uint32_t hi = rd(c, W, (ea & 0xFF00) | ((ea + 1) & 0xFF), t);
-                npc = lo | (hi << 8);
-            }
-        }
-        else if constexpr (I.mn == JSR) {
-            const uint32_t ret = (next - 1) & 0xFFFF;
-            push<0>(c, W, ret >> 8, t);
-            push<1>(c, W, ret & 0xFF, t);
-            npc = ea;
-        }
-        else if constexpr (I.mn == RTS) {
-            const uint32_t lo = pull(c, W, t);
-            const uint32_t hi = pull(c, W, t);
-            npc = ((lo | (hi << 8)) + 1) & 0xFFFF;
-        }
-        else if constexpr (I.mn == RTI) {
-            c.p = (pull(c, W, t) & ~FB) | FU;
-            const uint32_t lo = pull(c, W, t);
-            const uint32_t hi = pull(c, W, t);
-            npc = lo | (hi << 8);
-        }
-        else if constexpr (I.mn == BRK) {
-            const uint32_t ret = (c.pc + 2) & 0xFFFF;
-            push<0>(c, W, ret >> 8, t);
-            push<1>(c, W, ret & 0xFF, t);
-            push<2>(c, W, c.p | FB | FU, t);
-            c.p |= FI;
-            const uint32_t lo = rd(c, W, 0xFFFE, t);
-            const uint32_t hi = rd(c, W, 0xFFFF, t);
-            npc = lo | (hi << 8);
-        }
-        c.pc = npc;
-        c.cyc = t + 1;
     }
+    uint32_t ea = 0;
+    switch (md) {
+    case ZP: ea = b1; break;
+    case ZPX: ea = (b1 + c.x) & 0xFF; break;
+    case ZPY: ea = (b1 + c.y) & 0xFF; break;
+    case ABS: case IND: ea = b1 | (b2 << 8); break;
+    case ABX: case ABY: {
+        const uint32_t base = b1 | (b2 << 8);
+        ea = (base + (md == ABX ? c.x : c.y)) & 0xFFFF;
+        if ((d >> 13) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
+        break;
+    }
+    case IZX: {
+        const uint32_t z = (b1 + c.x) & 0xFF;
+        ea = zp_peek(c, W, z) | (zp_peek(c, W, (z + 1) & 0xFF) << 8);
+        break;
+    }
+    case IZY: {
+        const uint32_t base = zp_peek(c, W, b1) | (zp_peek(c, W, (b1 + 1) & 0xFF) << 8);
+        ea = (base + c.y) & 0xFFFF;
+        if ((d >> 13) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
+        break;
+    }
+    default: break;
+    }
+    const uint32_t next = (c.pc + ((d >> 14) & 3)) & 0xFFFF;
+    uint32_t npc = next;
+    if (md == REL) {
+        bool taken;
+        switch (mn) {
+        case BPL: taken = !(c.p & FN); break;
+        case BMI: taken = (c.p & FN) != 0; break;
+        case BVC: taken = !(c.p & FV); break;
+        case BVS: taken = (c.p & FV) != 0; break;
+        case BCC: taken = !(c.p & FC); break;
+        case BCS: taken = (c.p & FC) != 0; break;
+        case BNE: taken = !(c.p & FZ); break;
+        default: taken = (c.p & FZ) != 0; break;
+        }
+        if (taken) {
+            const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
+            n += 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0);
+            npc = tgt;
+        }
+    }
+    const uint32_t t = c.cyc + n - 1;     // access cycle
+    c.ac = t;
+    uint32_t v = b1;                      // operand (immediate, or read below)
+    if ((d >> 16) & 1) v = rd(c, W, ea, t);
+    uint32_t res = 0;                     // value written to ea when (d >> 17) & 1
+    switch (mn) {
+    case LDA: c.a = v; c.p = nz(c.p, v); break;
+    case LDX: c.x = v; c.p = nz(c.p, v); break;
+    case LDY: c.y = v; c.p = nz(c.p, v); break;
+    case STA: res = c.a; break;
+    case STX: res = c.x; break;
+    case STY: res = c.y; break;
+    case ADC: do_adc(c, v); break;
+    case SBC: do_sbc(c, v); break;
+    case AND: c.a &= v; c.p = nz(c.p, c.a); break;
+    case ORA: c.a |= v; c.p = nz(c.p, c.a); break;
+    case EOR: c.a ^= v; c.p = nz(c.p, c.a); break;
+    case CMP: do_cmp(c, c.a, v); break;
+    case CPX: do_cmp(c, c.x, v); break;
+    case CPY: do_cmp(c, c.y, v); break;
+    case BIT: c.p = (c.p & ~(FN | FV | FZ)) | (v & (FN | FV)) | ((c.a & v) == 0 ? FZ : 0); break;
+    case ASL: case LSR: case ROL: case ROR: case INC: case DEC: {
+        const uint32_t x = md == ACC ? c.a : v;
+        const uint32_t ci = c.p & FC;
+        uint32_t r, co = ci;
+        if (mn == ASL) { r = (x << 1) & 0xFF; co = x >> 7; }
+        else if (mn == LSR) { r = x >> 1; co = x & 1; }
+        else if (mn == ROL) { r = ((x << 1) | ci) & 0xFF; co = x >> 7; }
+        else if (mn == ROR) { r = (x >> 1) | (ci << 7); co = x & 1; }
+        else if (mn == INC) { r = (x + 1) & 0xFF; }
+        else { r = (x - 1) & 0xFF; }
+        c.p = nz((c.p & ~FC) | co, r);
+        if (md == ACC) c.a = r;
+        res = r;
+        break;
+    }
+    case INX: c.x = (c.x + 1) & 0xFF; c.p = nz(c.p, c.x); break;
+    case INY: c.y = (c.y + 1) & 0xFF; c.p = nz(c.p, c.y); break;
+    case DEX: c.x = (c.x - 1) & 0xFF; c.p = nz(c.p, c.x); break;
+    case DEY: c.y = (c.y - 1) & 0xFF; c.p = nz(c.p, c.y); break;
+    case TAX: c.x = c.a; c.p = nz(c.p, c.x); break;
+    case TAY: c.y = c.a; c.p = nz(c.p, c.y); break;
+    case TXA: c.a = c.x; c.p = nz(c.p, c.a); break;
+    case TYA: c.a = c.y; c.p = nz(c.p, c.a); break;
+    case TSX: c.x = c.sp; c.p = nz(c.p, c.x); break;
+    case TXS: c.sp = c.x; break;
+    case CLC: c.p &= ~FC; break;
+    case SEC: c.p |= FC; break;
+    case CLI: c.p &= ~FI; break;
+    case SEI: c.p |= FI; break;
+    case CLV: c.p &= ~FV; break;
+    case CLD: c.p &= ~FD; break;
+    case SED: c.p |= FD; break;
+    case PHA: push<0>(c, W, c.a, t); break;
+    case PHP: push<0>(c, W, c.p | FB | FU, t); break;
+    case PLA: c.a = pull(c, W, t); c.p = nz(c.p, c.a); break;
+    case PLP: c.p = (pull(c, W, t) & ~FB) | FU; break;
+    case JMP:
+        if (md == ABS) {
+            npc = ea;
+        } else {                          // the pointer's high byte stays in its page
+            const uint32_t lo = rd(c, W, ea, t);
+            const uint32_t hi = rd(c, W, (ea & 0xFF00) | ((ea + 1) & 0xFF), t);
+            npc = lo | (hi << 8);
+        }
+        break;
+    case JSR: {
+        const uint32_t ret = (next - 1) & 0xFFFF;
+        push<0>(c, W, ret >> 8, t);
+        push<1>(c, W, ret & 0xFF, t);
+        npc = ea;
+        break;
+    }
+    case RTS: {
+        const uint32_t lo = pull(c, W, t);
+        const uint32_t hi = pull(c, W, t);
+        npc = ((lo | (hi << 8)) + 1) & 0xFFFF;
+        break;
+    }
+    case RTI: {
+        c.p = (pull(c, W, t) & ~FB) | FU;
+        const uint32_t lo = pull(c, W, t);
+        const uint32_t hi = pull(c, W, t);
+        npc = lo | (hi << 8);
+        break;
+    }
+    case BRK: {
+        const uint32_t ret = (c.pc + 2) & 0xFFFF;
+        push<0>(c, W, ret >> 8, t);
+        push<1>(c, W, ret & 0xFF, t);
+        push<2>(c, W, c.p | FB | FU, t);
+        c.p |= FI;
+        const uint32_t lo = rd(c, W, 0xFFFE, t);
+        const uint32_t hi = rd(c, W, 0xFFFF, t);
+        npc = lo | (hi << 8);
+        break;
+    }
+    default: break;                       // NOP, branches
+    }
+    if ((d >> 17) & 1) wr<0>(c, W, ea, res, t);
+    c.pc = npc;
+    c.cyc = t + 1;
 }
 
 // ------------------------------------------------------------ row log
@@ -552,18 +579,6 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t q, uin
         R[R_P1X] = (uint8_t)v1;
     } else {
         R[code] = (uint8_t)v0;
-    }
-}
-
-#define VCS_CASE1(n) case n: exec<n>(c, W, b1, b2); break;
-#define VCS_CASE4(n) VCS_CASE1(n) VCS_CASE1(n + 1) VCS_CASE1(n + 2) VCS_CASE1(n + 3)
-#define VCS_CASE16(n) VCS_CASE4(n) VCS_CASE4(n + 4) VCS_CASE4(n + 8) VCS_CASE4(n + 12)
-#define VCS_CASE64(n) VCS_CASE16(n) VCS_CASE16(n + 16) VCS_CASE16(n + 32) VCS_CASE16(n + 48)
-
-__device__ __forceinline__ void dispatch(uint32_t sop, Cpu& c, const Wave& W, uint32_t b1, uint32_t b2) {
-    switch (sop) {
-        VCS_CASE64(0) VCS_CASE64(64) VCS_CASE64(128) VCS_CASE64(192)
-    default: break;
     }
 }
 
@@ -666,8 +681,8 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
             if ((uint32_t)(rng_draw(sticky_prefix, ctr) >> 32) < A.sticky_thr) eff = prev_action;
         }
         prev_action = eff;
-        c.swcha = (0xF0u & ~(uint32_t)kJoy[eff]) | 0x0Fu;
-        c.inpt4 = kFire[eff] ? 0x00u : 0x80u;
+        c.swcha = (0xF0u & ~joy_pressed(eff)) | 0x0Fu;
+        c.inpt4 = fire_pressed(eff) ? 0x00u : 0x80u;
         c.cap = 76u * (uint32_t)(320 + c.fl);
         const int32_t slot = A.render_all ? (int32_t)f : (int32_t)f - ((int32_t)nfr - 2);
         c.log = (A.log_enabled && slot >= 0 && slot < (int32_t)A.n_slots)
@@ -727,8 +742,14 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
         while (__any(todo)) {
             if (todo) {
                 const uint32_t sop = __builtin_amdgcn_readfirstlane(op);
+                // an opaque scalar copy: inside the branch below the compiler
+                // would otherwise switch on the per-lane `op` (equal there)
+                uint32_t sw = sop;
+                asm volatile("" : "+s"(sw));
+                uint32_t d = kDecode.w[sw];
+                asm volatile("" : "+s"(d));
                 if (op == sop) {
-                    dispatch(sop, c, W, b1, b2);
+                    exec_generic(d, c, W, b1, b2);
                     todo = false;
                 }
             }

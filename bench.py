@@ -111,7 +111,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     env.timing(False)
-    instr_last = env.last_step_instructions()
+    instr_last, instr_uniform = env.last_step_stats()
     kern = {}
     for k, name in KERNELS.items():
         ms, cnt = env.kernel_time(k)
@@ -152,6 +152,7 @@ def main():
         "render_roofline": render,
         "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
         "emulated_instr_per_step": instr_last,
+        "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -153,6 +153,12 @@ int vcs_poll_errors(vcs_ctx* ctx, uint32_t* first_env, uint32_t* bits);
    Used to report emulated-instruction throughput. */
 int vcs_last_step_instructions(vcs_ctx* ctx, uint64_t* out);
 
+/* out2[0]: instructions emulated by the last vcs_step; out2[1]: how many of
+   them ran in wave-uniform mode (every lane of a wave at the same PC, bank
+   and cycle, so fetch, decode and timing ran once for the wave).
+   Synchronises. */
+int vcs_last_step_stats(vcs_ctx* ctx, uint64_t* out2);
+
 /* Average device time of the named kernel over the timed region: the caller
    brackets steps with vcs_timing(ctx, 1) ... vcs_timing(ctx, 0), then reads
    the mean duration in ms and launch count of kernel `which`

@@ -64,12 +64,13 @@ def _declare(L):
     L.vcs_get_cache.argtypes = [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp]
     L.vcs_poll_errors.argtypes = [_vp, _vp, _vp]
     L.vcs_last_step_instructions.argtypes = [_vp, _vp]
+    L.vcs_last_step_stats.argtypes = [_vp, _vp]
     L.vcs_timing.argtypes = [_vp, ctypes.c_int]
     L.vcs_kernel_time.argtypes = [_vp, ctypes.c_int, _vp, _vp]
     L.vcs_last_error.argtypes = []
     L.vcs_last_error.restype = ctypes.c_char_p
     for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_get_state",
-                 "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions",
+                 "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions", "vcs_last_step_stats",
                  "vcs_timing", "vcs_kernel_time"):
         getattr(L, name).restype = ctypes.c_int
 
@@ -160,6 +161,12 @@ def vcs_last_step_instructions(h):
     v = ctypes.c_uint64()
     check(lib.vcs_last_step_instructions(h, ctypes.byref(v)), "vcs_last_step_instructions")
     return v.value
+
+
+def vcs_last_step_stats(h):
+    v = (ctypes.c_uint64 * 2)()
+    check(lib.vcs_last_step_stats(h, v), "vcs_last_step_stats")
+    return v[0], v[1]
 
 
 def vcs_timing(h, enable):

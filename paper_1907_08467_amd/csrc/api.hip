@@ -268,7 +268,7 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
     if (!rc) rc = alloc_n(c, &c->d_info, B, "step info");
     if (!rc) rc = alloc_n(c, &c->d_valid, B, "id validity");
     if (!rc) rc = alloc_n(c, &c->d_err, 2, "error word");
-    if (!rc) rc = alloc_n(c, &c->d_instr, 1, "instruction counter");
+    if (!rc) rc = alloc_n(c, &c->d_instr, 2, "instruction counters");
     if (!rc) rc = alloc_n(c, &c->d_gray, 128, "gray table");
     if (!rc) rc = alloc_n(c, &c->d_n_tiles, 1, "tile count");
     if (!rc) rc = alloc_n(c, &c->d_n_tiles_all, 1, "tile count");
@@ -554,7 +554,7 @@ int vcs_step(vcs_ctx* c, const int32_t* ids, const uint8_t* actions, uint32_t n,
         tiles = c->d_tiles;
         n_tiles = c->d_n_tiles;
     }
-    launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_instr), 2, 0, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_instr), 4, 0, s);
     InterpArgs ia{};
     ia.tiles = tiles;
     ia.n_tiles = n_tiles;
@@ -681,6 +681,17 @@ int vcs_last_step_instructions(vcs_ctx* c, uint64_t* out) {
     unsigned long long v = 0;
     HIP_OK(hipMemcpy(&v, c->d_instr, 8, hipMemcpyDeviceToHost));
     *out = v;
+    return VCS_OK;
+}
+
+int vcs_last_step_stats(vcs_ctx* c, uint64_t* out2) {
+    if (!c || !out2) return fail(VCS_E_INVAL, "null argument");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    HIP_OK(hipDeviceSynchronize());
+    unsigned long long v[2] = {0, 0};
+    HIP_OK(hipMemcpy(v, c->d_instr, 16, hipMemcpyDeviceToHost));
+    out2[0] = v[0];
+    out2[1] = v[1];
     return VCS_OK;
 }
 

@@ -170,13 +170,16 @@ struct Cpu {
     uint32_t tv, tshift;
     uint32_t ev, err;
     uint32_t ac;              // access cycle of the current instruction
-    uint32_t tq0, tq1, tq2, tqm;   // queued TIA writes (reg | value << 8) and their mask
+    uint32_t tqr0, tqr1, tqr2;     // queued TIA writes: register (scalar when the address is)
+    uint32_t tqv0, tqv1, tqv2;     //   and value
+    uint32_t tqm;                  //   and the mask of used slots
     uint32_t ram_off, tia_off;
     uint8_t* log;             // current frame's row log, or nullptr
     uint32_t slot, slots;     // its slot; slots completed so far
     int32_t open_row;
     uint32_t open_cnt;
     uint32_t icount;
+    uint32_t ucount;          // instructions executed in wave-uniform mode
 };
 
 __device__ __forceinline__ uint32_t nz(uint32_t p, uint32_t v) {
@@ -240,10 +243,9 @@ __device__ __forceinline__ void wr(Cpu& c, const Wave& W, uint32_t addr, uint32_
     if (a & 0x1000) {
         cart_touch(c, W, a);
     } else if (!(a & 0x80)) {
-        const uint32_t q = (a & 0x3F) | ((v & 0xFF) << 8);
-        if (K == 0) c.tq0 = q;
-        if (K == 1) c.tq1 = q;
-        if (K == 2) c.tq2 = q;
+        if (K == 0) { c.tqr0 = a & 0x3F; c.tqv0 = v & 0xFF; }
+        if (K == 1) { c.tqr1 = a & 0x3F; c.tqv1 = v & 0xFF; }
+        if (K == 2) { c.tqr2 = a & 0x3F; c.tqv2 = v & 0xFF; }
         c.tqm |= 1u << K;
     } else if (!(a & 0x200)) {
         W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
@@ -541,9 +543,8 @@ __device__ __forceinline__ void log_close(Cpu& c, const Wave& W, uint32_t t) {
     c.slots |= 1u << c.slot;
 }
 
-// Apply one queued TIA write (reg | value << 8) made at cycle t.
-__device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t q, uint32_t t) {
-    const uint32_t reg = q & 0x3F, v = q >> 8;
+// Apply one queued TIA write of `v` to register `reg` made at cycle t.
+__device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, uint32_t v, uint32_t t) {
     uint8_t* R = W.tia + c.tia_off;
     switch (reg) {
     case 0x00:
@@ -580,6 +581,81 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t q, uin
     } else {
         R[code] = (uint8_t)v0;
     }
+}
+
+__device__ __forceinline__ void apply_queue(Cpu& c, const Wave& W, uint32_t t) {
+    if (c.tqm) {
+        if (c.tqm & 1) tia_apply(c, W, c.tqr0, c.tqv0, t);
+        if (c.tqm & 2) tia_apply(c, W, c.tqr1, c.tqv1, t);
+        if (c.tqm & 4) tia_apply(c, W, c.tqr2, c.tqv2, t);
+    }
+}
+
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Wave-uniform execution.  Precondition: every lane in exec has the same pc,
+// bank, cycle and frame line.  Those stay scalar here (fetch, decode,
+// addressing and timing run on the scalar unit; the compiler sees them as
+// uniform); only data (A, X, Y, P, SP, RAM, TIA registers) is per lane.  The
+// block returns when the lanes stop agreeing (a branch, a page-crossing
+// penalty or a stack target that differs, a frame that ends in some lanes
+// only), when a frame ends, or at a fetch outside the cartridge; `c` then
+// holds every lane's state.
+__device__ __forceinline__ void run_uniform(Cpu& c, const Wave& W, const uint32_t* s_rom, bool& ended,
+                                            uint32_t& end_t) {
+    Cpu u = c;
+    u.pc = rfl(c.pc);
+    u.bank = rfl(c.bank);
+    u.cyc = rfl(c.cyc);
+    u.fl = rfl(c.fl);
+    u.cap = rfl(c.cap);
+    for (;;) {
+        if (u.cyc >= u.cap) {
+            u.err |= ERR_FRAME_CAP;
+            ended = true;
+            end_t = u.cyc - 1;
+            break;
+        }
+        const uint32_t off = u.pc & 0xFFF;
+        if (!(u.pc & 0x1000) || off > 0xFFD) break;    // the per-lane path fetches this one
+        const uint32_t boff = (u.bank << 12) | off;
+        const uint32_t w = rfl(__builtin_amdgcn_alignbyte(s_rom[(boff >> 2) + 1], s_rom[boff >> 2], boff & 3));
+        uint32_t d = kDecode.w[w & 0xFF];
+        asm volatile("" : "+s"(d));
+        u.ev = 0;
+        u.tqm = 0;
+        exec_generic(d, u, W, (w >> 8) & 0xFF, (w >> 16) & 0xFF);
+        if (u.err & ERR_ILLEGAL) {
+            ended = true;
+            end_t = u.cyc - 1;
+            break;
+        }
+        u.icount++;
+        u.ucount++;
+        const uint32_t t = u.ac;
+        apply_queue(u, W, t);
+        if (u.ev & EV_WSYNC) u.cyc = 76 * (t / 76 + 1);
+        const uint32_t vs = (u.ev & EV_VSYNC) ? 1u : 0u;
+        const uint32_t pc0 = rfl(u.pc), cy0 = rfl(u.cyc), bk0 = rfl(u.bank), vs0 = rfl(vs);
+        const bool same = u.pc == pc0 && u.cyc == cy0 && u.bank == bk0 && vs == vs0;
+        if (__builtin_amdgcn_ballot_w64(!same) != 0) {
+            if (vs) {
+                ended = true;
+                end_t = t;
+            }
+            break;
+        }
+        u.pc = pc0;
+        u.cyc = cy0;
+        u.bank = bk0;
+        if (vs0) {
+            ended = true;
+            end_t = t;
+            break;
+        }
+    }
+    c = u;
 }
 
 __device__ __forceinline__ uint32_t bcd_value(uint32_t b) { return 10 * (b >> 4) + (b & 15); }
@@ -664,6 +740,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
     score0 = active ? W.ram[c.ram_off + 0x50] : 0;
     c.base = base_line * 76;
     c.icount = 0;
+    c.ucount = 0;
     c.slots = 0;
     c.slot = 0;
     c.log = nullptr;
@@ -710,8 +787,20 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
         uint32_t op = 0, b1 = 0, b2 = 0;
         bool want = false, ended = false;
         uint32_t end_t = 0;
-        const uint32_t tmin = wave_min(active ? c.cyc : 0xFFFFFFFFu);
-        const bool go = active && c.cyc <= tmin + kSchedWindow;
+        // wave-uniform mode when every running lane is at the same place
+        bool uni = false;
+        if (active) {
+            const uint32_t pc0 = rfl(c.pc), bk0 = rfl(c.bank), cy0 = rfl(c.cyc);
+            const int32_t fl0 = rfl(c.fl);
+            const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == cy0 && c.fl == fl0;
+            if (__builtin_amdgcn_ballot_w64(!same) == 0) {
+                run_uniform(c, W, s_rom, ended, end_t);
+                uni = true;
+            }
+        }
+        const bool ran_uniform = __any(uni);
+        const uint32_t tmin = ran_uniform ? 0u : wave_min(active ? c.cyc : 0xFFFFFFFFu);
+        const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;
         if (go) {
             if (c.cyc >= c.cap) {
                 c.err |= ERR_FRAME_CAP;
@@ -761,11 +850,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
             } else {
                 c.icount++;
                 const uint32_t t = c.ac;
-                if (c.tqm) {
-                    if (c.tqm & 1) tia_apply(c, W, c.tq0, t);
-                    if (c.tqm & 2) tia_apply(c, W, c.tq1, t);
-                    if (c.tqm & 4) tia_apply(c, W, c.tq2, t);
-                }
+                apply_queue(c, W, t);
                 if (c.ev & EV_WSYNC) c.cyc = 76 * (t / 76 + 1);
                 if (c.ev & EV_VSYNC) {
                     ended = true;
@@ -822,7 +907,10 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
             atomicOr(&A.err_word[0], c.err);
             atomicMin(&A.err_word[1], (uint32_t)env);
         }
-        if (A.instr_total) atomicAdd(A.instr_total, (unsigned long long)c.icount);
+        if (A.instr_total) {
+            atomicAdd(&A.instr_total[0], (unsigned long long)c.icount);
+            atomicAdd(&A.instr_total[1], (unsigned long long)c.ucount);
+        }
     }
 }
 

@@ -108,6 +108,9 @@ class VcsEnv:
     def last_step_instructions(self):
         return B.vcs_last_step_instructions(self._h)
 
+    def last_step_stats(self):
+        return B.vcs_last_step_stats(self._h)
+
     def timing(self, enable):
         B.vcs_timing(self._h, enable)
 

@@ -36,6 +36,8 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
+    p.add_argument("--launch", type=str, default="auto",
+                   help="'auto' (autotuner) or tile_envs,workers,render_block, e.g. 64,0,256")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     return p.parse_args()
@@ -91,6 +93,13 @@ def main():
     dev = torch.device("cuda", 0)
     env = VcsEnv(roms, env_rom, GRAY, frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode)
     n, K, W = w.n_envs, args.steps, args.warmup
+    if args.launch == "auto":
+        launch, tune_ms = env.autotune(steps=3, want_frames=True, want_obs=True)
+        print(f"autotuner picked {launch} ({tune_ms:.3f} ms/step)", file=sys.stderr, flush=True)
+    else:
+        tw, wk, rb = (int(x) for x in args.launch.split(","))
+        env.set_launch(tw, wk, rb)
+        launch = env.get_launch()
     acts = torch.from_numpy(w.actions(steps=K + W)).to(dev)
     obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
     rew = torch.empty(n, dtype=torch.int32, device=dev)
@@ -147,7 +156,8 @@ def main():
         "config": {"workload": f"plain batched step: {n} envs x 1 seeded 4 KB synthetic cartridge, frameskip "
                                f"{w.frameskip}, every 210x160 frame rendered to HBM + 84x84 max-of-two gray obs, "
                                "random actions (seed 1), no sticky actions",
-                   "num_envs": n, "frameskip": w.frameskip, "render": "all frames"},
+                   "num_envs": n, "frameskip": w.frameskip, "render": "all frames",
+                   "launch": launch, "launch_from": "autotuner" if args.launch == "auto" else "fixed"},
         "roofline": roofline,
         "render_roofline": render,
         "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},

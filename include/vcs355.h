@@ -85,6 +85,9 @@ typedef struct {
     uint32_t max_batch;         /* largest n of one step/reset call (0 = num_envs) */
     uint64_t hbm_budget_bytes;  /* cap on device memory the context allocates; 0 = none */
     int32_t device;             /* HIP device ordinal */
+    uint32_t pipelines;         /* step pipelines (0 = 1, at most 8): each has its own
+                                   scratch of max_batch envs, so calls on different
+                                   pipelines may run concurrently (vcs_step_pipe) */
     uint8_t gray_lut[128];      /* gray level of colour index (colour >> 1)      */
 } vcs_config;
 
@@ -124,6 +127,14 @@ int vcs_reset(vcs_ctx* ctx, const int32_t* env_ids_dev, uint32_t n, uint8_t* obs
 int vcs_step(vcs_ctx* ctx, const int32_t* env_ids_dev, const uint8_t* actions_dev, uint32_t n,
              uint8_t* obs_dev, int32_t* reward_dev, uint8_t* done_dev, uint8_t* frames_dev,
              void* stream);
+
+/* vcs_step on pipeline `pipe` (vcs_step uses pipeline 0).  Calls on different
+   pipelines may be in flight at once, on different streams, provided they
+   list disjoint env ids: each env's steps then happen in the order the calls
+   were made for it, and its results are those it would get from the same
+   calls made one at a time.  VCS_E_INVAL for pipe >= pipelines. */
+int vcs_step_pipe(vcs_ctx* ctx, uint32_t pipe, const int32_t* env_ids_dev, const uint8_t* actions_dev, uint32_t n,
+                  uint8_t* obs_dev, int32_t* reward_dev, uint8_t* done_dev, uint8_t* frames_dev, void* stream);
 
 /* Machine-state record (256 bytes, little-endian) of one env:
      0 A  1 X  2 Y  3 SP  4 P  5 bank  6..7 PC
@@ -166,6 +177,60 @@ int vcs_last_step_stats(vcs_ctx* ctx, uint64_t* out2);
    Events are recorded on the stream each kernel is launched on. */
 int vcs_timing(vcs_ctx* ctx, int enable);
 int vcs_kernel_time(vcs_ctx* ctx, int which, double* mean_ms, uint32_t* launches);
+
+/* ---- batching form: launch shape, autotuner, captured steps ----------------
+   The paper runs one GPU thread per emulator and reports two effects of the
+   launch on throughput (Section 4, the emulation-only results and "Factors
+   affecting the FPS"): low occupancy at small env counts, and divergence of
+   envs that share a warp.  The calls below make the shape a parameter, pick
+   it by measurement and capture whole steps in a HIP graph.  None of them
+   changes any result: outputs and states are identical under every launch
+   shape. */
+typedef struct {
+    uint32_t tile_envs;     /* envs per interpreter wave (one tile): 1, 2, 4, ..., 64.
+                               Tiles hold envs of one ROM; fewer envs per wave spread a
+                               small batch over more compute units. Default 64. */
+    uint32_t workers;       /* 0: one workgroup per tile.  k > 0: a persistent
+                               interpreter of k workgroups that take tiles from a device
+                               queue until none are left (used only when k is below the
+                               tile count).  Default 0. */
+    uint32_t render_block;  /* threads per render / observation workgroup: 64, 128, 256
+                               or 512.  Default 256. */
+} vcs_launch;
+
+/* Set the launch shape (checked as above; VCS_E_INVAL otherwise).  Rebuilds the
+   tile table; synchronises.  Graphs captured before are invalidated. */
+int vcs_set_launch(vcs_ctx* ctx, const vcs_launch* launch);
+int vcs_get_launch(vcs_ctx* ctx, vcs_launch* out);
+
+/* Autotuner.  Times `steps` steps (after one untimed step) of envs 0..n-1
+   (n = 0: max_batch) with seeded random actions for each candidate shape,
+   one knob at a time: tile_envs (64 and every smaller width that keeps at most
+   8 tiles per compute unit), then workers (1, 2, 4, 8 per compute unit, below
+   the tile count), then render_block.  Every candidate starts from the same
+   env states; afterwards the states, the error bits and the counters are
+   restored, so later steps give the results they would have given without
+   tuning.  Keeps the fastest shape and returns it with its ms per step.
+   Temporary device buffers (a state snapshot, outputs: frames only if
+   want_frames, obs only if want_obs) count against the budget.
+   Synchronises. */
+int vcs_autotune(vcs_ctx* ctx, uint32_t n, uint32_t steps, int want_frames, int want_obs,
+                 vcs_launch* best_out, double* best_ms_out);
+
+/* A HIP graph holding `steps` (1..64) consecutive vcs_step calls with fixed
+   arguments: step j reads actions_dev + j*n and writes obs_dev + j*n*84*84,
+   reward_dev + j*n, done_dev + j*n and frames_dev + j*n*F*210*160 (obs_dev and
+   frames_dev may be NULL).  The caller refills actions_dev between launches.
+   A launch enqueues the whole graph on `stream` and gives exactly the results
+   of the same vcs_step calls.  VCS_E_STATE after vcs_load_roms, vcs_assign or
+   vcs_set_launch on the context.  The graph must be destroyed before its
+   context and must not run concurrently with other calls on that context. */
+typedef struct vcs_graph vcs_graph;
+int vcs_graph_create(vcs_ctx* ctx, const int32_t* env_ids_dev, const uint8_t* actions_dev, uint32_t n,
+                     uint32_t steps, uint8_t* obs_dev, int32_t* reward_dev, uint8_t* done_dev,
+                     uint8_t* frames_dev, vcs_graph** out);
+int vcs_graph_launch(vcs_graph* graph, void* stream);
+void vcs_graph_destroy(vcs_graph* graph);
 
 const char* vcs_last_error(void);
 

@@ -37,8 +37,20 @@ class VcsConfig(ctypes.Structure):
         ("max_batch", ctypes.c_uint32),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("device", ctypes.c_int32),
+        ("pipelines", ctypes.c_uint32),
         ("gray_lut", ctypes.c_uint8 * 128),
     ]
+
+
+class VcsLaunch(ctypes.Structure):
+    _fields_ = [
+        ("tile_envs", ctypes.c_uint32),
+        ("workers", ctypes.c_uint32),
+        ("render_block", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {"tile_envs": self.tile_envs, "workers": self.workers, "render_block": self.render_block}
 
 
 class VcsError(RuntimeError):
@@ -59,6 +71,7 @@ def _declare(L):
     L.vcs_assign.argtypes = [_vp, _vp]
     L.vcs_reset.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp]
     L.vcs_step.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp]
+    L.vcs_step_pipe.argtypes = [_vp, ctypes.c_uint32, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp]
     L.vcs_get_state.argtypes = [_vp, ctypes.c_uint32, _vp]
     L.vcs_set_state.argtypes = [_vp, ctypes.c_uint32, _vp]
     L.vcs_get_cache.argtypes = [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp]
@@ -67,11 +80,21 @@ def _declare(L):
     L.vcs_last_step_stats.argtypes = [_vp, _vp]
     L.vcs_timing.argtypes = [_vp, ctypes.c_int]
     L.vcs_kernel_time.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+    L.vcs_set_launch.argtypes = [_vp, ctypes.POINTER(VcsLaunch)]
+    L.vcs_get_launch.argtypes = [_vp, ctypes.POINTER(VcsLaunch)]
+    L.vcs_autotune.argtypes = [_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(VcsLaunch), ctypes.POINTER(ctypes.c_double)]
+    L.vcs_graph_create.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp, _vp,
+                                   ctypes.POINTER(_vp)]
+    L.vcs_graph_launch.argtypes = [_vp, _vp]
+    L.vcs_graph_destroy.argtypes = [_vp]
+    L.vcs_graph_destroy.restype = None
     L.vcs_last_error.argtypes = []
     L.vcs_last_error.restype = ctypes.c_char_p
-    for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_get_state",
+    for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_step_pipe", "vcs_get_state",
                  "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions", "vcs_last_step_stats",
-                 "vcs_timing", "vcs_kernel_time"):
+                 "vcs_timing", "vcs_kernel_time", "vcs_set_launch", "vcs_get_launch", "vcs_autotune",
+                 "vcs_graph_create", "vcs_graph_launch"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -132,6 +155,11 @@ def vcs_step(h, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_p
     check(lib.vcs_step(h, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_ptr, stream), "vcs_step")
 
 
+def vcs_step_pipe(h, pipe, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_ptr, stream):
+    check(lib.vcs_step_pipe(h, pipe, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_ptr, stream),
+          "vcs_step_pipe")
+
+
 def vcs_get_state(h, env):
     buf = (ctypes.c_uint8 * STATE_BYTES)()
     check(lib.vcs_get_state(h, env, buf), "vcs_get_state")
@@ -178,6 +206,40 @@ def vcs_kernel_time(h, which):
     cnt = ctypes.c_uint32()
     check(lib.vcs_kernel_time(h, which, ctypes.byref(ms), ctypes.byref(cnt)), "vcs_kernel_time")
     return ms.value, cnt.value
+
+
+def vcs_set_launch(h, tile_envs=64, workers=0, render_block=256):
+    l = VcsLaunch(tile_envs, workers, render_block)
+    check(lib.vcs_set_launch(h, ctypes.byref(l)), "vcs_set_launch")
+
+
+def vcs_get_launch(h):
+    l = VcsLaunch()
+    check(lib.vcs_get_launch(h, ctypes.byref(l)), "vcs_get_launch")
+    return l.as_dict()
+
+
+def vcs_autotune(h, n, steps, want_frames, want_obs):
+    l = VcsLaunch()
+    ms = ctypes.c_double()
+    check(lib.vcs_autotune(h, n, steps, int(bool(want_frames)), int(bool(want_obs)), ctypes.byref(l),
+                           ctypes.byref(ms)), "vcs_autotune")
+    return l.as_dict(), ms.value
+
+
+def vcs_graph_create(h, ids_ptr, actions_ptr, n, steps, obs_ptr, reward_ptr, done_ptr, frames_ptr):
+    g = _vp()
+    check(lib.vcs_graph_create(h, ids_ptr, actions_ptr, n, steps, obs_ptr, reward_ptr, done_ptr, frames_ptr,
+                               ctypes.byref(g)), "vcs_graph_create")
+    return g
+
+
+def vcs_graph_launch(g, stream):
+    check(lib.vcs_graph_launch(g, stream), "vcs_graph_launch")
+
+
+def vcs_graph_destroy(g):
+    lib.vcs_graph_destroy(g)
 
 
 def vcs_last_error():

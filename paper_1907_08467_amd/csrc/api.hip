@@ -1,6 +1,7 @@
 // vcs355 C ABI: context, device memory plan and the step/reset pipelines.
 //
 // Per step (all on the caller's stream, no host synchronisation):
+//   k_step_begin       clear the per-call counters (and the tile queue)
 //   [ids given]  validate ids, count per ROM, lay out ROM-homogeneous tiles
 //   k_interp           frameskip frames per env, row logs for rendered frames
 //   k_render_frames    frames that only go to the frames output (mode ALL)
@@ -39,6 +40,21 @@ struct TimedLaunch {
 
 }  // namespace
 
+// Scratch of one step pipeline.  d_stepw holds the per-call words
+// [counts R][offsets R][fill R] (pad) [instruction counters, 2 x u64][queue].
+struct Pipe {
+    uint8_t* d_logs = nullptr;      // [max_batch][n_slots] row logs
+    StepInfo* d_info = nullptr;     // [max_batch]
+    uint8_t* d_valid = nullptr;     // [max_batch]
+    Tile* d_tiles = nullptr;        // [tiles_cap]
+    uint32_t* d_n_tiles = nullptr;
+    uint32_t* d_tag = nullptr;      // claim tag: pipeline index + 8 x (calls that validated ids)
+    uint32_t* d_stepw = nullptr;
+    uint32_t* d_counts = nullptr;
+    unsigned long long* d_instr = nullptr;
+    uint32_t* d_queue = nullptr;
+};
+
 struct vcs_ctx {
     vcs_config cfg{};
     uint32_t max_batch = 0;
@@ -49,6 +65,7 @@ struct vcs_ctx {
     // ROMs
     uint32_t n_roms = 0;
     uint8_t* d_roms = nullptr;
+    uint2* d_pre = nullptr;
     uint32_t* d_schemes = nullptr;
     std::vector<uint32_t> h_schemes;
     std::vector<uint8_t> h_roms;   // [n_roms][kRomSlot]
@@ -63,23 +80,22 @@ struct vcs_ctx {
     DevEnv* d_cache_state = nullptr;
     uint8_t* d_cache_obs = nullptr;
 
-    // tiles
+    // launch shape and tiles
+    vcs_launch launch{64, 0, 256};
+    uint32_t n_cu = 0;
+    uint64_t generation = 0;        // bumped when tiles or the launch shape change
     Tile* d_tiles_all = nullptr;
     uint32_t n_tiles_all = 0;
     uint32_t* d_n_tiles_all = nullptr;
-    Tile* d_tiles = nullptr;
-    uint32_t tiles_cap = 0;
-    uint32_t* d_n_tiles = nullptr;
-    uint32_t* d_counts = nullptr;   // [n_roms] x 3: counts, offsets, fill
     uint32_t* d_claim = nullptr;
-    uint8_t* d_valid = nullptr;
-    uint32_t tag = 0;
+    uint32_t stepw_words = 0;
+    uint32_t instr_off = 0;         // word offset of the instruction counters in Pipe::d_stepw
+    uint32_t tiles_cap = 0;         // tiles per pipeline buffer
 
-    // per-step scratch
-    uint8_t* d_logs = nullptr;
-    StepInfo* d_info = nullptr;
+    // per-pipeline scratch: calls on different pipelines may run concurrently
+    std::vector<Pipe> pipes;
+
     uint32_t* d_err = nullptr;
-    unsigned long long* d_instr = nullptr;
     uint8_t* d_gray = nullptr;
 
     // timing
@@ -217,19 +233,174 @@ int from_record(const uint8_t* in, DevEnv* e) {
     return 0;
 }
 
-// Build ROM-homogeneous tiles on the device for the ids of one call.
-int build_tiles(vcs_ctx* c, const int32_t* ids, uint32_t n, int32_t* reward, uint8_t* done, hipStream_t s,
+// Build ROM-homogeneous tiles on the device for the ids of one call.  The
+// counters were cleared and the claim tag advanced by k_step_begin.
+int build_tiles(vcs_ctx* c, Pipe& P, const int32_t* ids, uint32_t n, int32_t* reward, uint8_t* done, hipStream_t s,
                 uint32_t* grid) {
-    uint32_t* counts = c->d_counts;
-    uint32_t* offsets = c->d_counts + c->n_roms;
-    uint32_t* fill = c->d_counts + 2 * c->n_roms;
-    launch_fill_u32(counts, c->n_roms, 0, s);
-    launch_validate(ids, n, c->cfg.num_envs, c->d_env_rom, c->d_claim, c->tag++, counts, c->d_valid, c->d_info,
+    const uint32_t R = c->n_roms, w = c->launch.tile_envs;
+    uint32_t* counts = P.d_counts;
+    uint32_t* offsets = P.d_counts + R;
+    uint32_t* fill = P.d_counts + 2 * R;
+    launch_validate(ids, n, c->cfg.num_envs, c->d_env_rom, c->d_claim, P.d_tag, counts, P.d_valid, P.d_info,
                     reward, done, c->d_err, s);
-    launch_tile_layout(counts, c->n_roms, offsets, fill, c->d_tiles, c->d_n_tiles, s);
-    launch_tile_fill(ids, n, c->d_env_rom, c->d_valid, offsets, fill, c->d_tiles, s);
-    *grid = (n + kLanes - 1) / kLanes + c->n_roms;
+    launch_tile_layout(counts, R, w, offsets, fill, P.d_tiles, P.d_n_tiles, s);
+    launch_tile_fill(ids, n, c->d_env_rom, P.d_valid, w, offsets, fill, P.d_tiles, s);
+    *grid = (n + w - 1) / w + R;
     HIP_OK(hipGetLastError());
+    return VCS_OK;
+}
+
+// (Re)allocate the per-call tile buffers for the current ROM count and width.
+int ensure_tile_buffer(vcs_ctx* c) {
+    const uint32_t cap = (c->max_batch + c->launch.tile_envs - 1) / c->launch.tile_envs + c->n_roms;
+    bool have = c->tiles_cap >= cap;
+    for (auto& P : c->pipes) have = have && P.d_tiles;
+    if (have) return VCS_OK;
+    for (auto& P : c->pipes) {
+        dev_free(c, P.d_tiles, (size_t)c->tiles_cap * sizeof(Tile));
+        P.d_tiles = nullptr;
+    }
+    c->tiles_cap = 0;
+    for (auto& P : c->pipes) {
+        int rc = alloc_n(c, &P.d_tiles, cap, "tiles");
+        if (rc) return rc;
+    }
+    c->tiles_cap = cap;
+    return VCS_OK;
+}
+
+// Tiles over all envs, ROM by ROM, `tile_envs` envs each (env id = output position).
+int build_all_tiles(vcs_ctx* c) {
+    const uint32_t N = c->cfg.num_envs, R = c->n_roms, w = c->launch.tile_envs;
+    std::vector<Tile> tiles;
+    std::vector<std::vector<int32_t>> by_rom(R);
+    for (uint32_t e = 0; e < N; ++e) by_rom[c->h_env_rom[e]].push_back((int32_t)e);
+    for (uint32_t r = 0; r < R; ++r) {
+        for (size_t i = 0; i < by_rom[r].size(); i += w) {
+            Tile t;
+            std::memset(&t, 0xFF, sizeof(t));
+            t.rom = (int32_t)r;
+            t.count = (int32_t)std::min<size_t>(w, by_rom[r].size() - i);
+            for (int l = 0; l < t.count; ++l) t.env[l] = t.out[l] = by_rom[r][i + l];
+            tiles.push_back(t);
+        }
+    }
+    dev_free(c, c->d_tiles_all, (size_t)c->n_tiles_all * sizeof(Tile));
+    c->d_tiles_all = nullptr;
+    c->n_tiles_all = 0;
+    int rc = alloc_n(c, &c->d_tiles_all, tiles.size(), "tiles (all envs)");
+    if (rc) return rc;
+    c->n_tiles_all = (uint32_t)tiles.size();
+    HIP_OK(hipMemcpy(c->d_tiles_all, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->d_n_tiles_all, &c->n_tiles_all, 4, hipMemcpyHostToDevice));
+    return VCS_OK;
+}
+
+bool pow2_le64(uint32_t w) { return w >= 1 && w <= 64 && (w & (w - 1)) == 0; }
+
+int check_launch(const vcs_launch* l) {
+    if (!pow2_le64(l->tile_envs)) return fail(VCS_E_INVAL, "tile_envs must be a power of two in [1, 64]");
+    if (l->workers > (1u << 20)) return fail(VCS_E_INVAL, "workers must be <= 2^20");
+    const uint32_t b = l->render_block;
+    if (b != 64 && b != 128 && b != 256 && b != 512) return fail(VCS_E_INVAL, "render_block must be 64, 128, 256 or 512");
+    return VCS_OK;
+}
+
+// Enqueue one step on stream s with the scratch of pipeline `pipe` (the body
+// of vcs_step; arguments checked).
+int enqueue_step(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
+                 int32_t* reward, uint8_t* done, uint8_t* frames, hipStream_t s) {
+    Pipe& P = c->pipes[pipe];
+    const Tile* tiles = c->d_tiles_all;
+    const uint32_t* n_tiles = c->d_n_tiles_all;
+    uint32_t grid = c->n_tiles_all;
+    const bool listed = ids || n != c->cfg.num_envs;
+    if (listed) {
+        // counts, offsets, fill, instruction counters and queue; advance the tag
+        launch_step_begin(P.d_stepw, c->stepw_words, P.d_tag, s);
+        int rc = build_tiles(c, P, ids, n, reward, done, s, &grid);
+        if (rc) return rc;
+        tiles = P.d_tiles;
+        n_tiles = P.d_n_tiles;
+    } else {
+        launch_step_begin(P.d_stepw + c->instr_off, c->stepw_words - c->instr_off, nullptr, s);
+    }
+    InterpArgs ia{};
+    ia.tiles = tiles;
+    ia.n_tiles = n_tiles;
+    ia.envs = c->d_envs;
+    ia.roms = c->d_roms;
+    ia.schemes = c->d_schemes;
+    ia.pre = c->d_pre;
+    ia.actions = actions;
+    ia.nframes_per_out = nullptr;
+    ia.nframes = c->cfg.frameskip;
+    ia.render_all = c->cfg.render_mode == VCS_RENDER_ALL;
+    ia.log_enabled = (obs || frames) ? 1 : 0;
+    ia.early_stop = 1;
+    ia.sticky_thr = c->cfg.sticky_threshold;
+    ia.frameskip = c->cfg.frameskip;
+    ia.seed = c->cfg.seed;
+    ia.logs = P.d_logs;
+    ia.n_slots = c->n_slots;
+    ia.info = P.d_info;
+    ia.reward = reward;
+    ia.done = done;
+    ia.err_word = c->d_err;
+    ia.instr_total = P.d_instr;
+    ia.queue = nullptr;
+    if (c->launch.workers && c->launch.workers < grid) {
+        ia.queue = P.d_queue;
+        grid = c->launch.workers;
+    }
+    begin_timed(c, 0, s);
+    launch_interp(ia, grid, s);
+    end_timed(c, s);
+
+    RenderArgs ra{};
+    ra.logs = P.d_logs;
+    ra.n_slots = c->n_slots;
+    ra.info = P.d_info;
+    ra.frames = frames;
+    ra.obs = obs;
+    ra.gray = c->d_gray;
+    ra.n = n;
+    ra.force_obs = 0;
+    if (frames && c->n_slots > 2) {
+        begin_timed(c, 1, s);
+        launch_render_frames(ra, c->n_slots - 2, c->launch.render_block, s);
+        end_timed(c, s);
+    }
+    if (obs || frames) {
+        begin_timed(c, 2, s);
+        launch_render_obs(ra, c->launch.render_block, s);
+        end_timed(c, s);
+    }
+    ResetArgs rs{};
+    rs.envs = c->d_envs;
+    rs.ids = ids;
+    rs.n = n;
+    rs.num_envs = c->cfg.num_envs;
+    rs.info = P.d_info;
+    rs.valid = nullptr;
+    rs.cache_state = c->d_cache_state;
+    rs.cache_obs = c->d_cache_obs;
+    rs.K = c->cfg.reset_cache_k;
+    rs.seed = c->cfg.seed;
+    rs.obs = obs;
+    begin_timed(c, 3, s);
+    launch_reset(rs, s);
+    end_timed(c, s);
+    HIP_OK(hipGetLastError());
+    return VCS_OK;
+}
+
+int check_step_args(vcs_ctx* c, uint32_t n, const uint8_t* actions, const int32_t* reward, const uint8_t* done) {
+    if (!c) return fail(VCS_E_INVAL, "null context");
+    if (!c->assigned) return fail(VCS_E_STATE, "vcs_assign first");
+    if (n > c->max_batch) return fail(VCS_E_INVAL, "n exceeds max_batch");
+    if (n == 0) return VCS_OK;
+    if (!actions || !reward || !done) return fail(VCS_E_INVAL, "actions, reward and done are required");
     return VCS_OK;
 }
 
@@ -250,13 +421,17 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
     if (cfg->reset_cache_k == 0) return fail(VCS_E_INVAL, "reset_cache_k must be >= 1");
     if (cfg->max_batch > cfg->num_envs) return fail(VCS_E_INVAL, "max_batch > num_envs");
     if (1 + cfg->startup_frames + cfg->noop_max > 65535) return fail(VCS_E_INVAL, "cache build too long");
+    if (cfg->pipelines > 8) return fail(VCS_E_INVAL, "pipelines must be in [0, 8]");
     int ndev = 0;
     HIP_OK(hipGetDeviceCount(&ndev));
     if (cfg->device < 0 || cfg->device >= ndev) return fail(VCS_E_INVAL, "bad device ordinal");
     HIP_OK(hipSetDevice(cfg->device));
 
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, cfg->device));
     vcs_ctx* c = new vcs_ctx();
     c->cfg = *cfg;
+    c->n_cu = (uint32_t)prop.multiProcessorCount;
     c->max_batch = cfg->max_batch ? cfg->max_batch : cfg->num_envs;
     c->n_slots = cfg->render_mode == VCS_RENDER_ALL ? cfg->frameskip : 2;
     int rc = VCS_OK;
@@ -264,22 +439,28 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
     if (!rc) rc = alloc_n(c, &c->d_envs, cfg->num_envs, "env state");
     if (!rc) rc = alloc_n(c, &c->d_env_rom, cfg->num_envs, "env rom");
     if (!rc) rc = alloc_n(c, &c->d_claim, cfg->num_envs, "id claims");
-    if (!rc) rc = alloc_n(c, &c->d_logs, B * c->n_slots * kFrameLogBytes, "row logs");
-    if (!rc) rc = alloc_n(c, &c->d_info, B, "step info");
-    if (!rc) rc = alloc_n(c, &c->d_valid, B, "id validity");
     if (!rc) rc = alloc_n(c, &c->d_err, 2, "error word");
-    if (!rc) rc = alloc_n(c, &c->d_instr, 2, "instruction counters");
     if (!rc) rc = alloc_n(c, &c->d_gray, 128, "gray table");
-    if (!rc) rc = alloc_n(c, &c->d_n_tiles, 1, "tile count");
     if (!rc) rc = alloc_n(c, &c->d_n_tiles_all, 1, "tile count");
+    c->pipes.resize(cfg->pipelines ? cfg->pipelines : 1);
+    for (auto& P : c->pipes) {
+        if (!rc) rc = alloc_n(c, &P.d_logs, B * c->n_slots * kFrameLogBytes, "row logs");
+        if (!rc) rc = alloc_n(c, &P.d_info, B, "step info");
+        if (!rc) rc = alloc_n(c, &P.d_valid, B, "id validity");
+        if (!rc) rc = alloc_n(c, &P.d_tag, 1, "claim tag");
+        if (!rc) rc = alloc_n(c, &P.d_n_tiles, 1, "tile count");
+    }
     if (rc) {
         vcs_destroy(c);
         return rc;
     }
-    if (hipMemcpy(c->d_gray, cfg->gray_lut, 128, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->d_claim, 0xFF, (size_t)cfg->num_envs * 4) != hipSuccess ||
-        hipMemset(c->d_err, 0, 4) != hipSuccess || hipMemset(c->d_err + 1, 0xFF, 4) != hipSuccess ||
-        hipMemset(c->d_envs, 0, (size_t)cfg->num_envs * sizeof(DevEnv)) != hipSuccess) {
+    bool ok = hipMemcpy(c->d_gray, cfg->gray_lut, 128, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(c->d_claim, 0xFF, (size_t)cfg->num_envs * 4) == hipSuccess &&
+              hipMemset(c->d_err, 0, 4) == hipSuccess && hipMemset(c->d_err + 1, 0xFF, 4) == hipSuccess &&
+              hipMemset(c->d_envs, 0, (size_t)cfg->num_envs * sizeof(DevEnv)) == hipSuccess;
+    for (uint32_t p = 0; p < c->pipes.size() && ok; ++p)
+        ok = hipMemcpy(c->pipes[p].d_tag, &p, 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
         vcs_destroy(c);
         return fail(VCS_E_HIP, "initial device copies failed");
     }
@@ -309,23 +490,44 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
     dev_free(c, c->d_roms, (size_t)c->n_roms * kRomSlot);
+    dev_free(c, c->d_pre, (size_t)c->n_roms * kRomSlot * sizeof(uint2));
     dev_free(c, c->d_schemes, (size_t)c->n_roms * 4);
-    dev_free(c, c->d_counts, (size_t)c->n_roms * 12);
-    dev_free(c, c->d_tiles, (size_t)c->tiles_cap * sizeof(Tile));
-    c->d_roms = nullptr; c->d_schemes = nullptr; c->d_counts = nullptr; c->d_tiles = nullptr;
+    for (auto& P : c->pipes) {
+        dev_free(c, P.d_stepw, (size_t)c->stepw_words * 4);
+        dev_free(c, P.d_tiles, (size_t)c->tiles_cap * sizeof(Tile));
+        P.d_tiles = nullptr;
+        P.d_stepw = nullptr; P.d_counts = nullptr; P.d_instr = nullptr; P.d_queue = nullptr;
+    }
+    c->d_roms = nullptr; c->d_pre = nullptr; c->d_schemes = nullptr;
+    c->stepw_words = 0;
+    c->tiles_cap = 0;
+    ++c->generation;
     c->assigned = false;
     c->n_roms = n_roms;
     c->h_roms.assign((size_t)n_roms * kRomSlot, 0);
     c->h_schemes.assign(scheme, scheme + n_roms);
     for (uint32_t r = 0; r < n_roms; ++r) std::memcpy(c->h_roms.data() + (size_t)r * kRomSlot, rom_host[r], rom_bytes[r]);
     int rc = alloc_n(c, &c->d_roms, (size_t)n_roms * kRomSlot, "ROMs");
+    if (!rc) rc = alloc_n(c, &c->d_pre, (size_t)n_roms * kRomSlot, "predecoded ROMs");
     if (!rc) rc = alloc_n(c, &c->d_schemes, n_roms, "ROM schemes");
-    if (!rc) rc = alloc_n(c, &c->d_counts, (size_t)n_roms * 3, "tile counters");
-    c->tiles_cap = (c->max_batch + kLanes - 1) / kLanes + n_roms;
-    if (!rc) rc = alloc_n(c, &c->d_tiles, c->tiles_cap, "tiles");
+    const uint32_t instr_off = (3 * n_roms + 1) & ~1u;   // 8-byte aligned counters
+    c->stepw_words = instr_off + 5;
+    c->instr_off = instr_off;
+    for (auto& P : c->pipes) {
+        if (!rc) rc = alloc_n(c, &P.d_stepw, c->stepw_words, "per-call counters");
+        if (rc) break;
+        P.d_counts = P.d_stepw;
+        P.d_instr = reinterpret_cast<unsigned long long*>(P.d_stepw + instr_off);
+        P.d_queue = P.d_stepw + instr_off + 4;
+    }
+    if (!rc) rc = ensure_tile_buffer(c);
     if (rc) return rc;
+    for (auto& P : c->pipes) HIP_OK(hipMemset(P.d_stepw, 0, (size_t)c->stepw_words * 4));
     HIP_OK(hipMemcpy(c->d_roms, c->h_roms.data(), c->h_roms.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->d_schemes, c->h_schemes.data(), n_roms * 4, hipMemcpyHostToDevice));
+    launch_predecode(c->d_roms, n_roms, c->d_pre, nullptr);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipDeviceSynchronize());
     return VCS_OK;
 }
 
@@ -339,32 +541,9 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     c->h_env_rom.assign(env_rom_host, env_rom_host + N);
     HIP_OK(hipMemcpy(c->d_env_rom, env_rom_host, (size_t)N * 2, hipMemcpyHostToDevice));
 
-    // tiles over all envs, ROM by ROM
-    std::vector<Tile> tiles;
-    {
-        std::vector<std::vector<int32_t>> by_rom(R);
-        for (uint32_t e = 0; e < N; ++e) by_rom[env_rom_host[e]].push_back((int32_t)e);
-        for (uint32_t r = 0; r < R; ++r) {
-            for (size_t i = 0; i < by_rom[r].size(); i += kLanes) {
-                Tile t;
-                std::memset(&t, 0xFF, sizeof(t));
-                t.rom = (int32_t)r;
-                t.count = (int32_t)std::min<size_t>(kLanes, by_rom[r].size() - i);
-                for (int l = 0; l < t.count; ++l) {
-                    t.env[l] = by_rom[r][i + l];
-                    t.out[l] = by_rom[r][i + l];
-                }
-                tiles.push_back(t);
-            }
-        }
-    }
-    dev_free(c, c->d_tiles_all, (size_t)c->n_tiles_all * sizeof(Tile));
-    c->d_tiles_all = nullptr;
-    c->n_tiles_all = (uint32_t)tiles.size();
-    int rc = alloc_n(c, &c->d_tiles_all, tiles.size(), "tiles (all envs)");
+    int rc = build_all_tiles(c);
     if (rc) return rc;
-    HIP_OK(hipMemcpy(c->d_tiles_all, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(c->d_n_tiles_all, &c->n_tiles_all, 4, hipMemcpyHostToDevice));
+    ++c->generation;
 
     // ---- reset cache: K entries per ROM
     const uint32_t M = R * K;
@@ -430,6 +609,7 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     ia.envs = c->d_cache_state;
     ia.roms = c->d_roms;
     ia.schemes = c->d_schemes;
+    ia.pre = c->d_pre;
     ia.actions = nullptr;
     ia.nframes_per_out = d_nfr;
     ia.nframes = 0;
@@ -456,7 +636,7 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     ra.gray = c->d_gray;
     ra.n = M;
     ra.force_obs = 1;
-    launch_render_obs(ra, nullptr);
+    launch_render_obs(ra, 256, nullptr);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipDeviceSynchronize();
     std::vector<StepInfo> cinfo(M);
@@ -520,10 +700,11 @@ int vcs_reset(vcs_ctx* c, const int32_t* ids, uint32_t n, uint8_t* obs, void* st
     rs.info = nullptr;
     rs.valid = nullptr;
     if (ids) {
-        launch_fill_u32(c->d_counts, c->n_roms, 0, s);
-        launch_validate(ids, n, c->cfg.num_envs, c->d_env_rom, c->d_claim, c->tag++, c->d_counts, c->d_valid,
+        Pipe& P = c->pipes[0];
+        launch_step_begin(P.d_counts, c->n_roms, P.d_tag, s);
+        launch_validate(ids, n, c->cfg.num_envs, c->d_env_rom, c->d_claim, P.d_tag, P.d_counts, P.d_valid,
                         nullptr, nullptr, nullptr, c->d_err, s);
-        rs.valid = c->d_valid;
+        rs.valid = P.d_valid;
     }
     rs.cache_state = c->d_cache_state;
     rs.cache_obs = c->d_cache_obs;
@@ -539,84 +720,17 @@ int vcs_reset(vcs_ctx* c, const int32_t* ids, uint32_t n, uint8_t* obs, void* st
 
 int vcs_step(vcs_ctx* c, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs, int32_t* reward,
              uint8_t* done, uint8_t* frames, void* stream) {
-    if (!c) return fail(VCS_E_INVAL, "null context");
-    if (!c->assigned) return fail(VCS_E_STATE, "vcs_assign first");
-    if (n > c->max_batch) return fail(VCS_E_INVAL, "n exceeds max_batch");
-    if (n == 0) return VCS_OK;
-    if (!actions || !reward || !done) return fail(VCS_E_INVAL, "actions, reward and done are required");
-    hipStream_t s = (hipStream_t)stream;
-    const Tile* tiles = c->d_tiles_all;
-    const uint32_t* n_tiles = c->d_n_tiles_all;
-    uint32_t grid = c->n_tiles_all;
-    if (ids || n != c->cfg.num_envs) {
-        int rc = build_tiles(c, ids, n, reward, done, s, &grid);
-        if (rc) return rc;
-        tiles = c->d_tiles;
-        n_tiles = c->d_n_tiles;
-    }
-    launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_instr), 4, 0, s);
-    InterpArgs ia{};
-    ia.tiles = tiles;
-    ia.n_tiles = n_tiles;
-    ia.envs = c->d_envs;
-    ia.roms = c->d_roms;
-    ia.schemes = c->d_schemes;
-    ia.actions = actions;
-    ia.nframes_per_out = nullptr;
-    ia.nframes = c->cfg.frameskip;
-    ia.render_all = c->cfg.render_mode == VCS_RENDER_ALL;
-    ia.log_enabled = (obs || frames) ? 1 : 0;
-    ia.early_stop = 1;
-    ia.sticky_thr = c->cfg.sticky_threshold;
-    ia.frameskip = c->cfg.frameskip;
-    ia.seed = c->cfg.seed;
-    ia.logs = c->d_logs;
-    ia.n_slots = c->n_slots;
-    ia.info = c->d_info;
-    ia.reward = reward;
-    ia.done = done;
-    ia.err_word = c->d_err;
-    ia.instr_total = c->d_instr;
-    begin_timed(c, 0, s);
-    launch_interp(ia, grid, s);
-    end_timed(c, s);
+    int rc = check_step_args(c, n, actions, reward, done);
+    if (rc || n == 0) return rc;
+    return enqueue_step(c, 0, ids, actions, n, obs, reward, done, frames, (hipStream_t)stream);
+}
 
-    RenderArgs ra{};
-    ra.logs = c->d_logs;
-    ra.n_slots = c->n_slots;
-    ra.info = c->d_info;
-    ra.frames = frames;
-    ra.obs = obs;
-    ra.gray = c->d_gray;
-    ra.n = n;
-    ra.force_obs = 0;
-    if (frames && c->n_slots > 2) {
-        begin_timed(c, 1, s);
-        launch_render_frames(ra, c->n_slots - 2, s);
-        end_timed(c, s);
-    }
-    if (obs || frames) {
-        begin_timed(c, 2, s);
-        launch_render_obs(ra, s);
-        end_timed(c, s);
-    }
-    ResetArgs rs{};
-    rs.envs = c->d_envs;
-    rs.ids = ids;
-    rs.n = n;
-    rs.num_envs = c->cfg.num_envs;
-    rs.info = c->d_info;
-    rs.valid = nullptr;
-    rs.cache_state = c->d_cache_state;
-    rs.cache_obs = c->d_cache_obs;
-    rs.K = c->cfg.reset_cache_k;
-    rs.seed = c->cfg.seed;
-    rs.obs = obs;
-    begin_timed(c, 3, s);
-    launch_reset(rs, s);
-    end_timed(c, s);
-    HIP_OK(hipGetLastError());
-    return VCS_OK;
+int vcs_step_pipe(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
+                  int32_t* reward, uint8_t* done, uint8_t* frames, void* stream) {
+    int rc = check_step_args(c, n, actions, reward, done);
+    if (rc || n == 0) return rc;
+    if (pipe >= c->pipes.size()) return fail(VCS_E_INVAL, "no such pipeline");
+    return enqueue_step(c, pipe, ids, actions, n, obs, reward, done, frames, (hipStream_t)stream);
 }
 
 int vcs_get_state(vcs_ctx* c, uint32_t env, uint8_t* out) {
@@ -679,7 +793,7 @@ int vcs_last_step_instructions(vcs_ctx* c, uint64_t* out) {
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
     unsigned long long v = 0;
-    HIP_OK(hipMemcpy(&v, c->d_instr, 8, hipMemcpyDeviceToHost));
+    if (c->pipes[0].d_instr) HIP_OK(hipMemcpy(&v, c->pipes[0].d_instr, 8, hipMemcpyDeviceToHost));
     *out = v;
     return VCS_OK;
 }
@@ -689,7 +803,7 @@ int vcs_last_step_stats(vcs_ctx* c, uint64_t* out2) {
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
     unsigned long long v[2] = {0, 0};
-    HIP_OK(hipMemcpy(v, c->d_instr, 16, hipMemcpyDeviceToHost));
+    if (c->pipes[0].d_instr) HIP_OK(hipMemcpy(v, c->pipes[0].d_instr, 16, hipMemcpyDeviceToHost));
     out2[0] = v[0];
     out2[1] = v[1];
     return VCS_OK;
@@ -717,6 +831,233 @@ int vcs_kernel_time(vcs_ctx* c, int which, double* mean_ms, uint32_t* launches) 
     *mean_ms = cnt ? total / cnt : 0.0;
     *launches = cnt;
     return VCS_OK;
+}
+
+int vcs_set_launch(vcs_ctx* c, const vcs_launch* l) {
+    if (!c || !l) return fail(VCS_E_INVAL, "null argument");
+    int rc = check_launch(l);
+    if (rc) return rc;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    HIP_OK(hipDeviceSynchronize());
+    const vcs_launch old = c->launch;
+    c->launch = *l;
+    if (c->n_roms) {
+        rc = ensure_tile_buffer(c);
+        if (!rc && c->assigned && l->tile_envs != old.tile_envs) rc = build_all_tiles(c);
+        if (rc) {
+            c->launch = old;
+            return rc;
+        }
+    }
+    ++c->generation;
+    return VCS_OK;
+}
+
+int vcs_get_launch(vcs_ctx* c, vcs_launch* out) {
+    if (!c || !out) return fail(VCS_E_INVAL, "null argument");
+    *out = c->launch;
+    return VCS_OK;
+}
+
+int vcs_autotune(vcs_ctx* c, uint32_t n, uint32_t steps, int want_frames, int want_obs, vcs_launch* best_out,
+                 double* best_ms_out) {
+    if (!c) return fail(VCS_E_INVAL, "null context");
+    if (!c->assigned) return fail(VCS_E_STATE, "vcs_assign first");
+    if (n == 0) n = c->max_batch;
+    if (n > c->max_batch) return fail(VCS_E_INVAL, "n exceeds max_batch");
+    if (steps == 0 || steps > 1000) return fail(VCS_E_INVAL, "steps must be in [1, 1000]");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    HIP_OK(hipDeviceSynchronize());
+    const uint32_t N = c->cfg.num_envs;
+    const vcs_launch start = c->launch;
+
+    // temporaries: env-state snapshot, outputs, actions
+    DevEnv* d_backup = nullptr;
+    uint8_t *d_obs = nullptr, *d_done = nullptr, *d_frames = nullptr, *d_act = nullptr;
+    int32_t* d_rew = nullptr;
+    const size_t frame_bytes = (size_t)n * c->n_slots * kFrameBytes;
+    int rc = alloc_n(c, &d_backup, N, "autotune state snapshot");
+    if (!rc) rc = alloc_n(c, &d_rew, n, "autotune reward");
+    if (!rc) rc = alloc_n(c, &d_done, n, "autotune done");
+    if (!rc) rc = alloc_n(c, &d_act, (size_t)(steps + 1) * n, "autotune actions");
+    if (!rc && want_obs) rc = alloc_n(c, &d_obs, (size_t)n * kObsBytes, "autotune obs");
+    if (!rc && want_frames) rc = alloc_n(c, &d_frames, frame_bytes, "autotune frames");
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    uint32_t err_host[2] = {0, 0xFFFFFFFFu};
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+        dev_free(c, d_backup, (size_t)N * sizeof(DevEnv));
+        dev_free(c, d_rew, (size_t)n * 4);
+        dev_free(c, d_done, n);
+        dev_free(c, d_act, (size_t)(steps + 1) * n);
+        dev_free(c, d_obs, (size_t)n * kObsBytes);
+        dev_free(c, d_frames, frame_bytes);
+    };
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    {
+        std::vector<uint8_t> act((size_t)(steps + 1) * n);
+        uint64_t z = c->cfg.seed ^ 0x5EED5EEDull;
+        for (auto& a : act) a = (uint8_t)((mix64(z += kGamma) >> 32) % VCS_N_ACTIONS);
+        if (hipMemcpy(d_act, act.data(), act.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_backup, c->d_envs, (size_t)N * sizeof(DevEnv), hipMemcpyDeviceToDevice) != hipSuccess ||
+            hipMemcpy(err_host, c->d_err, 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess) {
+            cleanup();
+            return fail(VCS_E_HIP, "autotune set-up failed");
+        }
+    }
+    const bool timing = c->timing;
+    c->timing = false;
+    // time one candidate: same start states, 1 untimed step then `steps` timed steps
+    auto measure = [&](const vcs_launch& l, double* ms) -> int {
+        c->launch = l;
+        int r = ensure_tile_buffer(c);
+        if (!r) r = build_all_tiles(c);
+        if (r) return r;
+        HIP_OK(hipMemcpyAsync(c->d_envs, d_backup, (size_t)N * sizeof(DevEnv), hipMemcpyDeviceToDevice, s));
+        for (uint32_t k = 0; k <= steps; ++k) {
+            if (k == 1) HIP_OK(hipEventRecord(e0, s));
+            r = enqueue_step(c, 0, nullptr, d_act + (size_t)k * n, n, d_obs, d_rew, d_done, d_frames, s);
+            if (r) return r;
+        }
+        HIP_OK(hipEventRecord(e1, s));
+        HIP_OK(hipEventSynchronize(e1));
+        float t = 0;
+        HIP_OK(hipEventElapsedTime(&t, e0, e1));
+        *ms = t / steps;
+        return VCS_OK;
+    };
+    vcs_launch best = start;
+    best.workers = 0;
+    double best_ms = 1e30;
+    auto consider = [&](const vcs_launch& l) -> int {
+        double ms = 0;
+        int r = measure(l, &ms);
+        if (r) return r;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = l;
+        }
+        return VCS_OK;
+    };
+    // 1) envs per wave (one workgroup per tile): widths that keep <= 8 waves per CU
+    for (uint32_t w = 64; w >= 1 && !rc; w >>= 1) {
+        const uint64_t tiles = (n + w - 1) / w + c->n_roms;
+        if (w != 64 && tiles > 8ull * c->n_cu) break;
+        vcs_launch l{w, 0, start.render_block};
+        rc = consider(l);
+    }
+    // 2) persistent interpreter with 1, 2, 4 or 8 workgroups per CU
+    const uint64_t tiles_best = (n + best.tile_envs - 1) / best.tile_envs + c->n_roms;
+    for (uint32_t k = 1; k <= 8 && !rc; k <<= 1) {
+        if ((uint64_t)k * c->n_cu >= tiles_best) break;
+        vcs_launch l = best;
+        l.workers = k * c->n_cu;
+        rc = consider(l);
+    }
+    // 3) render workgroup size
+    if (!rc && (want_frames || want_obs)) {
+        const vcs_launch b = best;
+        for (uint32_t blk : {128u, 256u, 512u}) {
+            if (blk == b.render_block || rc) continue;
+            vcs_launch l = b;
+            l.render_block = blk;
+            rc = consider(l);
+        }
+    }
+    c->timing = timing;
+    // restore the env states and error word whatever happened, keep the best shape
+    hipError_t he = hipStreamSynchronize(s);
+    if (he == hipSuccess) he = hipMemcpy(c->d_envs, d_backup, (size_t)N * sizeof(DevEnv), hipMemcpyDeviceToDevice);
+    if (he == hipSuccess) he = hipMemcpy(c->d_err, err_host, 8, hipMemcpyHostToDevice);
+    for (auto& P : c->pipes)
+        if (he == hipSuccess) he = hipMemset(P.d_stepw, 0, (size_t)c->stepw_words * 4);
+    c->launch = rc ? start : best;
+    int rc2 = ensure_tile_buffer(c);
+    if (!rc2) rc2 = build_all_tiles(c);
+    ++c->generation;
+    cleanup();
+    if (rc) return rc;
+    if (he != hipSuccess) return fail(VCS_E_HIP, std::string("autotune restore failed: ") + hipGetErrorString(he));
+    if (rc2) return rc2;
+    if (best_out) *best_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
+    return VCS_OK;
+}
+
+struct vcs_graph {
+    vcs_ctx* c = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t generation = 0;
+};
+
+int vcs_graph_create(vcs_ctx* c, const int32_t* ids, const uint8_t* actions, uint32_t n, uint32_t steps,
+                     uint8_t* obs, int32_t* reward, uint8_t* done, uint8_t* frames, vcs_graph** out) {
+    if (!out) return fail(VCS_E_INVAL, "null argument");
+    *out = nullptr;
+    int rc = check_step_args(c, n, actions, reward, done);
+    if (rc) return rc;
+    if (n == 0) return fail(VCS_E_INVAL, "a graph needs n >= 1");
+    if (steps == 0 || steps > 64) return fail(VCS_E_INVAL, "steps must be in [1, 64]");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    hipStream_t s = nullptr;
+    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipError_t he = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return fail(VCS_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(he));
+    }
+    const bool timing = c->timing;
+    c->timing = false;
+    for (uint32_t j = 0; j < steps && !rc; ++j) {
+        rc = enqueue_step(c, 0, ids, actions + (size_t)j * n, n, obs ? obs + (size_t)j * n * kObsBytes : nullptr,
+                          reward + (size_t)j * n, done + (size_t)j * n,
+                          frames ? frames + (size_t)j * n * c->n_slots * kFrameBytes : nullptr, s);
+    }
+    c->timing = timing;
+    hipGraph_t g = nullptr;
+    he = hipStreamEndCapture(s, &g);
+    (void)hipStreamDestroy(s);
+    if (rc || he != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : fail(VCS_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));
+    }
+    hipGraphExec_t x = nullptr;
+    he = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(VCS_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+    }
+    vcs_graph* G = new vcs_graph();
+    G->c = c;
+    G->graph = g;
+    G->exec = x;
+    G->generation = c->generation;
+    *out = G;
+    return VCS_OK;
+}
+
+int vcs_graph_launch(vcs_graph* g, void* stream) {
+    if (!g) return fail(VCS_E_INVAL, "null graph");
+    if (g->generation != g->c->generation)
+        return fail(VCS_E_STATE, "the context's ROMs, envs or launch shape changed since the graph was captured");
+    HIP_OK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return VCS_OK;
+}
+
+void vcs_graph_destroy(vcs_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 }  // extern "C"

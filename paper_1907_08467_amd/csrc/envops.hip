@@ -15,14 +15,26 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Start of a step or reset call: clear the per-call counters and, when the
+// call validates ids, advance its pipeline's claim tag by 8 (tags of the up
+// to 8 pipelines stay distinct: tag mod 8 is the pipeline).  Kernels only
+// (no memset), so a captured call replays correctly.
+__global__ void k_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag) {
+    for (uint32_t i = threadIdx.x; i < n_zero; i += blockDim.x) zero[i] = 0;
+    if (tag && threadIdx.x == 0) *tag = *tag + 8;
+}
+
 // Validate the ids of one call and count the valid ones per ROM.  An id out
 // of range, or seen twice in the call, is marked invalid: its output gets
-// done = 1 with the BAD_ID error and it is never dereferenced further.
+// done = 1 with the BAD_ID error and it is never dereferenced further.  An id
+// is claimed by swapping the call's tag into claim[id]: a second position
+// with the same id sees the tag already there.
 __global__ void k_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, const uint16_t* env_rom,
-                           uint32_t* claim, uint32_t tag, uint32_t* counts, uint8_t* valid,
+                           uint32_t* claim, const uint32_t* tag_ptr, uint32_t* counts, uint8_t* valid,
                            StepInfo* info, int32_t* reward, uint8_t* done, uint32_t* err_word) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const uint32_t tag = *tag_ptr;
     const int32_t e = ids ? ids[i] : (int32_t)i;
     bool ok = e >= 0 && (uint32_t)e < num_envs;
     if (ok) ok = atomicExch(&claim[e], tag) != tag;
@@ -40,9 +52,10 @@ __global__ void k_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, co
     }
 }
 
-// Tile offsets per ROM (one thread; the number of ROMs is small).
-__global__ void k_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t* offsets, uint32_t* fill,
-                              Tile* tiles, uint32_t* n_tiles) {
+// Tile offsets per ROM (one thread; the number of ROMs is small).  Tiles
+// hold `width` envs (the last tile of a ROM fewer).
+__global__ void k_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t width, uint32_t* offsets,
+                              uint32_t* fill, Tile* tiles, uint32_t* n_tiles) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     uint32_t t = 0;
     for (uint32_t r = 0; r < n_roms; ++r) {
@@ -50,7 +63,7 @@ __global__ void k_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t*
         fill[r] = 0;
         uint32_t c = counts[r];
         while (c > 0) {
-            const uint32_t take = c > (uint32_t)kLanes ? (uint32_t)kLanes : c;
+            const uint32_t take = c > width ? width : c;
             tiles[t].rom = (int32_t)r;
             tiles[t].count = (int32_t)take;
             ++t;
@@ -61,15 +74,15 @@ __global__ void k_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t*
 }
 
 __global__ void k_tile_fill(const int32_t* ids, uint32_t n, const uint16_t* env_rom, const uint8_t* valid,
-                            const uint32_t* offsets, uint32_t* fill, Tile* tiles) {
+                            uint32_t width, const uint32_t* offsets, uint32_t* fill, Tile* tiles) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !valid[i]) return;
     const int32_t e = ids ? ids[i] : (int32_t)i;
     const uint32_t r = env_rom[e];
     const uint32_t s = atomicAdd(&fill[r], 1u);
-    Tile& T = tiles[offsets[r] + s / kLanes];
-    T.env[s % kLanes] = e;
-    T.out[s % kLanes] = (int32_t)i;
+    Tile& T = tiles[offsets[r] + s / width];
+    T.env[s % width] = e;
+    T.out[s % width] = (int32_t)i;
 }
 
 
@@ -124,20 +137,24 @@ void launch_reset(const ResetArgs& a, hipStream_t s) {
 void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
 }
+void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, zero, n_zero, tag);
+}
 void launch_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, const uint16_t* env_rom,
-                     uint32_t* claim, uint32_t tag, uint32_t* counts, uint8_t* valid, StepInfo* info,
+                     uint32_t* claim, const uint32_t* tag, uint32_t* counts, uint8_t* valid, StepInfo* info,
                      int32_t* reward, uint8_t* done, uint32_t* err_word, hipStream_t s) {
     hipLaunchKernelGGL(k_validate, dim3((n + 255) / 256), dim3(256), 0, s, ids, n, num_envs, env_rom, claim,
                        tag, counts, valid, info, reward, done, err_word);
 }
-void launch_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t* offsets, uint32_t* fill,
-                        Tile* tiles, uint32_t* n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_layout, dim3(1), dim3(64), 0, s, counts, n_roms, offsets, fill, tiles, n_tiles);
+void launch_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t width, uint32_t* offsets,
+                        uint32_t* fill, Tile* tiles, uint32_t* n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_layout, dim3(1), dim3(64), 0, s, counts, n_roms, width, offsets, fill, tiles,
+                       n_tiles);
 }
 void launch_tile_fill(const int32_t* ids, uint32_t n, const uint16_t* env_rom, const uint8_t* valid,
-                      const uint32_t* offsets, uint32_t* fill, Tile* tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_fill, dim3((n + 255) / 256), dim3(256), 0, s, ids, n, env_rom, valid, offsets,
-                       fill, tiles);
+                      uint32_t width, const uint32_t* offsets, uint32_t* fill, Tile* tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_fill, dim3((n + 255) / 256), dim3(256), 0, s, ids, n, env_rom, valid, width,
+                       offsets, fill, tiles);
 }
 
 }  // namespace vcs

@@ -594,68 +594,374 @@ __device__ __forceinline__ void apply_queue(Cpu& c, const Wave& W, uint32_t t) {
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Wave-uniform execution.  Precondition: every lane in exec has the same pc,
-// bank, cycle and frame line.  Those stay scalar here (fetch, decode,
-// addressing and timing run on the scalar unit; the compiler sees them as
-// uniform); only data (A, X, Y, P, SP, RAM, TIA registers) is per lane.  The
-// block returns when the lanes stop agreeing (a branch, a page-crossing
-// penalty or a stack target that differs, a frame that ends in some lanes
-// only), when a frame ends, or at a fetch outside the cartridge; `c` then
-// holds every lane's state.
-__device__ __forceinline__ void run_uniform(Cpu& c, const Wave& W, const uint32_t* s_rom, bool& ended,
-                                            uint32_t& end_t) {
-    Cpu u = c;
-    u.pc = rfl(c.pc);
-    u.bank = rfl(c.bank);
-    u.cyc = rfl(c.cyc);
-    u.fl = rfl(c.fl);
-    u.cap = rfl(c.cap);
+// ------------------------------------------------------- wave-uniform path
+//
+// When every running lane of the wave is at the same PC, bank, cycle, frame
+// line and row-log position, those stay in scalar registers: one scalar load
+// of the predecoded ROM gives opcode, operands and decode word, addressing
+// and timing run on the scalar unit, and only the data (A, X, Y, P, SP, RAM,
+// TIA registers, log stores) is per lane.  Branches whose outcome differs,
+// page-crossing penalties or stack targets that differ, and frames that end
+// in some lanes only hand the wave back to the per-lane path; so do the
+// instructions this path does not cover (indirect modes, JMP (ind), RTI, BRK,
+// indexed accesses outside RAM/cartridge), which the per-lane path executes.
+struct Fast {
+    uint32_t pc, bank, cyc, cap, orow, ocnt;
+    int32_t fl;
+    bool logon;
+};
+
+__device__ __forceinline__ bool all_lanes(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
+
+// TIA write of per-lane `v` to scalar register `reg` at scalar cycle t.
+// Returns the per-lane "VSYNC turned on" flag; sets `wsync`.
+__device__ __forceinline__ bool fast_tia(Cpu& c, const Wave& W, Fast& F, uint32_t reg, uint32_t v, uint32_t t,
+                                         bool& wsync) {
+    uint8_t* R = W.tia + c.tia_off;
+    switch (reg) {
+    case 0x00: {
+        const bool on = (v & 2) && !(c.vsync & 2);
+        c.vsync = v;
+        return on;
+    }
+    case 0x02: wsync = true; return false;
+    case 0x20: c.hmp0 = v; return false;
+    case 0x21: c.hmp1 = v; return false;
+    case 0x2B: c.hmp0 = 0; c.hmp1 = 0; return false;
+    default: break;
+    }
+    uint32_t code;
+    uint32_t v0 = v, v1 = 0;
+    const uint32_t ln = (t + 1) / 76;
+    const uint32_t h = 3 * (t + 1 - 76 * ln);
+    if (reg >= 0x06 && reg <= 0x0F) code = reg - 0x06;
+    else if (reg == 0x01) code = R_VBLANK;
+    else if (reg == 0x1B) code = R_GRP0;
+    else if (reg == 0x1C) code = R_GRP1;
+    else if (reg == 0x10 || reg == 0x11) {
+        code = reg == 0x10 ? R_P0X : R_P1X;
+        v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
+    } else if (reg == 0x2A) {
+        code = R_HMOVE;
+        const int32_t d0 = sext8(c.hmp0 & 0xF0) >> 4, d1 = sext8(c.hmp1 & 0xF0) >> 4;
+        v0 = (uint32_t)(((int32_t)R[R_P0X] - d0 + 160) % 160);
+        v1 = (uint32_t)(((int32_t)R[R_P1X] - d1 + 160) % 160);
+    } else {
+        return false;
+    }
+    if (F.logon) {
+        const int32_t row = (int32_t)ln - F.fl - kFirstRow;
+        int32_t target = h >= 68 ? row : row - 1;
+        if (target > kRows - 1) target = kRows - 1;
+        while ((int32_t)F.orow <= target) {    // F.orow holds the open row + 1 (0 = none)
+            if (F.orow > 0 && F.ocnt) c.log[(F.orow - 1) * kRowBytes + 15] = (uint8_t)F.ocnt;
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(R);
+            *reinterpret_cast<uint4*>(c.log + F.orow * kRowBytes) =
+                make_uint4(src[0], src[1], src[2], src[3] & 0x00FFFFFFu);
+            F.orow++;
+            F.ocnt = 0;
+        }
+        if (h >= 68 && row >= 0 && row < kRows) {
+            if (F.ocnt >= (uint32_t)kRowEntries) {
+                c.err |= ERR_LOG;
+            } else {
+                *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * F.ocnt) =
+                    (h - 68) | (code << 8) | (v0 << 16) | (v1 << 24);
+                F.ocnt++;
+            }
+        }
+    }
+    if (code == R_HMOVE) {
+        R[R_P0X] = (uint8_t)v0;
+        R[R_P1X] = (uint8_t)v1;
+    } else {
+        R[code] = (uint8_t)v0;
+    }
+    return false;
+}
+
+// Read of scalar address a (13 bits) at scalar cycle t.
+__device__ __forceinline__ uint32_t fast_rd(Cpu& c, const Wave& W, Fast& F, uint32_t a, uint32_t t) {
+    if (a & 0x1000) {
+        if (W.f8) {
+            if ((a & 0xFFF) == 0xFF8) F.bank = 0;
+            else if ((a & 0xFFF) == 0xFF9) F.bank = 1;
+        }
+        return W.rom[(F.bank << 12) | (a & 0xFFF)];
+    }
+    if (!(a & 0x80)) {
+        const uint32_t r = a & 0x0F;
+        return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);
+    }
+    if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
+    return riot_read(c, W, a, t);
+}
+
+// Write of per-lane v to scalar address a at scalar cycle t.
+__device__ __forceinline__ bool fast_wr(Cpu& c, const Wave& W, Fast& F, uint32_t a, uint32_t v, uint32_t t,
+                                        bool& wsync) {
+    if (a & 0x1000) {
+        if (W.f8) {
+            if ((a & 0xFFF) == 0xFF8) F.bank = 0;
+            else if ((a & 0xFFF) == 0xFF9) F.bank = 1;
+        }
+        return false;
+    }
+    if (!(a & 0x80)) return fast_tia(c, W, F, a & 0x3F, v & 0xFF, t, wsync);
+    if (!(a & 0x200)) {
+        W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
+        return false;
+    }
+    if ((a & 0x14) == 0x14) {
+        c.tv = v & 0xFF;
+        c.tshift = (0x0A060300u >> (8 * (a & 3))) & 0xFF;
+        c.tbase = (int64_t)(c.base + t) + 1;
+    }
+    return false;
+}
+
+// Per-lane ALU part of the read-class operations (operand v).
+__device__ __forceinline__ void fast_alu(Cpu& c, uint32_t mn, uint32_t v) {
+    switch (mn) {
+    case LDA: c.a = v; c.p = nz(c.p, v); break;
+    case LDX: c.x = v; c.p = nz(c.p, v); break;
+    case LDY: c.y = v; c.p = nz(c.p, v); break;
+    case ADC: do_adc(c, v); break;
+    case SBC: do_sbc(c, v); break;
+    case AND: c.a &= v; c.p = nz(c.p, c.a); break;
+    case ORA: c.a |= v; c.p = nz(c.p, c.a); break;
+    case EOR: c.a ^= v; c.p = nz(c.p, c.a); break;
+    case CMP: do_cmp(c, c.a, v); break;
+    case CPX: do_cmp(c, c.x, v); break;
+    case CPY: do_cmp(c, c.y, v); break;
+    default: c.p = (c.p & ~(FN | FV | FZ)) | (v & (FN | FV)) | ((c.a & v) == 0 ? FZ : 0); break;   // BIT
+    }
+}
+
+__device__ __forceinline__ uint32_t fast_rmw(Cpu& c, uint32_t mn, uint32_t x) {
+    const uint32_t ci = c.p & FC;
+    uint32_t r, co = ci;
+    if (mn == ASL) { r = (x << 1) & 0xFF; co = x >> 7; }
+    else if (mn == LSR) { r = x >> 1; co = x & 1; }
+    else if (mn == ROL) { r = ((x << 1) | ci) & 0xFF; co = x >> 7; }
+    else if (mn == ROR) { r = (x >> 1) | (ci << 7); co = x & 1; }
+    else if (mn == INC) { r = (x + 1) & 0xFF; }
+    else { r = (x - 1) & 0xFF; }
+    c.p = nz((c.p & ~FC) | co, r);
+    return r;
+}
+
+__device__ __forceinline__ bool is_read_op(uint32_t mn) {
+    return mn == LDA || mn == LDX || mn == LDY || mn == ADC || mn == SBC || mn == AND || mn == ORA || mn == EOR ||
+           mn == CMP || mn == CPX || mn == CPY || mn == BIT;
+}
+__device__ __forceinline__ bool is_rmw_op(uint32_t mn) {
+    return mn == ASL || mn == LSR || mn == ROL || mn == ROR || mn == INC || mn == DEC;
+}
+
+// Runs instructions for the lanes in exec (which agree on the control
+// state) until they split or a frame ends.  On return `c` holds every
+// lane's state; `ended`/`end_t` mark lanes whose frame ended.
+__device__ __forceinline__ void run_fast(Cpu& c, const Wave& W, const uint2* pre, bool& ended, uint32_t& end_t) {
+    Fast F;
+    F.pc = rfl(c.pc);
+    F.bank = rfl(c.bank);
+    F.cyc = rfl(c.cyc);
+    F.cap = rfl(c.cap);
+    F.fl = rfl(c.fl);
+    F.orow = (uint32_t)(rfl(c.open_row) + 1);
+    F.ocnt = rfl(c.open_cnt);
+    F.logon = rfl(c.log != nullptr ? 1u : 0u) != 0;
+    bool lane_pc = false;          // the last instruction left per-lane pc/cyc in c
     for (;;) {
-        if (u.cyc >= u.cap) {
-            u.err |= ERR_FRAME_CAP;
+        if (F.cyc >= F.cap) {
+            c.err |= ERR_FRAME_CAP;
             ended = true;
-            end_t = u.cyc - 1;
+            end_t = F.cyc - 1;
             break;
         }
-        const uint32_t off = u.pc & 0xFFF;
-        if (!(u.pc & 0x1000) || off > 0xFFD) break;    // the per-lane path fetches this one
-        const uint32_t boff = (u.bank << 12) | off;
-        const uint32_t w = rfl(__builtin_amdgcn_alignbyte(s_rom[(boff >> 2) + 1], s_rom[boff >> 2], boff & 3));
-        uint32_t d = kDecode.w[w & 0xFF];
-        asm volatile("" : "+s"(d));
-        u.ev = 0;
-        u.tqm = 0;
-        exec_generic(d, u, W, (w >> 8) & 0xFF, (w >> 16) & 0xFF);
-        if (u.err & ERR_ILLEGAL) {
-            ended = true;
-            end_t = u.cyc - 1;
+        const uint32_t off = F.pc & 0xFFF;
+        if (!(F.pc & 0x1000) || off > 0xFFD) break;
+        const uint2 q = pre[(F.bank << 12) | off];
+        const uint32_t qx = rfl(q.x), d = rfl(q.y);
+        const uint32_t b1 = (qx >> 8) & 0xFF, b2 = (qx >> 16) & 0xFF;
+        const uint32_t md = d & 15, mn = (d >> 4) & 63;
+        uint32_t n = (d >> 10) & 7;
+        const uint32_t next = (F.pc + ((d >> 14) & 3)) & 0xFFFF;
+        uint32_t npc = next;
+        bool wsync = false, vs = false;
+        bool handled = true;
+        uint32_t t;
+        if (md == IMP || md == ACC || md == IMM) {
+            t = F.cyc + n - 1;
+            if (md == IMM) {
+                fast_alu(c, mn, b1);
+            } else if (md == ACC) {
+                c.a = fast_rmw(c, mn, c.a);
+            } else {
+                switch (mn) {
+                case INX: c.x = (c.x + 1) & 0xFF; c.p = nz(c.p, c.x); break;
+                case INY: c.y = (c.y + 1) & 0xFF; c.p = nz(c.p, c.y); break;
+                case DEX: c.x = (c.x - 1) & 0xFF; c.p = nz(c.p, c.x); break;
+                case DEY: c.y = (c.y - 1) & 0xFF; c.p = nz(c.p, c.y); break;
+                case TAX: c.x = c.a; c.p = nz(c.p, c.x); break;
+                case TAY: c.y = c.a; c.p = nz(c.p, c.y); break;
+                case TXA: c.a = c.x; c.p = nz(c.p, c.a); break;
+                case TYA: c.a = c.y; c.p = nz(c.p, c.a); break;
+                case TSX: c.x = c.sp; c.p = nz(c.p, c.x); break;
+                case TXS: c.sp = c.x; break;
+                case CLC: c.p &= ~FC; break;
+                case SEC: c.p |= FC; break;
+                case CLI: c.p &= ~FI; break;
+                case SEI: c.p |= FI; break;
+                case CLV: c.p &= ~FV; break;
+                case CLD: c.p &= ~FD; break;
+                case SED: c.p |= FD; break;
+                case NOP: break;
+                case PHA: case PHP: {
+                    if (!all_lanes(c.sp >= 0x80)) { handled = false; break; }
+                    W.ram[c.ram_off + (c.sp & 0x7F)] = (uint8_t)(mn == PHA ? c.a : (c.p | FB | FU));
+                    c.sp = (c.sp - 1) & 0xFF;
+                    break;
+                }
+                case PLA: case PLP: {
+                    if (!all_lanes(c.sp >= 0x7F && c.sp <= 0xFE)) { handled = false; break; }
+                    c.sp = (c.sp + 1) & 0xFF;
+                    const uint32_t v = W.ram[c.ram_off + (c.sp & 0x7F)];
+                    if (mn == PLA) { c.a = v; c.p = nz(c.p, v); }
+                    else c.p = (v & ~FB) | FU;
+                    break;
+                }
+                case RTS: {
+                    if (!all_lanes(c.sp >= 0x7F && c.sp <= 0xFD)) { handled = false; break; }
+                    const uint32_t lo = W.ram[c.ram_off + ((c.sp + 1) & 0x7F)];
+                    const uint32_t hi = W.ram[c.ram_off + ((c.sp + 2) & 0x7F)];
+                    c.sp = (c.sp + 2) & 0xFF;
+                    const uint32_t tgt = ((lo | (hi << 8)) + 1) & 0xFFFF;
+                    const uint32_t t0 = rfl(tgt);
+                    if (all_lanes(tgt == t0)) npc = t0;
+                    else { c.pc = tgt; lane_pc = true; }
+                    break;
+                }
+                default: handled = false; break;      // RTI, BRK, undocumented opcodes
+                }
+            }
+        } else if (md == ZP || md == ABS) {
+            const uint32_t ea = md == ZP ? b1 : (b1 | (b2 << 8));
+            const uint32_t a = ea & 0x1FFF;
+            t = F.cyc + n - 1;
+            if (mn == JMP) {
+                npc = ea;
+            } else if (mn == JSR) {
+                if (!all_lanes(c.sp >= 0x81)) { handled = false; }
+                else {
+                    const uint32_t ret = (next - 1) & 0xFFFF;
+                    W.ram[c.ram_off + (c.sp & 0x7F)] = (uint8_t)(ret >> 8);
+                    W.ram[c.ram_off + ((c.sp - 1) & 0x7F)] = (uint8_t)(ret & 0xFF);
+                    c.sp = (c.sp - 2) & 0xFF;
+                    npc = ea;
+                }
+            } else if (is_read_op(mn)) {
+                fast_alu(c, mn, fast_rd(c, W, F, a, t));
+            } else if (mn == STA || mn == STX || mn == STY) {
+                vs = fast_wr(c, W, F, a, mn == STA ? c.a : (mn == STX ? c.x : c.y), t, wsync);
+            } else {                                    // read-modify-write
+                const uint32_t v = fast_rd(c, W, F, a, t);
+                vs = fast_wr(c, W, F, a, fast_rmw(c, mn, v), t, wsync);
+            }
+        } else if (md == ZPX || md == ZPY || md == ABX || md == ABY) {
+            const uint32_t idx = (md == ZPX || md == ABX) ? c.x : c.y;
+            uint32_t ea;
+            bool cross = false;
+            if (md == ZPX || md == ZPY) {
+                ea = (b1 + idx) & 0xFF;
+            } else {
+                const uint32_t base = b1 | (b2 << 8);
+                ea = (base + idx) & 0xFFFF;
+                cross = ((base ^ ea) & 0xFF00) != 0;
+            }
+            const uint32_t a = ea & 0x1FFF;
+            const bool in_ram = (a & 0x1280) == 0x0080;
+            const bool in_cart = (a & 0x1000) && (!W.f8 || ((a & 0xFFF) != 0xFF8 && (a & 0xFFF) != 0xFF9));
+            const bool rd_op = is_read_op(mn);
+            const bool pen = (d >> 13) & 1;
+            if (!all_lanes(in_ram || (rd_op && in_cart)) || (pen && !all_lanes(cross == (rfl(cross ? 1u : 0u) != 0)))) {
+                handled = false;
+            } else {
+                if (pen && rfl(cross ? 1u : 0u)) n += 1;
+                t = F.cyc + n - 1;
+                if (rd_op) {
+                    const uint32_t v = in_ram ? (uint32_t)W.ram[c.ram_off + (a & 0x7F)]
+                                              : (uint32_t)W.rom[(F.bank << 12) | (a & 0xFFF)];
+                    fast_alu(c, mn, v);
+                } else if (mn == STA || mn == STX || mn == STY) {
+                    W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)(mn == STA ? c.a : (mn == STX ? c.x : c.y));
+                } else {
+                    uint8_t* m = &W.ram[c.ram_off + (a & 0x7F)];
+                    *m = (uint8_t)fast_rmw(c, mn, *m);
+                }
+            }
+        } else if (md == REL) {
+            bool taken;
+            switch (mn) {
+            case BPL: taken = !(c.p & FN); break;
+            case BMI: taken = (c.p & FN) != 0; break;
+            case BVC: taken = !(c.p & FV); break;
+            case BVS: taken = (c.p & FV) != 0; break;
+            case BCC: taken = !(c.p & FC); break;
+            case BCS: taken = (c.p & FC) != 0; break;
+            case BNE: taken = !(c.p & FZ); break;
+            default: taken = (c.p & FZ) != 0; break;
+            }
+            const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
+            const uint32_t extra = 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0);
+            const uint64_t tk = __builtin_amdgcn_ballot_w64(taken);
+            const uint64_t all = __builtin_amdgcn_ballot_w64(true);
+            if (tk == all) {
+                npc = tgt;
+                n += extra;
+            } else if (tk != 0) {
+                c.pc = taken ? tgt : next;            // the lanes part here
+                c.cyc = F.cyc + n + (taken ? extra : 0);
+                c.icount++;
+                c.ucount++;
+                lane_pc = true;
+                break;
+            }
+            t = F.cyc + n - 1;
+        } else {
+            handled = false;                            // (zp,x), (zp),y, jmp (ind)
+        }
+        if (!handled) break;                            // the per-lane path executes it
+        c.icount++;
+        c.ucount++;
+        if (lane_pc) {                                  // RTS to differing targets
+            c.cyc = t + 1;
             break;
         }
-        u.icount++;
-        u.ucount++;
-        const uint32_t t = u.ac;
-        apply_queue(u, W, t);
-        if (u.ev & EV_WSYNC) u.cyc = 76 * (t / 76 + 1);
-        const uint32_t vs = (u.ev & EV_VSYNC) ? 1u : 0u;
-        const uint32_t pc0 = rfl(u.pc), cy0 = rfl(u.cyc), bk0 = rfl(u.bank), vs0 = rfl(vs);
-        const bool same = u.pc == pc0 && u.cyc == cy0 && u.bank == bk0 && vs == vs0;
-        if (__builtin_amdgcn_ballot_w64(!same) != 0) {
+        F.pc = npc;
+        F.cyc = wsync ? 76 * (t / 76 + 1) : t + 1;
+        const uint64_t vsm = __builtin_amdgcn_ballot_w64(vs);
+        if (vsm != 0) {
             if (vs) {
                 ended = true;
                 end_t = t;
             }
-            break;
-        }
-        u.pc = pc0;
-        u.cyc = cy0;
-        u.bank = bk0;
-        if (vs0) {
-            ended = true;
-            end_t = t;
+            if (vsm != __builtin_amdgcn_ballot_w64(true)) {      // only some lanes' frames ended
+                c.pc = F.pc;
+                c.cyc = F.cyc;
+                lane_pc = true;
+            }
             break;
         }
     }
-    c = u;
+    if (!lane_pc) {
+        c.pc = F.pc;
+        c.cyc = F.cyc;
+    }
+    c.bank = F.bank;
+    c.open_row = (int32_t)F.orow - 1;
+    c.open_cnt = F.ocnt;
 }
 
 __device__ __forceinline__ uint32_t bcd_value(uint32_t b) { return 10 * (b >> 4) + (b & 15); }
@@ -678,244 +984,275 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
 // again at every WSYNC line start and share one dispatch pass per instruction.
 constexpr uint32_t kSchedWindow = 6;
 
-__global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A) {
+// Next tile of a persistent launch (lane 0 takes it, the wave shares it).
+__device__ __forceinline__ uint32_t take_tile(uint32_t* queue) {
+    uint32_t t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(queue, 1u);
+    return __builtin_amdgcn_readfirstlane(t);
+}
+
+__global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint2* __restrict__ pre_all) {
     __shared__ uint32_t s_rom[kRomSlot / 4 + 4];
     __shared__ uint32_t s_ram[kLanes * kRamStride / 4];
     __shared__ uint32_t s_tia[kLanes * kTiaStride / 4];
 
-    const uint32_t tile_id = blockIdx.x;
-    if (tile_id >= *A.n_tiles) return;
-    const Tile& T = A.tiles[tile_id];
-    const int lane = threadIdx.x;
-    const int rom_id = T.rom;
+    const uint32_t n_tiles = *A.n_tiles;
+    uint32_t tile_id = A.queue ? take_tile(A.queue) : blockIdx.x;
+    while (tile_id < n_tiles) {
+        const Tile& T = A.tiles[tile_id];
+        const int lane = threadIdx.x;
+        const int rom_id = T.rom;
 
-    // stage the cartridge in LDS
-    const uint4* rsrc = reinterpret_cast<const uint4*>(A.roms + (size_t)rom_id * kRomSlot);
-    for (int i = lane; i < kRomSlot / 16; i += kLanes) reinterpret_cast<uint4*>(s_rom)[i] = rsrc[i];
-    if (lane < 4) s_rom[kRomSlot / 4 + lane] = 0;
+        // stage the cartridge in LDS
+        const uint4* rsrc = reinterpret_cast<const uint4*>(A.roms + (size_t)rom_id * kRomSlot);
+        for (int i = lane; i < kRomSlot / 16; i += kLanes) reinterpret_cast<uint4*>(s_rom)[i] = rsrc[i];
+        if (lane < 4) s_rom[kRomSlot / 4 + lane] = 0;
 
-    Wave W;
-    W.rom = reinterpret_cast<uint8_t*>(s_rom);
-    W.ram = reinterpret_cast<uint8_t*>(s_ram);
-    W.tia = reinterpret_cast<uint8_t*>(s_tia);
-    W.f8 = A.schemes[rom_id];
+        Wave W;
+        W.rom = reinterpret_cast<uint8_t*>(s_rom);
+        W.ram = reinterpret_cast<uint8_t*>(s_ram);
+        W.tia = reinterpret_cast<uint8_t*>(s_tia);
+        W.f8 = A.schemes[rom_id];
 
-    const int env = lane < T.count ? T.env[lane] : -1;
-    const int out = lane < T.count ? T.out[lane] : 0;
-    bool active = env >= 0;
+        const int env = lane < T.count ? T.env[lane] : -1;
+        const int out = lane < T.count ? T.out[lane] : 0;
+        bool active = env >= 0;
 
-    Cpu c;
-    c.ram_off = lane * kRamStride;
-    c.tia_off = lane * kTiaStride;
-    DevEnv* E = active ? &A.envs[env] : nullptr;
-    uint64_t base_line = 0;
-    uint32_t prev_action = 0, act = 0, step_idx = 0, score0 = 0, nfr = A.nframes;
-    uint64_t sticky_prefix = 0;
-    if (active) {
-        const uint4* src = reinterpret_cast<const uint4*>(E->ram);
-        for (int i = 0; i < 8; ++i) {
-            const uint4 q = src[i];
-            uint32_t* d = s_ram + (c.ram_off >> 2) + 4 * i;
-            d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+        Cpu c;
+        c.ram_off = lane * kRamStride;
+        c.tia_off = lane * kTiaStride;
+        DevEnv* E = active ? &A.envs[env] : nullptr;
+        uint64_t base_line = 0;
+        uint32_t prev_action = 0, act = 0, step_idx = 0, score0 = 0, nfr = A.nframes;
+        uint64_t sticky_prefix = 0;
+        if (active) {
+            const uint4* src = reinterpret_cast<const uint4*>(E->ram);
+            for (int i = 0; i < 8; ++i) {
+                const uint4 q = src[i];
+                uint32_t* d = s_ram + (c.ram_off >> 2) + 4 * i;
+                d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+            }
+            const uint4 qt = reinterpret_cast<const uint4*>(E->tia)[0];
+            uint32_t* dt = s_tia + (c.tia_off >> 2);
+            dt[0] = qt.x; dt[1] = qt.y; dt[2] = qt.z; dt[3] = qt.w; dt[4] = 0;
+            c.a = E->a; c.x = E->x; c.y = E->y; c.sp = E->sp; c.p = E->p; c.bank = E->bank;
+            c.vsync = E->vsync; c.hmp0 = E->hmp0; c.hmp1 = E->hmp1;
+            c.tv = E->tv; c.tshift = E->tshift; c.tbase = E->tbase;
+            c.pc = E->pc;
+            const uint64_t cyc = E->cycle;
+            base_line = cyc / 76;
+            c.cyc = (uint32_t)(cyc - base_line * 76);
+            c.fl = (int32_t)((int64_t)E->frame_line0 - (int64_t)base_line);
+            prev_action = E->prev_action;
+            step_idx = E->step_idx;
+            c.err = E->err;
+            act = A.actions ? A.actions[out] : 0;
+            if (A.nframes_per_out) nfr = A.nframes_per_out[out];
+            sticky_prefix = rng_prefix(A.seed, (uint64_t)env, kStickyPurpose);
         }
-        const uint4 qt = reinterpret_cast<const uint4*>(E->tia)[0];
-        uint32_t* dt = s_tia + (c.tia_off >> 2);
-        dt[0] = qt.x; dt[1] = qt.y; dt[2] = qt.z; dt[3] = qt.w; dt[4] = 0;
-        c.a = E->a; c.x = E->x; c.y = E->y; c.sp = E->sp; c.p = E->p; c.bank = E->bank;
-        c.vsync = E->vsync; c.hmp0 = E->hmp0; c.hmp1 = E->hmp1;
-        c.tv = E->tv; c.tshift = E->tshift; c.tbase = E->tbase;
-        c.pc = E->pc;
-        const uint64_t cyc = E->cycle;
-        base_line = cyc / 76;
-        c.cyc = (uint32_t)(cyc - base_line * 76);
-        c.fl = (int32_t)((int64_t)E->frame_line0 - (int64_t)base_line);
-        prev_action = E->prev_action;
-        step_idx = E->step_idx;
-        c.err = E->err;
-        act = A.actions ? A.actions[out] : 0;
-        if (A.nframes_per_out) nfr = A.nframes_per_out[out];
-        sticky_prefix = rng_prefix(A.seed, (uint64_t)env, kStickyPurpose);
-    }
-    __syncthreads();
-    score0 = active ? W.ram[c.ram_off + 0x50] : 0;
-    c.base = base_line * 76;
-    c.icount = 0;
-    c.ucount = 0;
-    c.slots = 0;
-    c.slot = 0;
-    c.log = nullptr;
-    c.open_row = -1;
-    c.open_cnt = 0;
-    c.tqm = 0;
-    c.ev = 0;
-    uint32_t k = 0, done = 0;
-    uint32_t f = 0;
-
-    auto begin_frame = [&]() {
-        uint32_t eff = act;
-        if (A.sticky_thr) {
-            const uint64_t ctr = (uint64_t)step_idx * A.frameskip + f;
-            if ((uint32_t)(rng_draw(sticky_prefix, ctr) >> 32) < A.sticky_thr) eff = prev_action;
-        }
-        prev_action = eff;
-        c.swcha = (0xF0u & ~joy_pressed(eff)) | 0x0Fu;
-        c.inpt4 = fire_pressed(eff) ? 0x00u : 0x80u;
-        c.cap = 76u * (uint32_t)(320 + c.fl);
-        const int32_t slot = A.render_all ? (int32_t)f : (int32_t)f - ((int32_t)nfr - 2);
-        c.log = (A.log_enabled && slot >= 0 && slot < (int32_t)A.n_slots)
-                    ? A.logs + ((size_t)out * A.n_slots + slot) * kFrameLogBytes
-                    : nullptr;
-        c.slot = (uint32_t)slot;
+        __syncthreads();
+        score0 = active ? W.ram[c.ram_off + 0x50] : 0;
+        c.base = base_line * 76;
+        c.icount = 0;
+        c.ucount = 0;
+        c.slots = 0;
+        c.slot = 0;
+        c.log = nullptr;
         c.open_row = -1;
         c.open_cnt = 0;
-    };
+        c.tqm = 0;
+        c.ev = 0;
+        uint32_t k = 0, done = 0;
+        uint32_t f = 0;
 
-    if (active) {
-        if (act >= 18) {
-            c.err |= ERR_BAD_ACTION;
-            done = 1;
-            active = false;
-        } else if (nfr == 0) {
-            active = false;
-        } else {
-            begin_frame();
-        }
-    }
+        auto begin_frame = [&]() {
+            uint32_t eff = act;
+            if (A.sticky_thr) {
+                const uint64_t ctr = (uint64_t)step_idx * A.frameskip + f;
+                if ((uint32_t)(rng_draw(sticky_prefix, ctr) >> 32) < A.sticky_thr) eff = prev_action;
+            }
+            prev_action = eff;
+            c.swcha = (0xF0u & ~joy_pressed(eff)) | 0x0Fu;
+            c.inpt4 = fire_pressed(eff) ? 0x00u : 0x80u;
+            c.cap = 76u * (uint32_t)(320 + c.fl);
+            const int32_t slot = A.render_all ? (int32_t)f : (int32_t)f - ((int32_t)nfr - 2);
+            c.log = (A.log_enabled && slot >= 0 && slot < (int32_t)A.n_slots)
+                        ? A.logs + ((size_t)out * A.n_slots + slot) * kFrameLogBytes
+                        : nullptr;
+            c.slot = (uint32_t)slot;
+            c.open_row = -1;
+            c.open_cnt = 0;
+        };
 
-    // ---------------------------------------------------------- main loop
-    while (__any(active)) {
-        uint32_t op = 0, b1 = 0, b2 = 0;
-        bool want = false, ended = false;
-        uint32_t end_t = 0;
-        // wave-uniform mode when every running lane is at the same place
-        bool uni = false;
         if (active) {
-            const uint32_t pc0 = rfl(c.pc), bk0 = rfl(c.bank), cy0 = rfl(c.cyc);
-            const int32_t fl0 = rfl(c.fl);
-            const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == cy0 && c.fl == fl0;
-            if (__builtin_amdgcn_ballot_w64(!same) == 0) {
-                run_uniform(c, W, s_rom, ended, end_t);
-                uni = true;
-            }
-        }
-        const bool ran_uniform = __any(uni);
-        const uint32_t tmin = ran_uniform ? 0u : wave_min(active ? c.cyc : 0xFFFFFFFFu);
-        const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;
-        if (go) {
-            if (c.cyc >= c.cap) {
-                c.err |= ERR_FRAME_CAP;
-                ended = true;
-                end_t = c.cyc - 1;
-            } else {
-                const uint32_t pc = c.pc;
-                const uint32_t off = pc & 0xFFF;
-                if ((pc & 0x1000) && off <= 0xFFD) {
-                    const uint32_t boff = (c.bank << 12) | off;
-                    const uint32_t w0 = s_rom[boff >> 2], w1 = s_rom[(boff >> 2) + 1];
-                    const uint32_t v = __builtin_amdgcn_alignbyte(w1, w0, boff & 3);
-                    op = v & 0xFF;
-                    b1 = (v >> 8) & 0xFF;
-                    b2 = (v >> 16) & 0xFF;
-                } else {
-                    op = peek(c, W, pc, c.cyc);
-                    b1 = peek(c, W, pc + 1, c.cyc);
-                    b2 = peek(c, W, pc + 2, c.cyc);
-                }
-                want = true;
-                c.ev = 0;
-                c.tqm = 0;
-            }
-        }
-        // one pass per distinct opcode among the lanes that fetched one
-        bool todo = want;
-        while (__any(todo)) {
-            if (todo) {
-                const uint32_t sop = __builtin_amdgcn_readfirstlane(op);
-                // an opaque scalar copy: inside the branch below the compiler
-                // would otherwise switch on the per-lane `op` (equal there)
-                uint32_t sw = sop;
-                asm volatile("" : "+s"(sw));
-                uint32_t d = kDecode.w[sw];
-                asm volatile("" : "+s"(d));
-                if (op == sop) {
-                    exec_generic(d, c, W, b1, b2);
-                    todo = false;
-                }
-            }
-        }
-        if (want) {
-            if (c.err & ERR_ILLEGAL) {
-                ended = true;
-                end_t = c.cyc - 1;
-            } else {
-                c.icount++;
-                const uint32_t t = c.ac;
-                apply_queue(c, W, t);
-                if (c.ev & EV_WSYNC) c.cyc = 76 * (t / 76 + 1);
-                if (c.ev & EV_VSYNC) {
-                    ended = true;
-                    end_t = t;
-                }
-            }
-        }
-        if (ended) {
-            if (c.log) log_close(c, W, end_t);
-            c.fl = (int32_t)(end_t / 76);
-            ++k;
-            ++f;
-            const bool term = A.early_stop && W.ram[c.ram_off + 0x51] != 0;
-            if (c.err || term) {
+            if (act >= 18) {
+                c.err |= ERR_BAD_ACTION;
                 done = 1;
                 active = false;
-            } else if (f >= nfr) {
+            } else if (nfr == 0) {
                 active = false;
             } else {
                 begin_frame();
             }
         }
-    }
 
-    // ---------------------------------------------------------- write back
-    if (env >= 0) {
-        const uint32_t* sr = s_ram + (c.ram_off >> 2);
-        uint4* dst = reinterpret_cast<uint4*>(E->ram);
-        for (int i = 0; i < 8; ++i) dst[i] = make_uint4(sr[4 * i], sr[4 * i + 1], sr[4 * i + 2], sr[4 * i + 3]);
-        const uint32_t* st = s_tia + (c.tia_off >> 2);
-        reinterpret_cast<uint4*>(E->tia)[0] = make_uint4(st[0], st[1], st[2], st[3]);
-        E->a = c.a; E->x = c.x; E->y = c.y; E->sp = c.sp; E->p = c.p; E->bank = c.bank;
-        E->vsync = c.vsync; E->hmp0 = c.hmp0; E->hmp1 = c.hmp1;
-        E->tv = c.tv; E->tshift = c.tshift; E->tbase = c.tbase;
-        E->pc = c.pc;
-        E->cycle = c.base + c.cyc;
-        E->frame_line0 = (uint64_t)((int64_t)base_line + c.fl);
-        E->instr += c.icount;
-        E->prev_action = prev_action;
-        E->err = c.err;
-        E->step_idx = step_idx + 1;
-        StepInfo si;
-        si.k = (uint8_t)k;
-        si.done = (uint8_t)done;
-        si.err = (uint8_t)c.err;
-        si.slots = (uint8_t)c.slots;
-        A.info[out] = si;
-        if (A.done) A.done[out] = (uint8_t)done;
-        if (A.reward) {
-            const uint32_t s1 = W.ram[c.ram_off + 0x50];
-            A.reward[out] = (int32_t)bcd_value(s1) - (int32_t)bcd_value(score0);
+        // ---------------------------------------------------------- main loop
+        while (__any(active)) {
+            uint32_t op = 0, b1 = 0, b2 = 0;
+            bool want = false, ended = false;
+            uint32_t end_t = 0;
+            // wave-uniform mode when every running lane is at the same place
+            bool uni = false;
+            if (active) {
+                const uint32_t pc0 = rfl(c.pc), bk0 = rfl(c.bank), cy0 = rfl(c.cyc);
+                const int32_t fl0 = rfl(c.fl), or0 = rfl(c.open_row);
+                const uint32_t oc0 = rfl(c.open_cnt), lg0 = rfl(c.log != nullptr ? 1u : 0u);
+                const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == cy0 && c.fl == fl0 &&
+                                  c.open_row == or0 && c.open_cnt == oc0 && (c.log != nullptr ? 1u : 0u) == lg0;
+                if (__builtin_amdgcn_ballot_w64(!same) == 0) {
+                    run_fast(c, W, pre_all + (size_t)rom_id * kRomSlot, ended, end_t);
+                    uni = true;
+                }
+            }
+            const bool ran_uniform = __any(uni);
+            const uint32_t tmin = ran_uniform ? 0u : wave_min(active ? c.cyc : 0xFFFFFFFFu);
+            const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;
+            if (go) {
+                if (c.cyc >= c.cap) {
+                    c.err |= ERR_FRAME_CAP;
+                    ended = true;
+                    end_t = c.cyc - 1;
+                } else {
+                    const uint32_t pc = c.pc;
+                    const uint32_t off = pc & 0xFFF;
+                    if ((pc & 0x1000) && off <= 0xFFD) {
+                        const uint32_t boff = (c.bank << 12) | off;
+                        const uint32_t w0 = s_rom[boff >> 2], w1 = s_rom[(boff >> 2) + 1];
+                        const uint32_t v = __builtin_amdgcn_alignbyte(w1, w0, boff & 3);
+                        op = v & 0xFF;
+                        b1 = (v >> 8) & 0xFF;
+                        b2 = (v >> 16) & 0xFF;
+                    } else {
+                        op = peek(c, W, pc, c.cyc);
+                        b1 = peek(c, W, pc + 1, c.cyc);
+                        b2 = peek(c, W, pc + 2, c.cyc);
+                    }
+                    want = true;
+                    c.ev = 0;
+                    c.tqm = 0;
+                }
+            }
+            // one pass per distinct opcode among the lanes that fetched one
+            bool todo = want;
+            while (__any(todo)) {
+                if (todo) {
+                    const uint32_t sop = __builtin_amdgcn_readfirstlane(op);
+                    // an opaque scalar copy: inside the branch below the compiler
+                    // would otherwise switch on the per-lane `op` (equal there)
+                    uint32_t sw = sop;
+                    asm volatile("" : "+s"(sw));
+                    uint32_t d = kDecode.w[sw];
+                    asm volatile("" : "+s"(d));
+                    if (op == sop) {
+                        exec_generic(d, c, W, b1, b2);
+                        todo = false;
+                    }
+                }
+            }
+            if (want) {
+                if (c.err & ERR_ILLEGAL) {
+                    ended = true;
+                    end_t = c.cyc - 1;
+                } else {
+                    c.icount++;
+                    const uint32_t t = c.ac;
+                    apply_queue(c, W, t);
+                    if (c.ev & EV_WSYNC) c.cyc = 76 * (t / 76 + 1);
+                    if (c.ev & EV_VSYNC) {
+                        ended = true;
+                        end_t = t;
+                    }
+                }
+            }
+            if (ended) {
+                if (c.log) log_close(c, W, end_t);
+                c.fl = (int32_t)(end_t / 76);
+                ++k;
+                ++f;
+                const bool term = A.early_stop && W.ram[c.ram_off + 0x51] != 0;
+                if (c.err || term) {
+                    done = 1;
+                    active = false;
+                } else if (f >= nfr) {
+                    active = false;
+                } else {
+                    begin_frame();
+                }
+            }
         }
-        if (c.err) {
-            atomicOr(&A.err_word[0], c.err);
-            atomicMin(&A.err_word[1], (uint32_t)env);
+
+        // ---------------------------------------------------------- write back
+        if (env >= 0) {
+            const uint32_t* sr = s_ram + (c.ram_off >> 2);
+            uint4* dst = reinterpret_cast<uint4*>(E->ram);
+            for (int i = 0; i < 8; ++i) dst[i] = make_uint4(sr[4 * i], sr[4 * i + 1], sr[4 * i + 2], sr[4 * i + 3]);
+            const uint32_t* st = s_tia + (c.tia_off >> 2);
+            reinterpret_cast<uint4*>(E->tia)[0] = make_uint4(st[0], st[1], st[2], st[3]);
+            E->a = c.a; E->x = c.x; E->y = c.y; E->sp = c.sp; E->p = c.p; E->bank = c.bank;
+            E->vsync = c.vsync; E->hmp0 = c.hmp0; E->hmp1 = c.hmp1;
+            E->tv = c.tv; E->tshift = c.tshift; E->tbase = c.tbase;
+            E->pc = c.pc;
+            E->cycle = c.base + c.cyc;
+            E->frame_line0 = (uint64_t)((int64_t)base_line + c.fl);
+            E->instr += c.icount;
+            E->prev_action = prev_action;
+            E->err = c.err;
+            E->step_idx = step_idx + 1;
+            StepInfo si;
+            si.k = (uint8_t)k;
+            si.done = (uint8_t)done;
+            si.err = (uint8_t)c.err;
+            si.slots = (uint8_t)c.slots;
+            A.info[out] = si;
+            if (A.done) A.done[out] = (uint8_t)done;
+            if (A.reward) {
+                const uint32_t s1 = W.ram[c.ram_off + 0x50];
+                A.reward[out] = (int32_t)bcd_value(s1) - (int32_t)bcd_value(score0);
+            }
+            if (c.err) {
+                atomicOr(&A.err_word[0], c.err);
+                atomicMin(&A.err_word[1], (uint32_t)env);
+            }
+            if (A.instr_total) {
+                atomicAdd(&A.instr_total[0], (unsigned long long)c.icount);
+                atomicAdd(&A.instr_total[1], (unsigned long long)c.ucount);
+            }
         }
-        if (A.instr_total) {
-            atomicAdd(&A.instr_total[0], (unsigned long long)c.icount);
-            atomicAdd(&A.instr_total[1], (unsigned long long)c.ucount);
-        }
+        if (!A.queue) break;
+        __syncthreads();   // every lane is done with the LDS of this tile
+        tile_id = take_tile(A.queue);
     }
 }
 
+// Predecoded ROM: for every bank offset, opcode | b1 << 8 | b2 << 16 and the
+// opcode's decode word (entries past offset $FFD are never used).
+__global__ void k_predecode(const uint8_t* roms, uint32_t n_roms, uint2* pre) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_roms * (uint32_t)kRomSlot) return;
+    const uint32_t r = i / kRomSlot, o = i % kRomSlot, bank = o >> 12, off = o & 0xFFF;
+    const uint8_t* rom = roms + (size_t)r * kRomSlot + (bank << 12);
+    const uint32_t op = rom[off];
+    const uint32_t b1 = off + 1 < 4096 ? rom[off + 1] : 0, b2 = off + 2 < 4096 ? rom[off + 2] : 0;
+    pre[i] = make_uint2(op | (b1 << 8) | (b2 << 16), kDecode.w[op]);
+}
+
+void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint2* pre, hipStream_t s) {
+    const uint32_t n = n_roms * (uint32_t)kRomSlot;
+    hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, roms, n_roms, pre);
+}
+
 void launch_interp(const InterpArgs& a, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_interp, dim3(grid), dim3(kLanes), 0, s, a);
+    hipLaunchKernelGGL(k_interp, dim3(grid), dim3(kLanes), 0, s, a, a.pre);
 }
 
 }  // namespace vcs

@@ -136,8 +136,8 @@ constexpr int kSegs = kCols / 16;            // 10 segments per row
 constexpr int kFrameSegs = kRows * kSegs;    // 2100
 
 // Frames that only go to the frames output (render mode ALL, slots before the
-// last two).  grid = (n, n_slots - 2), block 256.
-__global__ void __launch_bounds__(256) k_render_frames(RenderArgs A) {
+// last two).  grid = (n, n_slots - 2), block 64..512 threads.
+__global__ void __launch_bounds__(512) k_render_frames(RenderArgs A) {
     const uint32_t i = blockIdx.x;
     const int slot = blockIdx.y;
     const StepInfo si = A.info[i];
@@ -152,15 +152,15 @@ __global__ void __launch_bounds__(256) k_render_frames(RenderArgs A) {
 }
 
 // The last two frame slots: frames output (optional) and the observation.
-// grid = n, block 256.
-__global__ void __launch_bounds__(256) k_render_obs(RenderArgs A) {
+// grid = n, block 64..512 threads.
+__global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
     __shared__ uint32_t s_m[kFrameBytes / 4];   // max gray of the two frames
     __shared__ uint8_t s_lut[128];
     const uint32_t i = blockIdx.x;
     const StepInfo si = A.info[i];
     const bool bad = (si.err & ERR_BAD_ID) != 0;
     const bool want_obs = A.obs && !bad && (A.force_obs || !si.done);
-    if (threadIdx.x < 128) s_lut[threadIdx.x] = A.gray[threadIdx.x];
+    for (int j = threadIdx.x; j < 128; j += blockDim.x) s_lut[j] = A.gray[j];
     uint8_t* m = reinterpret_cast<uint8_t*>(s_m);
     __syncthreads();
     const int s0 = (int)A.n_slots - 2;
@@ -214,11 +214,11 @@ __global__ void __launch_bounds__(256) k_render_obs(RenderArgs A) {
     }
 }
 
-void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, hipStream_t s) {
-    hipLaunchKernelGGL(k_render_frames, dim3(a.n, n_front_slots), dim3(256), 0, s, a);
+void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s) {
+    hipLaunchKernelGGL(k_render_frames, dim3(a.n, n_front_slots), dim3(block), 0, s, a);
 }
-void launch_render_obs(const RenderArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_render_obs, dim3(a.n), dim3(256), 0, s, a);
+void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s) {
+    hipLaunchKernelGGL(k_render_obs, dim3(a.n), dim3(block), 0, s, a);
 }
 
 }  // namespace vcs

@@ -53,9 +53,9 @@ struct alignas(16) DevEnv {
 };
 static_assert(sizeof(DevEnv) == 256, "DevEnv is 256 bytes");
 
-struct Tile {                 // 64 lanes of one ROM
+struct Tile {                 // up to 64 envs of one ROM, one per lane
     int32_t rom;
-    int32_t count;
+    int32_t count;            // envs in the tile (<= the launch's tile width)
     int32_t env[kLanes];      // env id per lane (-1 = idle lane)
     int32_t out[kLanes];      // output position per lane
 };
@@ -73,6 +73,7 @@ struct InterpArgs {
     DevEnv* envs;
     const uint8_t* roms;      // [n_roms][kRomSlot]
     const uint32_t* schemes;  // [n_roms]
+    const uint2* pre;         // [n_roms][kRomSlot] predecoded ROM
     const uint8_t* actions;   // [n outputs]; NULL = NOOP
     const uint16_t* nframes_per_out;  // [n outputs] or NULL
     uint32_t nframes;         // frames per step when nframes_per_out is NULL
@@ -89,6 +90,8 @@ struct InterpArgs {
     uint8_t* done;            // [n outputs] or NULL
     uint32_t* err_word;       // [0] bits, [1] smallest env id with an error
     unsigned long long* instr_total;
+    uint32_t* queue;          // NULL: workgroup b runs tile b; else workgroups take
+                              // tiles from this counter until it passes *n_tiles
 };
 
 // SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014)
@@ -133,16 +136,18 @@ struct ResetArgs {
 
 // host launchers (one per kernel)
 void launch_interp(const InterpArgs& a, uint32_t grid, hipStream_t s);
-void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, hipStream_t s);
-void launch_render_obs(const RenderArgs& a, hipStream_t s);
+void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint2* pre, hipStream_t s);
+void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s);
+void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s);
 void launch_reset(const ResetArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, hipStream_t s);
 void launch_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, const uint16_t* env_rom,
-                     uint32_t* claim, uint32_t tag, uint32_t* counts, uint8_t* valid, StepInfo* info,
+                     uint32_t* claim, const uint32_t* tag, uint32_t* counts, uint8_t* valid, StepInfo* info,
                      int32_t* reward, uint8_t* done, uint32_t* err_word, hipStream_t s);
-void launch_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t* offsets, uint32_t* fill,
-                        Tile* tiles, uint32_t* n_tiles, hipStream_t s);
+void launch_tile_layout(const uint32_t* counts, uint32_t n_roms, uint32_t width, uint32_t* offsets,
+                        uint32_t* fill, Tile* tiles, uint32_t* n_tiles, hipStream_t s);
 void launch_tile_fill(const int32_t* ids, uint32_t n, const uint16_t* env_rom, const uint8_t* valid,
-                      const uint32_t* offsets, uint32_t* fill, Tile* tiles, hipStream_t s);
+                      uint32_t width, const uint32_t* offsets, uint32_t* fill, Tile* tiles, hipStream_t s);
 
 }  // namespace vcs

@@ -17,7 +17,7 @@ class VcsEnv:
 
     def __init__(self, roms, env_rom, gray_lut, frameskip=4, sticky_threshold=0, reset_cache_k=30,
                  noop_max=30, startup_frames=64, seed=0, render_mode=B.VCS_RENDER_ALL, max_batch=0,
-                 hbm_budget_bytes=0, device=0):
+                 hbm_budget_bytes=0, device=0, pipelines=1):
         env_rom = np.ascontiguousarray(env_rom, dtype=np.uint16)
         cfg = B.VcsConfig()
         cfg.num_envs = int(env_rom.shape[0])
@@ -31,9 +31,11 @@ class VcsEnv:
         cfg.max_batch = max_batch
         cfg.hbm_budget_bytes = hbm_budget_bytes
         cfg.device = device
+        cfg.pipelines = pipelines
         for i, g in enumerate(bytes(gray_lut)):
             cfg.gray_lut[i] = g
         self.num_envs = cfg.num_envs
+        self.pipelines = max(1, pipelines)
         self.frameskip = frameskip
         self.render_mode = render_mode
         self.max_batch = max_batch or cfg.num_envs
@@ -74,8 +76,15 @@ class VcsEnv:
         B.vcs_reset(self._h, ids_ptr, n, obs.data_ptr(), self._stream())
         return obs
 
-    def step(self, actions, env_ids=None, want_frames=False, want_obs=True, out=None):
-        """actions: uint8 cuda tensor [n].  Returns (obs, reward, done, frames)."""
+    def step(self, actions, env_ids=None, want_frames=False, want_obs=True, out=None, pipe=0, stream=None):
+        """actions: uint8 cuda tensor [n].  Returns (obs, reward, done, frames).
+
+        `pipe` selects the scratch pipeline and `stream` (a torch stream; default
+        the current one) the stream: steps on different pipelines and streams
+        may overlap when their env ids are disjoint."""
+        if stream is not None:
+            with torch.cuda.stream(stream):
+                return self.step(actions, env_ids, want_frames, want_obs, out, pipe)
         actions = torch.as_tensor(actions, dtype=torch.uint8, device=self.device).contiguous()
         n = actions.numel()
         ids, ids_ptr = self._ids(env_ids)
@@ -87,9 +96,9 @@ class VcsEnv:
                       if want_frames else None)
         else:
             obs, reward, done, frames = out
-        B.vcs_step(self._h, ids_ptr, actions.data_ptr(), n, obs.data_ptr() if obs is not None else None,
-                   reward.data_ptr(), done.data_ptr(), frames.data_ptr() if frames is not None else None,
-                   self._stream())
+        B.vcs_step_pipe(self._h, pipe, ids_ptr, actions.data_ptr(), n, obs.data_ptr() if obs is not None else None,
+                        reward.data_ptr(), done.data_ptr(), frames.data_ptr() if frames is not None else None,
+                        self._stream())
         return obs, reward, done, frames
 
     def get_state(self, env):
@@ -116,3 +125,55 @@ class VcsEnv:
 
     def kernel_time(self, which):
         return B.vcs_kernel_time(self._h, which)
+
+    # launch shape (results do not depend on it)
+    def set_launch(self, tile_envs=64, workers=0, render_block=256):
+        B.vcs_set_launch(self._h, tile_envs, workers, render_block)
+
+    def get_launch(self):
+        return B.vcs_get_launch(self._h)
+
+    def autotune(self, n=0, steps=3, want_frames=False, want_obs=True):
+        """Pick the fastest launch shape for steps over envs 0..n-1; states are restored."""
+        return B.vcs_autotune(self._h, n, steps, want_frames, want_obs)
+
+    def capture(self, n=None, steps=1, env_ids=None, want_frames=False, want_obs=True):
+        return StepGraph(self, n, steps, env_ids, want_frames, want_obs)
+
+
+class StepGraph:
+    """`steps` consecutive step calls captured in one HIP graph with fixed
+    buffers: write actions into `.actions` ([steps, n]) and call launch()."""
+
+    def __init__(self, env, n=None, steps=1, env_ids=None, want_frames=False, want_obs=True):
+        dev = env.device
+        self.env = env
+        self.ids = None if env_ids is None else torch.as_tensor(env_ids, dtype=torch.int32, device=dev).contiguous()
+        n = self.ids.numel() if self.ids is not None else (env.num_envs if n is None else n)
+        self.n, self.steps = n, steps
+        self.actions = torch.zeros((steps, n), dtype=torch.uint8, device=dev)
+        self.obs = torch.empty((steps, n, 84, 84), dtype=torch.uint8, device=dev) if want_obs else None
+        self.reward = torch.empty((steps, n), dtype=torch.int32, device=dev)
+        self.done = torch.empty((steps, n), dtype=torch.uint8, device=dev)
+        self.frames = (torch.empty((steps, n, env.n_slots, 210, 160), dtype=torch.uint8, device=dev)
+                       if want_frames else None)
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        self._g = B.vcs_graph_create(env._h, ptr(self.ids), self.actions.data_ptr(), n, steps, ptr(self.obs),
+                                     self.reward.data_ptr(), self.done.data_ptr(), ptr(self.frames))
+
+    def launch(self, actions=None):
+        if actions is not None:
+            self.actions.copy_(torch.as_tensor(actions, dtype=torch.uint8).reshape(self.steps, self.n))
+        B.vcs_graph_launch(self._g, self.env._stream())
+        return self.obs, self.reward, self.done, self.frames
+
+    def close(self):
+        if getattr(self, "_g", None):
+            B.vcs_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

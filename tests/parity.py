@@ -6,15 +6,16 @@ from helpers import diff_records
 from paper_1907_08467_amd.inputs.palette import GRAY
 
 
-def make_pair(roms, env_rom, **cfg):
-    """roms: [(bytes, scheme)].  Returns (oracle, gpu env) with identical configs."""
+def make_pair(roms, env_rom, gpu_kw=None, **cfg):
+    """roms: [(bytes, scheme)].  Returns (oracle, gpu env) with identical configs
+    (gpu_kw: options of the GPU env only, such as pipelines)."""
     import torch  # noqa: F401
     from paper_1907_08467_amd.env import VcsEnv
     env_rom = np.ascontiguousarray(env_rom, np.uint16)
     o = oracle.Oracle(len(env_rom), GRAY, **cfg)
     o.load_roms(roms)
     o.assign(env_rom)
-    g = VcsEnv(roms, env_rom, GRAY, **cfg)
+    g = VcsEnv(roms, env_rom, GRAY, **cfg, **(gpu_kw or {}))
     return o, g
 
 

@@ -1,0 +1,97 @@
+"""GPU library vs CPU oracle at full env counts, on sampled envs.
+
+The GPU steps every env of the configuration in the launch shape the
+benchmark times (all envs in one call, env ids implicit); the oracle steps
+only a seeded sample of them with the same actions.  Envs are independent
+and every random draw is keyed by (seed, env id, purpose, counter), so the
+sampled envs must agree bit for bit: frames (or the last two frames), obs,
+rewards, done flags and full machine-state records.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import diff_records
+from paper_1907_08467_amd.inputs.palette import GRAY
+from paper_1907_08467_amd.inputs.workloads import config
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sample_envs(env_rom, per_rom, seed):
+    """per_rom env ids of every ROM, plus the first and last env."""
+    rng = np.random.default_rng(seed)
+    out = {0, len(env_rom) - 1}
+    for r in np.unique(env_rom):
+        ids = np.nonzero(env_rom == r)[0]
+        out.update(int(x) for x in rng.choice(ids, size=min(per_rom, ids.size), replace=False))
+    return np.array(sorted(out), np.int32)
+
+
+def run_sampled(c, steps, per_rom, check_every):
+    import torch
+    from paper_1907_08467_amd.env import VcsEnv
+    w = config(c)
+    say("case:", w.name, f"steps {steps}")
+    roms = [(r.data, r.scheme) for r in w.roms()]
+    env_rom = w.env_rom()
+    cfg = dict(frameskip=w.frameskip, sticky_threshold=w.sticky_threshold, seed=w.rng_seed,
+               render_mode=w.render_mode)
+    g = VcsEnv(roms, env_rom, GRAY, **cfg)
+    o = oracle.Oracle(w.n_envs, GRAY, **cfg)
+    o.load_roms(roms)
+    o.assign(env_rom)
+    ids = sample_envs(env_rom, per_rom, c)
+    tid = torch.from_numpy(ids.astype(np.int64)).cuda()
+    acts = w.actions(steps=steps)
+    dev = torch.device("cuda", 0)
+    n = w.n_envs
+    obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
+    rew = torch.empty(n, dtype=torch.int32, device=dev)
+    done = torch.empty(n, dtype=torch.uint8, device=dev)
+    frames = torch.empty((n, g.n_slots, 210, 160), dtype=torch.uint8, device=dev)
+    dones = 0
+    for s in range(steps):
+        a = torch.from_numpy(acts[s]).to(dev)
+        g.step(a, out=(obs, rew, done, frames))
+        oo, orr, od, of = o.step(acts[s][ids], env_ids=ids, want_frames=True)
+        gf = frames.index_select(0, tid).cpu().numpy()
+        go = obs.index_select(0, tid).cpu().numpy()
+        gr = rew.index_select(0, tid).cpu().numpy()
+        gd = done.index_select(0, tid).cpu().numpy()
+        for name, x, y in (("done", gd, od), ("reward", gr, orr), ("obs", go, oo), ("frames", gf, of)):
+            bad = np.nonzero((x != y).reshape(x.shape[0], -1).any(axis=1))[0]
+            assert bad.size == 0, f"c{c} step {s}: {name} differs for envs {ids[bad[:8]].tolist()}"
+        dones += int(od.sum())
+        if s % check_every == 0 or s == steps - 1:
+            for e in ids:
+                a_, b_ = g.get_state(int(e)), o.get_state(int(e))
+                assert np.array_equal(a_, b_), f"c{c} step {s}: state of env {e}: {diff_records(a_, b_)}"
+    errs_g = g.poll_errors()
+    say(f"c{c}: {ids.size} sampled envs x {steps} steps agree; episodes ended among them: {dones}; "
+        f"gpu error bits {errs_g[1]:#x}")
+    assert errs_g[1] == 0
+    g.close()
+    o.close()
+
+
+def test_plain_batch_4096_sampled():
+    """All 4096 envs of the plain batched step, frameskip 4, every frame."""
+    run_sampled(2, steps=60, per_rom=96, check_every=20)
+
+
+def test_divergent_32768_sampled():
+    """32768 envs over 8 ROMs (4 KB and F8), sticky actions p = 0.25."""
+    run_sampled(3, steps=40, per_rom=12, check_every=20)
+
+
+def test_batching_65536_sampled():
+    """65536 envs, 16 ROMs in Zipf populations, last two frames rendered."""
+    run_sampled(4, steps=30, per_rom=6, check_every=15)

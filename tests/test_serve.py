@@ -1,0 +1,116 @@
+"""Request loop of the env server, on the CPU with the oracle as its backend.
+
+The loop logic (merging, the per-env ordering rule, capacity, several
+pipelines in flight) does not depend on the device, so it is checked here
+against solo runs of every request: each served result equals the result of
+the same request run alone, one request at a time in arrival order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_08467_amd.inputs.palette import GRAY
+from paper_1907_08467_amd.inputs.romgen import RomSpec, generate
+from paper_1907_08467_amd.serve import ActorPool, EnvServer, Request, slots_for_budget
+
+
+class OracleBackend:
+    """Batches run on the oracle when launched; a batch reports finished
+    only after `latency` polls, so several pipelines are in flight at once."""
+
+    def __init__(self, o, pipelines, latency):
+        self.o, self.pipelines, self.latency = o, pipelines, latency
+        self.res = [None] * pipelines
+        self.age = [0] * pipelines
+        self.max_inflight = 0
+
+    def launch(self, p, ids, actions):
+        obs, rew, done, _ = self.o.step(actions, env_ids=ids)
+        self.res[p] = (obs, rew, done)
+        self.age[p] = 0
+        self.max_inflight = max(self.max_inflight, sum(r is not None for r in self.res))
+
+    def finished(self, p):
+        if self.res[p] is None:
+            return False
+        self.age[p] += 1
+        return self.age[p] > self.latency
+
+    def results(self, p, lo, hi):
+        obs, rew, done = self.res[p]
+        return obs[lo:hi], rew[lo:hi], done[lo:hi]
+
+    def release(self, p):
+        self.res[p] = None
+
+
+def roms():
+    return [(r.data, r.scheme) for r in (generate(RomSpec(4000, "4k", True)), generate(RomSpec(4001, "f8", True)))]
+
+
+def make_oracle(n, seed=9):
+    o = oracle.Oracle(n, GRAY, frameskip=4, render_mode=1, seed=seed, sticky_threshold=0x40000000)
+    o.load_roms(roms())
+    o.assign(np.arange(n, dtype=np.uint16) % 2)
+    return o
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-4
+        return self.t
+
+
+@pytest.mark.parametrize("pipelines,latency,cap", [(1, 0, 64), (3, 2, 40), (2, 5, 17)])
+def test_served_equals_solo(pipelines, latency, cap):
+    n_envs = 48
+    backend = OracleBackend(make_oracle(n_envs), pipelines, latency)
+    clock = FakeClock()
+    actors = ActorPool(6, n_envs, mean_wait_s=2e-4, size_lo=2, size_hi=16, seed0=77)
+    served = {}
+
+    def keep(req, obs, rew, done):
+        served[req.seq] = (req, obs.copy(), rew.copy(), done.copy())
+        actors.responded(req.client, req.t_done)
+
+    server = EnvServer(backend, max_batch=cap, on_result=keep, clock=clock)
+    actors.start(clock())
+    while server.completed < 120:
+        for r in actors.due(clock()):
+            server.submit(r)
+        server.poll()
+    server.drain()
+    assert server.deferred > 0, "no request ever waited for a conflicting one"
+    if pipelines > 1 and latency > 0:
+        assert backend.max_inflight > 1
+    assert max(server.batch_sizes) <= cap
+    # solo: every request alone, in arrival order, on a fresh oracle
+    solo = make_oracle(n_envs)
+    for seq in sorted(served):
+        req, obs, rew, done = served[seq]
+        o_obs, o_rew, o_done, _ = solo.step(req.actions, env_ids=req.ids)
+        assert np.array_equal(o_done, done), f"request {seq}: done"
+        assert np.array_equal(o_rew, rew), f"request {seq}: reward"
+        assert np.array_equal(o_obs, obs), f"request {seq}: obs"
+    for e in range(n_envs):
+        assert np.array_equal(solo.get_state(e), backend.o.get_state(e)), f"env {e}"
+
+
+def test_submit_checks():
+    backend = OracleBackend(make_oracle(8), 1, 0)
+    server = EnvServer(backend, max_batch=4)
+    with pytest.raises(ValueError):
+        server.submit(Request(0, np.arange(5, dtype=np.int32), np.zeros(5, np.uint8), 0.0))
+    with pytest.raises(ValueError):
+        server.submit(Request(0, np.array([1, 1], np.int32), np.zeros(2, np.uint8), 0.0))
+
+
+def test_budget_sizing():
+    # 16 GiB, 131072 resident envs, 16 ROMs, last-two render, 2 pipelines
+    m = slots_for_budget(16 << 30, 131072, 16, 2, 2)
+    assert 100_000 < m <= 131072
+    with pytest.raises(ValueError):
+        slots_for_budget(1 << 20, 131072, 16, 2, 1)

@@ -36,6 +36,10 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
+    p.add_argument("--workload", choices=["plain", "batching", "serve"], default="plain",
+                   help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
+                        "serve: 131072 resident envs behind the env server")
+    p.add_argument("--serve-seconds", type=float, default=20.0)
     p.add_argument("--launch", type=str, default="auto",
                    help="'auto' (autotuner) or tile_envs,workers,render_block, e.g. 64,0,256")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -71,35 +75,62 @@ def cpu_baseline(w, roms, env_rom, steps):
             "seconds": dt}
 
 
-def main():
-    args = parse()
-    if args.copy_calibration_mib:
-        copy_calibration(args.copy_calibration_mib)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the envs are independent and "
-              "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)
-        sys.exit(2)
-    import torch
+def select_launch(env, args, n, want_frames, want_obs):
+    if args.launch == "auto":
+        launch, tune_ms = env.autotune(n=n, steps=3, want_frames=want_frames, want_obs=want_obs)
+        print(f"autotuner picked {launch} ({tune_ms:.3f} ms/step)", file=sys.stderr, flush=True)
+        return launch, "autotuner"
+    tw, wk, rb = (int(x) for x in args.launch.split(","))
+    env.set_launch(tw, wk, rb)
+    return env.get_launch(), "fixed"
+
+
+def kernel_table(env):
+    kern = {}
+    for k, name in KERNELS.items():
+        ms, cnt = env.kernel_time(k)
+        kern[name] = {"mean_ms": ms, "launches": cnt}
+    return kern
+
+
+def interp_roofline(kern, instr, n, frameskip):
+    """The interpreter against the chip's integer lane-op issue rate."""
+    t = kern["k_interp"]["mean_ms"] * 1e-3
+    rate = instr / t if t > 0 else 0.0
+    return {"bound": "alu", "kernel": "k_interp", "achieved": rate / 1e9, "peak": ALU_LANE_OPS_PEAK / 1e9,
+            "unit": "G emulated instr/s vs G lane-ops/s", "frac": rate / ALU_LANE_OPS_PEAK, "traffic": None,
+            "work_per_launch": f"{instr} emulated 6502 instructions ({n} envs x {frameskip} frames)"}
+
+
+def render_roofline(kern, n, frames_per_step, with_frames):
+    fb = (n * frames_per_step * 210 * 160 if with_frames else 0) + n * 84 * 84
+    t = (kern["k_render_frames"]["mean_ms"] + kern["k_render_obs"]["mean_ms"]) * 1e-3
+    r = {"bound": "hbm", "algorithmic_bytes_written": fb, "achieved_GBs": fb / t / 1e9 if t > 0 else 0.0,
+         "peak_GBs": HBM_PEAK_GBS}
+    r["frac"] = r["achieved_GBs"] / HBM_PEAK_GBS
+    return r
+
+
+def gpu_env(w, **kw):
     from paper_1907_08467_amd.env import VcsEnv
     from paper_1907_08467_amd.inputs.palette import GRAY
-    from paper_1907_08467_amd.inputs.workloads import config
+    roms = [(r.data, r.scheme) for r in w.roms()]
+    env_rom = w.env_rom()
+    env = VcsEnv(roms, env_rom, GRAY, frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode,
+                 sticky_threshold=w.sticky_threshold, **kw)
+    return env, roms, env_rom
 
+
+def bench_plain(args):
+    import torch
+    from paper_1907_08467_amd.inputs.workloads import config
     w = config(2)
     if args.envs != w.n_envs:
         w.n_envs = args.envs
-    roms = [(r.data, r.scheme) for r in w.roms()]
-    env_rom = w.env_rom()
+    env, roms, env_rom = gpu_env(w)
     dev = torch.device("cuda", 0)
-    env = VcsEnv(roms, env_rom, GRAY, frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode)
     n, K, W = w.n_envs, args.steps, args.warmup
-    if args.launch == "auto":
-        launch, tune_ms = env.autotune(steps=3, want_frames=True, want_obs=True)
-        print(f"autotuner picked {launch} ({tune_ms:.3f} ms/step)", file=sys.stderr, flush=True)
-    else:
-        tw, wk, rb = (int(x) for x in args.launch.split(","))
-        env.set_launch(tw, wk, rb)
-        launch = env.get_launch()
+    launch, launch_from = select_launch(env, args, n, True, True)
     acts = torch.from_numpy(w.actions(steps=K + W)).to(dev)
     obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
     rew = torch.empty(n, dtype=torch.int32, device=dev)
@@ -121,34 +152,16 @@ def main():
     dt = time.perf_counter() - t0
     env.timing(False)
     instr_last, instr_uniform = env.last_step_stats()
-    kern = {}
-    for k, name in KERNELS.items():
-        ms, cnt = env.kernel_time(k)
-        kern[name] = {"mean_ms": ms, "launches": cnt}
-    raw_frames = n * w.frameskip * K
-    value = raw_frames / dt
+    kern = kernel_table(env)
+    value = n * w.frameskip * K / dt
     first, bits = env.poll_errors()
     print(f"timed {K} steps in {dt:.3f}s; errors {bits:#x}", file=sys.stderr, flush=True)
-
-    # dominant kernel = the interpreter: emulated instructions per launch over its mean duration
-    t_interp = kern["k_interp"]["mean_ms"] * 1e-3
-    instr_rate = instr_last / t_interp if t_interp > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": "k_interp", "achieved": instr_rate / 1e9,
-                "peak": ALU_LANE_OPS_PEAK / 1e9, "unit": "G emulated instr/s vs G lane-ops/s",
-                "frac": instr_rate / ALU_LANE_OPS_PEAK, "traffic": None,
-                "work_per_launch": f"{instr_last} emulated 6502 instructions ({n} envs x {w.frameskip} frames)"}
-    # render + observation kernels against HBM
-    fb = n * w.frameskip * 210 * 160 + n * 84 * 84
-    t_render = (kern["k_render_frames"]["mean_ms"] + kern["k_render_obs"]["mean_ms"]) * 1e-3
-    render = {"bound": "hbm", "algorithmic_bytes_written": fb,
-              "achieved_GBs": fb / t_render / 1e9 if t_render > 0 else 0.0, "peak_GBs": HBM_PEAK_GBS}
-    render["frac"] = render["achieved_GBs"] / HBM_PEAK_GBS
 
     cpu = None
     if not args.no_cpu_baseline:
         print(f"cpu baseline: oracle, {args.cpu_steps} steps", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, roms, env_rom, args.cpu_steps)
-    line = {
+    return {
         "metric": "raw emulated frames/s on 1 MI355X (p50/p99 step latency in served mode)",
         "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -157,15 +170,166 @@ def main():
                                f"{w.frameskip}, every 210x160 frame rendered to HBM + 84x84 max-of-two gray obs, "
                                "random actions (seed 1), no sticky actions",
                    "num_envs": n, "frameskip": w.frameskip, "render": "all frames",
-                   "launch": launch, "launch_from": "autotuner" if args.launch == "auto" else "fixed"},
-        "roofline": roofline,
-        "render_roofline": render,
+                   "launch": launch, "launch_from": launch_from},
+        "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
+        "render_roofline": render_roofline(kern, n, w.frameskip, True),
         "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
         "emulated_instr_per_step": instr_last,
         "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
+        "errors": bits,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line))
+
+
+def bench_batching(args):
+    """Uneven populations over 16 mixed ROMs, last two frames rendered, obs
+    only: the plain kernel (64 envs per wave, eager steps) against the
+    batching form (autotuned shape, graph-captured steps) on the same inputs."""
+    import torch
+    from paper_1907_08467_amd.inputs.workloads import config
+    w = config(4)
+    n = w.n_envs
+    G = 4                                    # steps per captured graph
+    K = max(G, args.steps - args.steps % G)
+    W = args.warmup
+    dev = torch.device("cuda", 0)
+    acts = torch.from_numpy(w.actions(steps=K + W)).to(dev)
+    res = {}
+    finals = {}
+    for form in ("plain", "batching"):
+        env, roms, env_rom = gpu_env(w)
+        if form == "plain":
+            env.set_launch(64, 0, 256)
+            launch, launch_from = env.get_launch(), "fixed"
+        else:
+            launch, launch_from = select_launch(env, args, n, False, True)
+        obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
+        rew = torch.empty(n, dtype=torch.int32, device=dev)
+        done = torch.empty(n, dtype=torch.uint8, device=dev)
+        for s in range(W):
+            env.step(acts[s], out=(obs, rew, done, None))
+        torch.cuda.synchronize()
+        print(f"{form}: warmup done ({W} steps)", file=sys.stderr, flush=True)
+        if form == "plain":
+            env.timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(K):
+                env.step(acts[W + s], out=(obs, rew, done, None))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            env.timing(False)
+            kern = kernel_table(env)
+            last = (obs, rew, done)
+        else:
+            graph = env.capture(n=n, steps=G, want_obs=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(0, K, G):
+                graph.actions.copy_(acts[W + s:W + s + G])
+                graph.launch()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            last = (graph.obs[G - 1], graph.reward[G - 1], graph.done[G - 1])
+            # kernel durations of the same shape, measured eagerly
+            env.timing(True)
+            for s in range(G):
+                env.step(acts[s], out=(obs, rew, done, None))
+            torch.cuda.synchronize()
+            env.timing(False)
+            kern = kernel_table(env)
+        instr_last, instr_uniform = env.last_step_stats()
+        bits = env.poll_errors()[1]
+        finals[form] = [t.cpu().numpy() for t in last]
+        res[form] = {"value": n * w.frameskip * K / dt, "ms_per_step": dt / K * 1e3, "launch": launch,
+                     "launch_from": launch_from, "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
+                     "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
+                     "render_roofline": render_roofline(kern, n, 2, False), "errors": bits}
+        print(f"{form}: {res[form]['value']:.4g} raw frames/s", file=sys.stderr, flush=True)
+        del env
+        torch.cuda.empty_cache()
+    same = all(np.array_equal(a, b) for a, b in zip(finals["plain"], finals["batching"]))
+    b = res["batching"]
+    return {
+        "metric": "raw emulated frames/s on 1 MI355X (p50/p99 step latency in served mode)",
+        "value": b["value"], "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"batching form: {n} envs over 16 synthetic ROMs (8 x 4 KB, 8 x F8) in Zipf 1.2 "
+                               "populations, frameskip 4, last two frames rendered into the 84x84 obs, "
+                               f"random actions (seed 3); {G}-step HIP graphs, autotuned launch",
+                   "num_envs": n, "frameskip": w.frameskip, "render": "last two", "launch": b["launch"],
+                   "launch_from": b["launch_from"], "graph_steps": G},
+        "roofline": b["roofline"], "render_roofline": b["render_roofline"], "kernels_ms": b["kernels_ms"],
+        "plain_kernel": res["plain"], "speedup_vs_plain": b["value"] / res["plain"]["value"],
+        "last_step_identical_to_plain": bool(same), "errors": b["errors"] | res["plain"]["errors"],
+        "cpu_baseline": None,
+    }
+
+
+def bench_serve(args):
+    """131072 resident envs, 64 closed-loop actors, continuous batching."""
+    import torch
+    from paper_1907_08467_amd.inputs.workloads import config
+    from paper_1907_08467_amd.serve import ActorPool, EnvServer, GpuBackend, run_served, slots_for_budget
+    w = config(5)
+    n = w.n_envs
+    budget = 16 << 30
+    pipes = 2
+    cap = slots_for_budget(budget - (512 << 20), n, 16, 2, pipes)   # 512 MiB kept for tile tables and tuning
+    env, roms, env_rom = gpu_env(w, max_batch=cap, pipelines=pipes, hbm_budget_bytes=budget)
+    dev = torch.device("cuda", 0)
+    launch, launch_from = select_launch(env, args, min(cap, 16384), False, True)
+    # the fixed-batch reference: 65536 listed envs per step, eager
+    m = min(65536, cap)
+    ids = torch.arange(m, dtype=torch.int32, device=dev)
+    acts = torch.from_numpy(w.actions(steps=12, n=m)).to(dev)
+    out = (torch.empty((m, 84, 84), dtype=torch.uint8, device=dev), torch.empty(m, dtype=torch.int32, device=dev),
+           torch.empty(m, dtype=torch.uint8, device=dev), None)
+    for s in range(2):
+        env.step(acts[s], env_ids=ids, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(2, 12):
+        env.step(acts[s], env_ids=ids, out=out)
+    torch.cuda.synchronize()
+    fixed_dt = (time.perf_counter() - t0) / 10
+    fixed = {"envs_per_step": m, "ms_per_step": fixed_dt * 1e3, "value": m * w.frameskip / fixed_dt}
+    print(f"fixed batch: {fixed}", file=sys.stderr, flush=True)
+
+    backend = GpuBackend(env, cap)
+    server = EnvServer(backend, cap)
+    actors = ActorPool(64, n, mean_wait_s=2e-3, size_lo=64, size_hi=4096, seed0=5000)
+    st = run_served(server, actors, seconds=args.serve_seconds)
+    value = st["env_steps"] * w.frameskip / st["seconds"]
+    bits = env.poll_errors()[1]
+    print(f"served: {st}", file=sys.stderr, flush=True)
+    return {
+        "metric": "raw emulated frames/s on 1 MI355X + p50/p99 step latency (served mode)",
+        "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": st["batches"], "warmup": 0,
+        "ms_per_step": st["seconds"] / max(1, st["batches"]) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
+        "config": {"workload": f"serving form: {n} resident envs over 16 synthetic ROMs (Zipf 1.2), 64 closed-loop "
+                               "actors, exponential think time (mean 2 ms), requests of floor(exp U(ln 64, ln 4096)) "
+                               f"distinct env ids, continuous batching on {pipes} pipelines, 16 GiB budget",
+                   "num_envs": n, "frameskip": w.frameskip, "render": "last two", "pipelines": pipes,
+                   "max_batch": cap, "launch": launch, "launch_from": launch_from, "seconds": st["seconds"]},
+        "served": st, "fixed_batch": fixed, "errors": bits, "roofline": None, "cpu_baseline": None,
+    }
+
+
+def main():
+    args = parse()
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the envs are independent and "
+              "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve}[args.workload]
+    print(json.dumps(fn(args)))
 
 
 if __name__ == "__main__":

@@ -253,7 +253,7 @@ int build_tiles(vcs_ctx* c, Pipe& P, const int32_t* ids, uint32_t n, int32_t* re
 // (Re)allocate the per-call tile buffers for the current ROM count and width.
 int ensure_tile_buffer(vcs_ctx* c) {
     const uint32_t cap = (c->max_batch + c->launch.tile_envs - 1) / c->launch.tile_envs + c->n_roms;
-    bool have = c->tiles_cap >= cap;
+    bool have = c->tiles_cap >= cap && c->tiles_cap / 4 <= cap;
     for (auto& P : c->pipes) have = have && P.d_tiles;
     if (have) return VCS_OK;
     for (auto& P : c->pipes) {
@@ -940,6 +940,7 @@ int vcs_autotune(vcs_ctx* c, uint32_t n, uint32_t steps, int want_frames, int wa
     auto consider = [&](const vcs_launch& l) -> int {
         double ms = 0;
         int r = measure(l, &ms);
+        if (r == VCS_E_BUDGET) return VCS_OK;   // this shape's tile tables do not fit: skip it
         if (r) return r;
         if (ms < best_ms) {
             best_ms = ms;

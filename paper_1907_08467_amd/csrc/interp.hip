@@ -761,8 +761,10 @@ __device__ __forceinline__ bool is_rmw_op(uint32_t mn) {
 
 // Runs instructions for the lanes in exec (which agree on the control
 // state) until they split or a frame ends.  On return `c` holds every
-// lane's state; `ended`/`end_t` mark lanes whose frame ended.
-__device__ __forceinline__ void run_fast(Cpu& c, const Wave& W, const uint2* pre, bool& ended, uint32_t& end_t) {
+// lane's state; `ended`/`end_t` mark lanes whose frame ended.  Returns false
+// when it made no progress (the first instruction is one this path leaves to
+// the per-lane path, which must then execute it in the same iteration).
+__device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint2* pre, bool& ended, uint32_t& end_t) {
     Fast F;
     F.pc = rfl(c.pc);
     F.bank = rfl(c.bank);
@@ -773,11 +775,13 @@ __device__ __forceinline__ void run_fast(Cpu& c, const Wave& W, const uint2* pre
     F.ocnt = rfl(c.open_cnt);
     F.logon = rfl(c.log != nullptr ? 1u : 0u) != 0;
     bool lane_pc = false;          // the last instruction left per-lane pc/cyc in c
+    bool progress = false;
     for (;;) {
         if (F.cyc >= F.cap) {
             c.err |= ERR_FRAME_CAP;
             ended = true;
             end_t = F.cyc - 1;
+            progress = true;
             break;
         }
         const uint32_t off = F.pc & 0xFFF;
@@ -926,6 +930,7 @@ __device__ __forceinline__ void run_fast(Cpu& c, const Wave& W, const uint2* pre
                 c.icount++;
                 c.ucount++;
                 lane_pc = true;
+                progress = true;
                 break;
             }
             t = F.cyc + n - 1;
@@ -933,6 +938,7 @@ __device__ __forceinline__ void run_fast(Cpu& c, const Wave& W, const uint2* pre
             handled = false;                            // (zp,x), (zp),y, jmp (ind)
         }
         if (!handled) break;                            // the per-lane path executes it
+        progress = true;
         c.icount++;
         c.ucount++;
         if (lane_pc) {                                  // RTS to differing targets
@@ -962,6 +968,7 @@ __device__ __forceinline__ void run_fast(Cpu& c, const Wave& W, const uint2* pre
     c.bank = F.bank;
     c.open_row = (int32_t)F.orow - 1;
     c.open_cnt = F.ocnt;
+    return progress;
 }
 
 __device__ __forceinline__ uint32_t bcd_value(uint32_t b) { return 10 * (b >> 4) + (b & 15); }
@@ -1109,10 +1116,8 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint2* __
                 const uint32_t oc0 = rfl(c.open_cnt), lg0 = rfl(c.log != nullptr ? 1u : 0u);
                 const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == cy0 && c.fl == fl0 &&
                                   c.open_row == or0 && c.open_cnt == oc0 && (c.log != nullptr ? 1u : 0u) == lg0;
-                if (__builtin_amdgcn_ballot_w64(!same) == 0) {
-                    run_fast(c, W, pre_all + (size_t)rom_id * kRomSlot, ended, end_t);
-                    uni = true;
-                }
+                if (__builtin_amdgcn_ballot_w64(!same) == 0)
+                    uni = run_fast(c, W, pre_all + (size_t)rom_id * kRomSlot, ended, end_t);
             }
             const bool ran_uniform = __any(uni);
             const uint32_t tmin = ran_uniform ? 0u : wave_min(active ? c.cyc : 0xFFFFFFFFu);
@@ -1173,6 +1178,14 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint2* __
                         end_t = t;
                     }
                 }
+            }
+            // Every iteration moves some lane on (the earliest lane always
+            // runs); if none moved, stop the wave's frames with an error
+            // instead of spinning.
+            if (!__any(want || uni || ended) && active) {
+                c.err |= ERR_FRAME_CAP;
+                ended = true;
+                end_t = c.cyc;
             }
             if (ended) {
                 if (c.log) log_close(c, W, end_t);

@@ -298,7 +298,7 @@ def bench_serve(args):
     print(f"fixed batch: {fixed}", file=sys.stderr, flush=True)
 
     backend = GpuBackend(env, cap)
-    server = EnvServer(backend, cap)
+    server = EnvServer(backend, cap, n)
     actors = ActorPool(64, n, mean_wait_s=2e-3, size_lo=64, size_hi=4096, seed0=5000)
     st = run_served(server, actors, seconds=args.serve_seconds)
     value = st["env_steps"] * w.frameskip / st["seconds"]

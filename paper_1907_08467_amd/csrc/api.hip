@@ -65,7 +65,7 @@ struct vcs_ctx {
     // ROMs
     uint32_t n_roms = 0;
     uint8_t* d_roms = nullptr;
-    uint2* d_pre = nullptr;
+    uint32_t* d_pre = nullptr;
     uint32_t* d_schemes = nullptr;
     std::vector<uint32_t> h_schemes;
     std::vector<uint8_t> h_roms;   // [n_roms][kRomSlot]
@@ -490,7 +490,7 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
     dev_free(c, c->d_roms, (size_t)c->n_roms * kRomSlot);
-    dev_free(c, c->d_pre, (size_t)c->n_roms * kRomSlot * sizeof(uint2));
+    dev_free(c, c->d_pre, (size_t)c->n_roms * kRomSlot * sizeof(uint32_t));
     dev_free(c, c->d_schemes, (size_t)c->n_roms * 4);
     for (auto& P : c->pipes) {
         dev_free(c, P.d_stepw, (size_t)c->stepw_words * 4);

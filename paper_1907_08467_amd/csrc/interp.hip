@@ -751,20 +751,226 @@ __device__ __forceinline__ uint32_t fast_rmw(Cpu& c, uint32_t mn, uint32_t x) {
     return r;
 }
 
-__device__ __forceinline__ bool is_read_op(uint32_t mn) {
+// Outcome of one instruction on the wave-uniform path.
+enum : uint32_t {
+    FS_NEXT = 0,     // executed; F holds the next pc and cycle
+    FS_EXIT = 1,     // not executed: the per-lane path takes this instruction
+    FS_LANE = 2,     // executed; lanes parted, c.pc / c.cyc hold each lane's
+    FS_VSYNC = 3     // executed; VSYNC turned on in the lanes with `vs` set (at cycle tv)
+};
+
+constexpr bool read_mn(int mn) {
     return mn == LDA || mn == LDX || mn == LDY || mn == ADC || mn == SBC || mn == AND || mn == ORA || mn == EOR ||
            mn == CMP || mn == CPX || mn == CPY || mn == BIT;
 }
-__device__ __forceinline__ bool is_rmw_op(uint32_t mn) {
-    return mn == ASL || mn == LSR || mn == ROL || mn == ROR || mn == INC || mn == DEC;
+constexpr bool store_mn(int mn) { return mn == STA || mn == STX || mn == STY; }
+constexpr bool rmw_mn(int mn) { return mn == ASL || mn == LSR || mn == ROL || mn == ROR || mn == INC || mn == DEC; }
+
+template <int MN>
+__device__ __forceinline__ uint32_t store_value(const Cpu& c) {
+    return MN == STA ? c.a : (MN == STX ? c.x : c.y);
 }
 
+// End of an instruction that may have written a TIA register: next pc and
+// cycle (a WSYNC write stalls to the next line start), and VSYNC detection.
+__device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t t, uint32_t wsync, bool on,
+                                                uint32_t& vs, uint32_t& tv) {
+    F.pc = next;
+    F.cyc = wsync ? 76 * (t / 76 + 1) : t + 1;
+    if (__builtin_amdgcn_ballot_w64(on) != 0) {
+        vs = on ? 1u : 0u;
+        tv = t;
+        return FS_VSYNC;
+    }
+    return FS_NEXT;
+}
+
+// One instruction with opcode OP (a compile-time constant, so addressing
+// mode, operation and base cycles are folded) for every lane in exec.
+template <int OP>
+__device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t b1, uint32_t b2, uint32_t& vs,
+                                        uint32_t& tv) {
+    constexpr OpInfo I = decode(OP);
+    constexpr int MD = I.md, MN = I.mn;
+    constexpr uint32_t N = (uint32_t)I.cyc;
+    const uint32_t next = (F.pc + (uint32_t)op_len(MD)) & 0xFFFF;
+    if constexpr (MN == ILL || MN == BRK || MN == RTI || MD == IZX || MD == IZY || MD == IND) {
+        return FS_EXIT;
+    } else if constexpr (MD == IMM) {
+        fast_alu(c, MN, b1);
+        F.pc = next;
+        F.cyc += N;
+        return FS_NEXT;
+    } else if constexpr (MD == ACC) {
+        c.a = fast_rmw(c, MN, c.a);
+        F.pc = next;
+        F.cyc += N;
+        return FS_NEXT;
+    } else if constexpr (MD == IMP) {
+        if constexpr (MN == PHA || MN == PHP) {
+            if (!all_lanes(c.sp >= 0x80)) return FS_EXIT;
+            W.ram[c.ram_off + (c.sp & 0x7F)] = (uint8_t)(MN == PHA ? c.a : (c.p | FB | FU));
+            c.sp = (c.sp - 1) & 0xFF;
+        } else if constexpr (MN == PLA || MN == PLP) {
+            if (!all_lanes(c.sp >= 0x7F && c.sp <= 0xFE)) return FS_EXIT;
+            c.sp = (c.sp + 1) & 0xFF;
+            const uint32_t v = W.ram[c.ram_off + (c.sp & 0x7F)];
+            if constexpr (MN == PLA) {
+                c.a = v;
+                c.p = nz(c.p, v);
+            } else {
+                c.p = (v & ~FB) | FU;
+            }
+        } else if constexpr (MN == RTS) {
+            if (!all_lanes(c.sp >= 0x7F && c.sp <= 0xFD)) return FS_EXIT;
+            const uint32_t lo = W.ram[c.ram_off + ((c.sp + 1) & 0x7F)];
+            const uint32_t hi = W.ram[c.ram_off + ((c.sp + 2) & 0x7F)];
+            c.sp = (c.sp + 2) & 0xFF;
+            const uint32_t tgt = ((lo | (hi << 8)) + 1) & 0xFFFF;
+            const uint32_t t0 = rfl(tgt);
+            if (!all_lanes(tgt == t0)) {
+                c.pc = tgt;
+                c.cyc = F.cyc + N;
+                return FS_LANE;
+            }
+            F.pc = t0;
+            F.cyc += N;
+            return FS_NEXT;
+        } else if constexpr (MN == INX) { c.x = (c.x + 1) & 0xFF; c.p = nz(c.p, c.x); }
+        else if constexpr (MN == INY) { c.y = (c.y + 1) & 0xFF; c.p = nz(c.p, c.y); }
+        else if constexpr (MN == DEX) { c.x = (c.x - 1) & 0xFF; c.p = nz(c.p, c.x); }
+        else if constexpr (MN == DEY) { c.y = (c.y - 1) & 0xFF; c.p = nz(c.p, c.y); }
+        else if constexpr (MN == TAX) { c.x = c.a; c.p = nz(c.p, c.x); }
+        else if constexpr (MN == TAY) { c.y = c.a; c.p = nz(c.p, c.y); }
+        else if constexpr (MN == TXA) { c.a = c.x; c.p = nz(c.p, c.a); }
+        else if constexpr (MN == TYA) { c.a = c.y; c.p = nz(c.p, c.a); }
+        else if constexpr (MN == TSX) { c.x = c.sp; c.p = nz(c.p, c.x); }
+        else if constexpr (MN == TXS) { c.sp = c.x; }
+        else if constexpr (MN == CLC) { c.p &= ~FC; }
+        else if constexpr (MN == SEC) { c.p |= FC; }
+        else if constexpr (MN == CLI) { c.p &= ~FI; }
+        else if constexpr (MN == SEI) { c.p |= FI; }
+        else if constexpr (MN == CLV) { c.p &= ~FV; }
+        else if constexpr (MN == CLD) { c.p &= ~FD; }
+        else if constexpr (MN == SED) { c.p |= FD; }
+        F.pc = next;
+        F.cyc += N;
+        return FS_NEXT;
+    } else if constexpr (MD == ZP || MD == ABS) {
+        const uint32_t ea = MD == ZP ? b1 : (b1 | (b2 << 8));
+        const uint32_t a = ea & 0x1FFF;
+        const uint32_t t = F.cyc + N - 1;
+        if constexpr (MN == JMP) {
+            F.pc = ea;
+            F.cyc += N;
+            return FS_NEXT;
+        } else if constexpr (MN == JSR) {
+            if (!all_lanes(c.sp >= 0x81)) return FS_EXIT;
+            const uint32_t ret = (next - 1) & 0xFFFF;
+            W.ram[c.ram_off + (c.sp & 0x7F)] = (uint8_t)(ret >> 8);
+            W.ram[c.ram_off + ((c.sp - 1) & 0x7F)] = (uint8_t)(ret & 0xFF);
+            c.sp = (c.sp - 2) & 0xFF;
+            F.pc = ea;
+            F.cyc += N;
+            return FS_NEXT;
+        } else if constexpr (read_mn(MN)) {
+            fast_alu(c, MN, fast_rd(c, W, F, a, t));
+            F.pc = next;
+            F.cyc += N;
+            return FS_NEXT;
+        } else if constexpr (store_mn(MN)) {
+            bool wsync = false;
+            const bool on = fast_wr(c, W, F, a, store_value<MN>(c), t, wsync);
+            return fast_finish(F, next, t, wsync ? 1u : 0u, on, vs, tv);
+        } else {
+            static_assert(rmw_mn(MN), "read-modify-write");
+            bool wsync = false;
+            const uint32_t v = fast_rd(c, W, F, a, t);
+            const bool on = fast_wr(c, W, F, a, fast_rmw(c, MN, v), t, wsync);
+            return fast_finish(F, next, t, wsync ? 1u : 0u, on, vs, tv);
+        }
+    } else if constexpr (MD == ZPX || MD == ZPY || MD == ABX || MD == ABY) {
+        const uint32_t idx = (MD == ZPX || MD == ABX) ? c.x : c.y;
+        uint32_t ea;
+        bool cross = false;
+        if constexpr (MD == ZPX || MD == ZPY) {
+            ea = (b1 + idx) & 0xFF;
+        } else {
+            const uint32_t base = b1 | (b2 << 8);
+            ea = (base + idx) & 0xFFFF;
+            cross = ((base ^ ea) & 0xFF00) != 0;
+        }
+        const uint32_t a = ea & 0x1FFF;
+        const bool in_ram = (a & 0x1280) == 0x0080;
+        if constexpr (read_mn(MN)) {
+            const bool in_cart = (a & 0x1000) && (!W.f8 || ((a & 0xFFF) != 0xFF8 && (a & 0xFFF) != 0xFF9));
+            if (!all_lanes(in_ram || in_cart)) return FS_EXIT;
+        } else {
+            if (!all_lanes(in_ram)) return FS_EXIT;
+        }
+        uint32_t n = N;
+        if constexpr (I.pen) {
+            const uint32_t cr = rfl(cross ? 1u : 0u);
+            if (!all_lanes(cross == (cr != 0))) return FS_EXIT;
+            n += cr;
+        }
+        if constexpr (read_mn(MN)) {
+            const uint32_t v = in_ram ? (uint32_t)W.ram[c.ram_off + (a & 0x7F)]
+                                      : (uint32_t)W.rom[(F.bank << 12) | (a & 0xFFF)];
+            fast_alu(c, MN, v);
+        } else if constexpr (store_mn(MN)) {
+            W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)store_value<MN>(c);
+        } else {
+            static_assert(rmw_mn(MN), "read-modify-write");
+            uint8_t* m = &W.ram[c.ram_off + (a & 0x7F)];
+            *m = (uint8_t)fast_rmw(c, MN, *m);
+        }
+        F.pc = next;
+        F.cyc += n;
+        return FS_NEXT;
+    } else {
+        static_assert(MD == REL, "branch");
+        bool taken;
+        if constexpr (MN == BPL) taken = !(c.p & FN);
+        else if constexpr (MN == BMI) taken = (c.p & FN) != 0;
+        else if constexpr (MN == BVC) taken = !(c.p & FV);
+        else if constexpr (MN == BVS) taken = (c.p & FV) != 0;
+        else if constexpr (MN == BCC) taken = !(c.p & FC);
+        else if constexpr (MN == BCS) taken = (c.p & FC) != 0;
+        else if constexpr (MN == BNE) taken = !(c.p & FZ);
+        else taken = (c.p & FZ) != 0;
+        const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
+        const uint32_t extra = 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0);
+        const uint64_t tk = __builtin_amdgcn_ballot_w64(taken);
+        if (tk == 0) {
+            F.pc = next;
+            F.cyc += N;
+            return FS_NEXT;
+        }
+        if (tk == __builtin_amdgcn_ballot_w64(true)) {
+            F.pc = tgt;
+            F.cyc += N + extra;
+            return FS_NEXT;
+        }
+        c.pc = taken ? tgt : next;            // the lanes part here
+        c.cyc = F.cyc + N + (taken ? extra : 0);
+        return FS_LANE;
+    }
+}
+
+#define VCS_FAST_CASE(o) \
+    case (o): st = fop<(o)>(c, W, F, b1, b2, vs, tv); break;
+#define VCS_FAST_4(o) VCS_FAST_CASE(o) VCS_FAST_CASE((o) + 1) VCS_FAST_CASE((o) + 2) VCS_FAST_CASE((o) + 3)
+#define VCS_FAST_16(o) VCS_FAST_4(o) VCS_FAST_4((o) + 4) VCS_FAST_4((o) + 8) VCS_FAST_4((o) + 12)
+#define VCS_FAST_64(o) VCS_FAST_16(o) VCS_FAST_16((o) + 16) VCS_FAST_16((o) + 32) VCS_FAST_16((o) + 48)
+
 // Runs instructions for the lanes in exec (which agree on the control
-// state) until they split or a frame ends.  On return `c` holds every
-// lane's state; `ended`/`end_t` mark lanes whose frame ended.  Returns false
-// when it made no progress (the first instruction is one this path leaves to
-// the per-lane path, which must then execute it in the same iteration).
-__device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint2* pre, bool& ended, uint32_t& end_t) {
+// state) until they part, a frame ends, or an instruction this path leaves
+// to the per-lane path comes up.  On return `c` holds every lane's state;
+// `ended`/`end_t` mark lanes whose frame ended.  Returns false when it made
+// no progress (the per-lane path must then execute the instruction in the
+// same iteration).
+__device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* pre, bool& ended, uint32_t& end_t) {
     Fast F;
     F.pc = rfl(c.pc);
     F.bank = rfl(c.bank);
@@ -774,202 +980,56 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint2* pre
     F.orow = (uint32_t)(rfl(c.open_row) + 1);
     F.ocnt = rfl(c.open_cnt);
     F.logon = rfl(c.log != nullptr ? 1u : 0u) != 0;
-    bool lane_pc = false;          // the last instruction left per-lane pc/cyc in c
-    bool progress = false;
+    uint32_t done_n = 0;       // instructions executed on this path
+    uint32_t st = FS_EXIT;
+    uint32_t vs = 0, tv = 0;
+    bool capped = false;
     for (;;) {
         if (F.cyc >= F.cap) {
-            c.err |= ERR_FRAME_CAP;
-            ended = true;
-            end_t = F.cyc - 1;
-            progress = true;
+            capped = true;
             break;
         }
         const uint32_t off = F.pc & 0xFFF;
-        if (!(F.pc & 0x1000) || off > 0xFFD) break;
-        const uint2 q = pre[(F.bank << 12) | off];
-        const uint32_t qx = rfl(q.x), d = rfl(q.y);
-        const uint32_t b1 = (qx >> 8) & 0xFF, b2 = (qx >> 16) & 0xFF;
-        const uint32_t md = d & 15, mn = (d >> 4) & 63;
-        uint32_t n = (d >> 10) & 7;
-        const uint32_t next = (F.pc + ((d >> 14) & 3)) & 0xFFFF;
-        uint32_t npc = next;
-        bool wsync = false, vs = false;
-        bool handled = true;
-        uint32_t t;
-        if (md == IMP || md == ACC || md == IMM) {
-            t = F.cyc + n - 1;
-            if (md == IMM) {
-                fast_alu(c, mn, b1);
-            } else if (md == ACC) {
-                c.a = fast_rmw(c, mn, c.a);
-            } else {
-                switch (mn) {
-                case INX: c.x = (c.x + 1) & 0xFF; c.p = nz(c.p, c.x); break;
-                case INY: c.y = (c.y + 1) & 0xFF; c.p = nz(c.p, c.y); break;
-                case DEX: c.x = (c.x - 1) & 0xFF; c.p = nz(c.p, c.x); break;
-                case DEY: c.y = (c.y - 1) & 0xFF; c.p = nz(c.p, c.y); break;
-                case TAX: c.x = c.a; c.p = nz(c.p, c.x); break;
-                case TAY: c.y = c.a; c.p = nz(c.p, c.y); break;
-                case TXA: c.a = c.x; c.p = nz(c.p, c.a); break;
-                case TYA: c.a = c.y; c.p = nz(c.p, c.a); break;
-                case TSX: c.x = c.sp; c.p = nz(c.p, c.x); break;
-                case TXS: c.sp = c.x; break;
-                case CLC: c.p &= ~FC; break;
-                case SEC: c.p |= FC; break;
-                case CLI: c.p &= ~FI; break;
-                case SEI: c.p |= FI; break;
-                case CLV: c.p &= ~FV; break;
-                case CLD: c.p &= ~FD; break;
-                case SED: c.p |= FD; break;
-                case NOP: break;
-                case PHA: case PHP: {
-                    if (!all_lanes(c.sp >= 0x80)) { handled = false; break; }
-                    W.ram[c.ram_off + (c.sp & 0x7F)] = (uint8_t)(mn == PHA ? c.a : (c.p | FB | FU));
-                    c.sp = (c.sp - 1) & 0xFF;
-                    break;
-                }
-                case PLA: case PLP: {
-                    if (!all_lanes(c.sp >= 0x7F && c.sp <= 0xFE)) { handled = false; break; }
-                    c.sp = (c.sp + 1) & 0xFF;
-                    const uint32_t v = W.ram[c.ram_off + (c.sp & 0x7F)];
-                    if (mn == PLA) { c.a = v; c.p = nz(c.p, v); }
-                    else c.p = (v & ~FB) | FU;
-                    break;
-                }
-                case RTS: {
-                    if (!all_lanes(c.sp >= 0x7F && c.sp <= 0xFD)) { handled = false; break; }
-                    const uint32_t lo = W.ram[c.ram_off + ((c.sp + 1) & 0x7F)];
-                    const uint32_t hi = W.ram[c.ram_off + ((c.sp + 2) & 0x7F)];
-                    c.sp = (c.sp + 2) & 0xFF;
-                    const uint32_t tgt = ((lo | (hi << 8)) + 1) & 0xFFFF;
-                    const uint32_t t0 = rfl(tgt);
-                    if (all_lanes(tgt == t0)) npc = t0;
-                    else { c.pc = tgt; lane_pc = true; }
-                    break;
-                }
-                default: handled = false; break;      // RTI, BRK, undocumented opcodes
-                }
-            }
-        } else if (md == ZP || md == ABS) {
-            const uint32_t ea = md == ZP ? b1 : (b1 | (b2 << 8));
-            const uint32_t a = ea & 0x1FFF;
-            t = F.cyc + n - 1;
-            if (mn == JMP) {
-                npc = ea;
-            } else if (mn == JSR) {
-                if (!all_lanes(c.sp >= 0x81)) { handled = false; }
-                else {
-                    const uint32_t ret = (next - 1) & 0xFFFF;
-                    W.ram[c.ram_off + (c.sp & 0x7F)] = (uint8_t)(ret >> 8);
-                    W.ram[c.ram_off + ((c.sp - 1) & 0x7F)] = (uint8_t)(ret & 0xFF);
-                    c.sp = (c.sp - 2) & 0xFF;
-                    npc = ea;
-                }
-            } else if (is_read_op(mn)) {
-                fast_alu(c, mn, fast_rd(c, W, F, a, t));
-            } else if (mn == STA || mn == STX || mn == STY) {
-                vs = fast_wr(c, W, F, a, mn == STA ? c.a : (mn == STX ? c.x : c.y), t, wsync);
-            } else {                                    // read-modify-write
-                const uint32_t v = fast_rd(c, W, F, a, t);
-                vs = fast_wr(c, W, F, a, fast_rmw(c, mn, v), t, wsync);
-            }
-        } else if (md == ZPX || md == ZPY || md == ABX || md == ABY) {
-            const uint32_t idx = (md == ZPX || md == ABX) ? c.x : c.y;
-            uint32_t ea;
-            bool cross = false;
-            if (md == ZPX || md == ZPY) {
-                ea = (b1 + idx) & 0xFF;
-            } else {
-                const uint32_t base = b1 | (b2 << 8);
-                ea = (base + idx) & 0xFFFF;
-                cross = ((base ^ ea) & 0xFF00) != 0;
-            }
-            const uint32_t a = ea & 0x1FFF;
-            const bool in_ram = (a & 0x1280) == 0x0080;
-            const bool in_cart = (a & 0x1000) && (!W.f8 || ((a & 0xFFF) != 0xFF8 && (a & 0xFFF) != 0xFF9));
-            const bool rd_op = is_read_op(mn);
-            const bool pen = (d >> 13) & 1;
-            if (!all_lanes(in_ram || (rd_op && in_cart)) || (pen && !all_lanes(cross == (rfl(cross ? 1u : 0u) != 0)))) {
-                handled = false;
-            } else {
-                if (pen && rfl(cross ? 1u : 0u)) n += 1;
-                t = F.cyc + n - 1;
-                if (rd_op) {
-                    const uint32_t v = in_ram ? (uint32_t)W.ram[c.ram_off + (a & 0x7F)]
-                                              : (uint32_t)W.rom[(F.bank << 12) | (a & 0xFFF)];
-                    fast_alu(c, mn, v);
-                } else if (mn == STA || mn == STX || mn == STY) {
-                    W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)(mn == STA ? c.a : (mn == STX ? c.x : c.y));
-                } else {
-                    uint8_t* m = &W.ram[c.ram_off + (a & 0x7F)];
-                    *m = (uint8_t)fast_rmw(c, mn, *m);
-                }
-            }
-        } else if (md == REL) {
-            bool taken;
-            switch (mn) {
-            case BPL: taken = !(c.p & FN); break;
-            case BMI: taken = (c.p & FN) != 0; break;
-            case BVC: taken = !(c.p & FV); break;
-            case BVS: taken = (c.p & FV) != 0; break;
-            case BCC: taken = !(c.p & FC); break;
-            case BCS: taken = (c.p & FC) != 0; break;
-            case BNE: taken = !(c.p & FZ); break;
-            default: taken = (c.p & FZ) != 0; break;
-            }
-            const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
-            const uint32_t extra = 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0);
-            const uint64_t tk = __builtin_amdgcn_ballot_w64(taken);
-            const uint64_t all = __builtin_amdgcn_ballot_w64(true);
-            if (tk == all) {
-                npc = tgt;
-                n += extra;
-            } else if (tk != 0) {
-                c.pc = taken ? tgt : next;            // the lanes part here
-                c.cyc = F.cyc + n + (taken ? extra : 0);
-                c.icount++;
-                c.ucount++;
-                lane_pc = true;
-                progress = true;
-                break;
-            }
-            t = F.cyc + n - 1;
-        } else {
-            handled = false;                            // (zp,x), (zp),y, jmp (ind)
-        }
-        if (!handled) break;                            // the per-lane path executes it
-        progress = true;
-        c.icount++;
-        c.ucount++;
-        if (lane_pc) {                                  // RTS to differing targets
-            c.cyc = t + 1;
+        if (!(F.pc & 0x1000) || off > 0xFFD) {
+            st = FS_EXIT;
             break;
         }
-        F.pc = npc;
-        F.cyc = wsync ? 76 * (t / 76 + 1) : t + 1;
-        const uint64_t vsm = __builtin_amdgcn_ballot_w64(vs);
-        if (vsm != 0) {
-            if (vs) {
-                ended = true;
-                end_t = t;
-            }
-            if (vsm != __builtin_amdgcn_ballot_w64(true)) {      // only some lanes' frames ended
-                c.pc = F.pc;
-                c.cyc = F.cyc;
-                lane_pc = true;
-            }
-            break;
+        const uint32_t q = pre[(F.bank << 12) | off];
+        const uint32_t op = q & 0xFF, b1 = (q >> 8) & 0xFF, b2 = (q >> 16) & 0xFF;
+        switch (op) {
+            VCS_FAST_64(0x00)
+            VCS_FAST_64(0x40)
+            VCS_FAST_64(0x80)
+            VCS_FAST_64(0xC0)
         }
+        if (st != FS_NEXT) break;
+        ++done_n;
     }
-    if (!lane_pc) {
+    if (capped) {
+        c.err |= ERR_FRAME_CAP;
+        ended = true;
+        end_t = F.cyc - 1;
+    }
+    if (st == FS_LANE || st == FS_VSYNC) ++done_n;
+    if (st == FS_VSYNC && vs) {               // these lanes' frames end; the others go on
+        ended = true;
+        end_t = tv;
+    }
+    if (st != FS_LANE) {                      // pc and cycle are still common to all lanes
         c.pc = F.pc;
         c.cyc = F.cyc;
     }
+    c.icount += done_n;
+    c.ucount += done_n;
     c.bank = F.bank;
     c.open_row = (int32_t)F.orow - 1;
     c.open_cnt = F.ocnt;
-    return progress;
+    return done_n > 0 || capped;
 }
+#undef VCS_FAST_64
+#undef VCS_FAST_16
+#undef VCS_FAST_4
+#undef VCS_FAST_CASE
 
 __device__ __forceinline__ uint32_t bcd_value(uint32_t b) { return 10 * (b >> 4) + (b & 15); }
 
@@ -998,7 +1058,7 @@ __device__ __forceinline__ uint32_t take_tile(uint32_t* queue) {
     return __builtin_amdgcn_readfirstlane(t);
 }
 
-__global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint2* __restrict__ pre_all) {
+__global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t* __restrict__ pre_all) {
     __shared__ uint32_t s_rom[kRomSlot / 4 + 4];
     __shared__ uint32_t s_ram[kLanes * kRamStride / 4];
     __shared__ uint32_t s_tia[kLanes * kTiaStride / 4];
@@ -1247,19 +1307,19 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint2* __
     }
 }
 
-// Predecoded ROM: for every bank offset, opcode | b1 << 8 | b2 << 16 and the
-// opcode's decode word (entries past offset $FFD are never used).
-__global__ void k_predecode(const uint8_t* roms, uint32_t n_roms, uint2* pre) {
+// Predecoded ROM: for every bank offset, opcode | b1 << 8 | b2 << 16 (the
+// instruction that starts there; entries past offset $FFD are never used).
+__global__ void k_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_roms * (uint32_t)kRomSlot) return;
     const uint32_t r = i / kRomSlot, o = i % kRomSlot, bank = o >> 12, off = o & 0xFFF;
     const uint8_t* rom = roms + (size_t)r * kRomSlot + (bank << 12);
     const uint32_t op = rom[off];
     const uint32_t b1 = off + 1 < 4096 ? rom[off + 1] : 0, b2 = off + 2 < 4096 ? rom[off + 2] : 0;
-    pre[i] = make_uint2(op | (b1 << 8) | (b2 << 16), kDecode.w[op]);
+    pre[i] = op | (b1 << 8) | (b2 << 16);
 }
 
-void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint2* pre, hipStream_t s) {
+void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre, hipStream_t s) {
     const uint32_t n = n_roms * (uint32_t)kRomSlot;
     hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, roms, n_roms, pre);
 }

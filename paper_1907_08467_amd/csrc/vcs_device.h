@@ -73,7 +73,7 @@ struct InterpArgs {
     DevEnv* envs;
     const uint8_t* roms;      // [n_roms][kRomSlot]
     const uint32_t* schemes;  // [n_roms]
-    const uint2* pre;         // [n_roms][kRomSlot] predecoded ROM
+    const uint32_t* pre;      // [n_roms][kRomSlot] predecoded ROM
     const uint8_t* actions;   // [n outputs]; NULL = NOOP
     const uint16_t* nframes_per_out;  // [n outputs] or NULL
     uint32_t nframes;         // frames per step when nframes_per_out is NULL
@@ -136,7 +136,7 @@ struct ResetArgs {
 
 // host launchers (one per kernel)
 void launch_interp(const InterpArgs& a, uint32_t grid, hipStream_t s);
-void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint2* pre, hipStream_t s);
+void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre, hipStream_t s);
 void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s);
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s);
 void launch_reset(const ResetArgs& a, hipStream_t s);

@@ -1,19 +1,22 @@
 """Serving form: an env server with continuous batching over resident envs.
 
 Many actors send step requests (a set of env ids and one action each) at
-their own pace.  The request loop merges waiting requests into batches, runs
-each batch as one step call on one of the library's pipelines, and admits new
-requests into the next batch of any pipeline whose previous batch finished,
-while batches on other pipelines are still on the device.  All machine state
-stays on the device; a request's observations, rewards and done flags are
-handed to its callback as device views.
+their own pace.  The request loop keeps a queue of pending env-steps and
+merges them into batches: whenever one of the library's step pipelines is
+free, every pending env-step that may run now goes into its next batch, while
+batches on other pipelines are still on the device.  A request completes when
+all of its env-steps have; its observations, rewards and done flags are
+gathered on the device into the request's own buffers.  All machine state
+stays on the device.
 
-Ordering rule (what makes served results equal to solo results): a request
-is admitted only if none of its envs is in a batch on the device or in an
-earlier request still waiting.  So every env takes its steps in the order its
-requests arrived, and since envs are independent and every random draw is
-keyed by the env's own id and counters, each result equals the one the same
-request gets when run alone in that per-env order.
+Ordering rule (what makes served results equal to solo results): an env-step
+may run only when its env is in no batch on the device and no earlier request
+still holds an unrun step of that env.  Every env therefore takes its steps
+in the order its requests arrived, and since envs are independent and every
+random draw is keyed by the env's own id and counters, each result equals the
+one the same request gets when run alone, one request at a time in arrival
+order.  Requests are split at env granularity, so two requests that share a
+few envs still run their other envs in the same batch.
 
 Admission by memory: each pipeline's scratch holds `max_batch` env-steps;
 `slots_for_budget` sizes max_batch from a fixed device-memory budget.
@@ -58,36 +61,46 @@ class Request:
     t_arrival: float
     seq: int = 0
     t_done: float = 0.0
+    sched: np.ndarray | None = None   # env-steps already put into a batch
+    left: int = 0                     # env-steps not finished yet
+    out: tuple | None = None          # (obs, reward, done) buffers of the request
 
 
 class GpuBackend:
-    """Runs merged batches on the library's pipelines, one HIP stream each."""
+    """Runs merged batches on the library's pipelines, one HIP stream each.
+
+    Request buffers live on the caller's current stream: gathers into them
+    are enqueued there after the batch's event, and a pipeline's next batch
+    waits for the gathers from its previous one."""
 
     def __init__(self, env, max_batch):
         import torch
         self.torch = torch
         self.env = env
         self.pipelines = env.pipelines
-        dev = env.device
-        self.streams = [torch.cuda.Stream(dev) for _ in range(self.pipelines)]
-        pin = dict(dtype=torch.int32, pin_memory=True)
-        self.h_ids = [torch.empty(max_batch, **pin) for _ in range(self.pipelines)]
-        self.h_act = [torch.empty(max_batch, dtype=torch.uint8, pin_memory=True) for _ in range(self.pipelines)]
-        self.d_ids = [torch.empty(max_batch, dtype=torch.int32, device=dev) for _ in range(self.pipelines)]
-        self.d_act = [torch.empty(max_batch, dtype=torch.uint8, device=dev) for _ in range(self.pipelines)]
-        self.obs = [torch.empty((max_batch, 84, 84), dtype=torch.uint8, device=dev) for _ in range(self.pipelines)]
-        self.rew = [torch.empty(max_batch, dtype=torch.int32, device=dev) for _ in range(self.pipelines)]
-        self.done = [torch.empty(max_batch, dtype=torch.uint8, device=dev) for _ in range(self.pipelines)]
-        self.events = [None] * self.pipelines
+        dev = self.dev = env.device
+        P = self.pipelines
+        self.streams = [torch.cuda.Stream(dev) for _ in range(P)]
+        self.h_ids = [torch.empty(max_batch, dtype=torch.int32, pin_memory=True) for _ in range(P)]
+        self.h_act = [torch.empty(max_batch, dtype=torch.uint8, pin_memory=True) for _ in range(P)]
+        self.d_ids = [torch.empty(max_batch, dtype=torch.int32, device=dev) for _ in range(P)]
+        self.d_act = [torch.empty(max_batch, dtype=torch.uint8, device=dev) for _ in range(P)]
+        self.obs = [torch.empty((max_batch, 84, 84), dtype=torch.uint8, device=dev) for _ in range(P)]
+        self.rew = [torch.empty(max_batch, dtype=torch.int32, device=dev) for _ in range(P)]
+        self.done = [torch.empty(max_batch, dtype=torch.uint8, device=dev) for _ in range(P)]
+        self.events = [None] * P
+        self.gathered = [None] * P
 
     def launch(self, p, ids, actions):
         torch = self.torch
         n = ids.size
         st = self.streams[p]
-        # the host staging buffers of pipeline p are free: its previous batch finished
+        # pipeline p's previous batch has finished, so its host staging buffers are free
         self.h_ids[p][:n].numpy()[:] = ids
         self.h_act[p][:n].numpy()[:] = actions
         with torch.cuda.stream(st):
+            if self.gathered[p] is not None:
+                st.wait_event(self.gathered[p])
             self.d_ids[p][:n].copy_(self.h_ids[p][:n], non_blocking=True)
             self.d_act[p][:n].copy_(self.h_act[p][:n], non_blocking=True)
             out = (self.obs[p][:n], self.rew[p][:n], self.done[p][:n], None)
@@ -99,95 +112,127 @@ class GpuBackend:
     def finished(self, p):
         return self.events[p] is not None and self.events[p].query()
 
-    def results(self, p, lo, hi):
-        return self.obs[p][lo:hi], self.rew[p][lo:hi], self.done[p][lo:hi]
+    def alloc(self, k):
+        t = self.torch
+        return (t.empty((k, 84, 84), dtype=t.uint8, device=self.dev), t.empty(k, dtype=t.int32, device=self.dev),
+                t.empty(k, dtype=t.uint8, device=self.dev))
+
+    def scatter(self, out, pos, p, lo, hi):
+        torch = self.torch
+        cur = torch.cuda.current_stream(self.dev)
+        cur.wait_event(self.events[p])
+        if hi - lo == out[1].numel():                 # the whole request ran in this batch, in order
+            out[0].copy_(self.obs[p][lo:hi])
+            out[1].copy_(self.rew[p][lo:hi])
+            out[2].copy_(self.done[p][lo:hi])
+        else:
+            idx = torch.from_numpy(pos.astype(np.int64)).to(self.dev, non_blocking=True)
+            out[0].index_copy_(0, idx, self.obs[p][lo:hi])
+            out[1].index_copy_(0, idx, self.rew[p][lo:hi])
+            out[2].index_copy_(0, idx, self.done[p][lo:hi])
 
     def release(self, p):
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(self.dev))
+        self.gathered[p] = ev
         self.events[p] = None
 
 
 class EnvServer:
-    """The request loop.  `on_result(req, obs, reward, done)` runs when a
-    request's batch has finished; the views are valid during the call only."""
+    """The request loop.  `on_result(req, obs, reward, done)` runs when the
+    last env-step of a request has finished, with the request's buffers."""
 
-    def __init__(self, backend, max_batch, on_result=None, clock=time.perf_counter):
+    def __init__(self, backend, max_batch, num_envs, on_result=None, clock=time.perf_counter):
         self.backend = backend
         self.max_batch = max_batch
+        self.num_envs = num_envs
         self.on_result = on_result
         self.clock = clock
-        self.pending = collections.deque()
-        self.inflight = [None] * backend.pipelines     # (batch requests, offsets)
-        self.busy = set()                               # envs in batches on the device
+        self.pending = []                               # requests with unscheduled env-steps
+        self.inflight = [None] * backend.pipelines      # parts (request, positions, lo, hi)
+        self.busy = np.zeros(num_envs, dtype=bool)      # env in a batch on the device
+        self.stamp = np.zeros(num_envs, dtype=np.int64) # merge pass that last claimed the env
+        self.passes = 0
         self.seq = 0
         self.completed = 0
         self.env_steps = 0
         self.batches = 0
         self.batch_sizes = []
-        self.deferred = 0          # times a waiting request was passed over by a batch
+        self.deferred = 0          # env-steps held back by an earlier step of their env
 
     def submit(self, req: Request):
-        if req.ids.size > self.max_batch:
-            raise ValueError(f"request of {req.ids.size} envs exceeds the batch capacity {self.max_batch}")
-        if np.unique(req.ids).size != req.ids.size:
+        k = req.ids.size
+        if k == 0:
+            raise ValueError("empty request")
+        if req.ids.min() < 0 or req.ids.max() >= self.num_envs:
+            raise ValueError("env id out of range")
+        if np.unique(req.ids).size != k:
             raise ValueError("a request lists an env twice")
         req.seq = self.seq
         self.seq += 1
+        req.sched = np.zeros(k, dtype=bool)
+        req.left = k
+        req.out = self.backend.alloc(k)
         self.pending.append(req)
 
     def _merge(self):
-        """Admit waiting requests in arrival order under the ordering rule."""
-        taken, blocked = [], set()
+        """One batch of env-steps that may run now, in arrival order."""
+        self.passes += 1
+        stamp = self.passes
+        parts, ids, acts = [], [], []
         size = 0
-        keep = collections.deque()
-        while self.pending:
-            r = self.pending.popleft()
-            ids = r.ids.tolist()
-            fits = size + len(ids) <= self.max_batch
-            free = fits and not any((e in self.busy) or (e in blocked) for e in ids)
-            if free:
-                taken.append(r)
-                size += len(ids)
-                self.busy.update(ids)
-            else:
-                keep.append(r)
-                blocked.update(ids)
-                self.deferred += 1
+        for r in self.pending:
             if size == self.max_batch:
                 break
-        keep.extend(self.pending)
-        self.pending = keep
-        return taken, size
+            un = np.flatnonzero(~r.sched)
+            e = r.ids[un]
+            ok = ~self.busy[e] & (self.stamp[e] != stamp)
+            pos = un[ok][:self.max_batch - size]
+            self.deferred += int(un.size - pos.size)
+            self.stamp[e] = stamp                      # later requests may not pass these envs
+            if pos.size:
+                r.sched[pos] = True
+                self.busy[r.ids[pos]] = True
+                parts.append((r, pos, size, size + pos.size))
+                ids.append(r.ids[pos])
+                acts.append(r.actions[pos])
+                size += pos.size
+        self.pending = [r for r in self.pending if not r.sched.all()]
+        if not parts:
+            return None
+        return parts, np.concatenate(ids).astype(np.int32), np.concatenate(acts).astype(np.uint8)
 
     def poll(self):
-        """Finish batches that are done and start new ones; returns requests finished."""
+        """Finish batches that are done and start new ones; returns requests completed."""
         finished = 0
         for p in range(self.backend.pipelines):
-            cur = self.inflight[p]
-            if cur is not None and self.backend.finished(p):
-                reqs, offs = cur
-                now = self.clock()
-                for r, lo in zip(reqs, offs):
+            parts = self.inflight[p]
+            if parts is None or not self.backend.finished(p):
+                continue
+            now = self.clock()
+            for r, pos, lo, hi in parts:
+                self.backend.scatter(r.out, pos, p, lo, hi)
+                self.busy[r.ids[pos]] = False
+                r.left -= pos.size
+                if r.left == 0:
                     r.t_done = now
+                    self.completed += 1
+                    finished += 1
                     if self.on_result is not None:
-                        self.on_result(r, *self.backend.results(p, lo, lo + r.ids.size))
-                    self.busy.difference_update(r.ids.tolist())
-                self.backend.release(p)
-                self.inflight[p] = None
-                self.completed += len(reqs)
-                finished += len(reqs)
+                        self.on_result(r, *r.out)
+            self.backend.release(p)
+            self.inflight[p] = None
         for p in range(self.backend.pipelines):
             if self.inflight[p] is None and self.pending:
-                reqs, size = self._merge()
-                if not reqs:
+                m = self._merge()
+                if m is None:
                     break
-                ids = np.concatenate([r.ids for r in reqs]).astype(np.int32)
-                act = np.concatenate([r.actions for r in reqs]).astype(np.uint8)
-                offs = np.concatenate([[0], np.cumsum([r.ids.size for r in reqs])[:-1]]).tolist()
-                self.backend.launch(p, ids, act)
-                self.inflight[p] = (reqs, offs)
-                self.env_steps += size
+                parts, ids, acts = m
+                self.backend.launch(p, ids, acts)
+                self.inflight[p] = parts
+                self.env_steps += ids.size
                 self.batches += 1
-                self.batch_sizes.append(size)
+                self.batch_sizes.append(ids.size)
         return finished
 
     def idle(self):

@@ -42,13 +42,14 @@ def test_served_equals_solo_gpu():
     def keep(req, obs, rew, done):
         served[req.seq] = (req, obs.cpu().numpy(), rew.cpu().numpy(), done.cpu().numpy())
 
-    server = EnvServer(backend, cap, on_result=keep)
+    server = EnvServer(backend, cap, n_envs, on_result=keep)
     actors = ActorPool(8, n_envs, mean_wait_s=3e-4, size_lo=16, size_hi=256, seed0=900)
     t0 = time.perf_counter()
     stats = run_served(server, actors, seconds=1.5)
     say("served:", stats, f"deferred {server.deferred}", f"wall {time.perf_counter() - t0:.2f}s")
     assert stats["requests"] == len(served) > 20
     assert server.deferred > 0
+    assert max(server.batch_sizes) <= cap
 
     solo = VcsEnv(roms, env_rom, GRAY, max_batch=cap, **cfg)
     o = oracle.Oracle(n_envs, GRAY, **cfg)

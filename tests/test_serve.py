@@ -36,9 +36,12 @@ class OracleBackend:
         self.age[p] += 1
         return self.age[p] > self.latency
 
-    def results(self, p, lo, hi):
-        obs, rew, done = self.res[p]
-        return obs[lo:hi], rew[lo:hi], done[lo:hi]
+    def alloc(self, k):
+        return np.zeros((k, 84, 84), np.uint8), np.zeros(k, np.int32), np.zeros(k, np.uint8)
+
+    def scatter(self, out, pos, p, lo, hi):
+        for dst, src in zip(out, self.res[p]):
+            dst[pos] = src[lo:hi]
 
     def release(self, p):
         self.res[p] = None
@@ -76,14 +79,14 @@ def test_served_equals_solo(pipelines, latency, cap):
         served[req.seq] = (req, obs.copy(), rew.copy(), done.copy())
         actors.responded(req.client, req.t_done)
 
-    server = EnvServer(backend, max_batch=cap, on_result=keep, clock=clock)
+    server = EnvServer(backend, max_batch=cap, num_envs=n_envs, on_result=keep, clock=clock)
     actors.start(clock())
     while server.completed < 120:
         for r in actors.due(clock()):
             server.submit(r)
         server.poll()
     server.drain()
-    assert server.deferred > 0, "no request ever waited for a conflicting one"
+    assert server.deferred > 0, "no env-step ever waited for an earlier step of its env"
     if pipelines > 1 and latency > 0:
         assert backend.max_inflight > 1
     assert max(server.batch_sizes) <= cap
@@ -101,11 +104,31 @@ def test_served_equals_solo(pipelines, latency, cap):
 
 def test_submit_checks():
     backend = OracleBackend(make_oracle(8), 1, 0)
-    server = EnvServer(backend, max_batch=4)
+    server = EnvServer(backend, max_batch=4, num_envs=8)
     with pytest.raises(ValueError):
-        server.submit(Request(0, np.arange(5, dtype=np.int32), np.zeros(5, np.uint8), 0.0))
+        server.submit(Request(0, np.array([1, 8], np.int32), np.zeros(2, np.uint8), 0.0))
     with pytest.raises(ValueError):
         server.submit(Request(0, np.array([1, 1], np.int32), np.zeros(2, np.uint8), 0.0))
+    with pytest.raises(ValueError):
+        server.submit(Request(0, np.zeros(0, np.int32), np.zeros(0, np.uint8), 0.0))
+
+
+def test_requests_larger_than_a_batch_are_split():
+    """A request of more envs than one batch holds runs over several batches."""
+    backend = OracleBackend(make_oracle(16), 2, 1)
+    got = {}
+    server = EnvServer(backend, max_batch=5, num_envs=16, on_result=lambda r, o, rw, d: got.update({r.seq: rw}))
+    rng = np.random.default_rng(3)
+    reqs = [Request(0, rng.permutation(16)[:12].astype(np.int32), rng.integers(0, 18, 12).astype(np.uint8), 0.0)
+            for _ in range(3)]
+    for r in reqs:
+        server.submit(r)
+    server.drain()
+    assert max(server.batch_sizes) <= 5 and len(got) == 3
+    solo = make_oracle(16)
+    for r in reqs:
+        _, rew, _, _ = solo.step(r.actions, env_ids=r.ids)
+        assert np.array_equal(rew, got[r.seq])
 
 
 def test_budget_sizing():

@@ -242,6 +242,7 @@ def bench_batching(args):
         bits = env.poll_errors()[1]
         finals[form] = [t.cpu().numpy() for t in last]
         res[form] = {"value": n * w.frameskip * K / dt, "ms_per_step": dt / K * 1e3, "launch": launch,
+                     "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
                      "launch_from": launch_from, "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
                      "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
                      "render_roofline": render_roofline(kern, n, 2, False), "errors": bits}
@@ -261,6 +262,7 @@ def bench_batching(args):
                    "num_envs": n, "frameskip": w.frameskip, "render": "last two", "launch": b["launch"],
                    "launch_from": b["launch_from"], "graph_steps": G},
         "roofline": b["roofline"], "render_roofline": b["render_roofline"], "kernels_ms": b["kernels_ms"],
+        "uniform_mode_fraction": b["uniform_mode_fraction"],
         "plain_kernel": res["plain"], "speedup_vs_plain": b["value"] / res["plain"]["value"],
         "last_step_identical_to_plain": bool(same), "errors": b["errors"] | res["plain"]["errors"],
         "cpu_baseline": None,

@@ -592,6 +592,8 @@ __device__ __forceinline__ void apply_queue(Cpu& c, const Wave& W, uint32_t t) {
 }
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint32_t rdl(uint32_t v, int lane) { return (uint32_t)__builtin_amdgcn_readlane((int)v, lane); }
+__device__ __forceinline__ int32_t rdl(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 __device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ------------------------------------------------------- wave-uniform path
@@ -609,6 +611,8 @@ struct Fast {
     uint32_t pc, bank, cyc, cap, orow, ocnt;
     int32_t fl;
     bool logon;
+    uint32_t partial;   // 1: other running lanes are elsewhere; stop at the next line start
+    uint32_t stop;
 };
 
 __device__ __forceinline__ bool all_lanes(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
@@ -777,6 +781,7 @@ __device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t
                                                 uint32_t& vs, uint32_t& tv) {
     F.pc = next;
     F.cyc = wsync ? 76 * (t / 76 + 1) : t + 1;
+    F.stop = wsync & F.partial;
     if (__builtin_amdgcn_ballot_w64(on) != 0) {
         vs = on ? 1u : 0u;
         tv = t;
@@ -966,12 +971,17 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
 
 // Runs instructions for the lanes in exec (which agree on the control
 // state) until they part, a frame ends, or an instruction this path leaves
-// to the per-lane path comes up.  On return `c` holds every lane's state;
-// `ended`/`end_t` mark lanes whose frame ended.  Returns false when it made
-// no progress (the per-lane path must then execute the instruction in the
-// same iteration).
-__device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* pre, bool& ended, uint32_t& end_t) {
+// to the per-lane path comes up; when other running lanes of the wave are
+// elsewhere (`partial`), also at the first WSYNC, so that lanes that took
+// different paths through a scanline meet again at the next line start.  On
+// return `c` holds every lane's state; `ended`/`end_t` mark lanes whose frame
+// ended.  Returns false when it made no progress (the per-lane path must then
+// execute the instruction in the same iteration).
+__device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* pre, bool& ended, uint32_t& end_t,
+                                         uint32_t partial) {
     Fast F;
+    F.partial = partial;
+    F.stop = 0;
     F.pc = rfl(c.pc);
     F.bank = rfl(c.bank);
     F.cyc = rfl(c.cyc);
@@ -1004,6 +1014,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
         }
         if (st != FS_NEXT) break;
         ++done_n;
+        if (F.stop) break;
     }
     if (capped) {
         c.err |= ERR_FRAME_CAP;
@@ -1168,19 +1179,21 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             uint32_t op = 0, b1 = 0, b2 = 0;
             bool want = false, ended = false;
             uint32_t end_t = 0;
-            // wave-uniform mode when every running lane is at the same place
+            // Scalar mode for the group of running lanes at exactly the place
+            // of the earliest one (the whole wave when all lanes agree).
             bool uni = false;
+            const uint32_t tmin = wave_min(active ? c.cyc : 0xFFFFFFFFu);
             if (active) {
-                const uint32_t pc0 = rfl(c.pc), bk0 = rfl(c.bank), cy0 = rfl(c.cyc);
-                const int32_t fl0 = rfl(c.fl), or0 = rfl(c.open_row);
-                const uint32_t oc0 = rfl(c.open_cnt), lg0 = rfl(c.log != nullptr ? 1u : 0u);
-                const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == cy0 && c.fl == fl0 &&
+                const int lead = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(c.cyc == tmin));
+                const uint32_t pc0 = rdl(c.pc, lead), bk0 = rdl(c.bank, lead);
+                const int32_t fl0 = rdl(c.fl, lead), or0 = rdl(c.open_row, lead);
+                const uint32_t oc0 = rdl(c.open_cnt, lead), lg0 = rdl(c.log != nullptr ? 1u : 0u, lead);
+                const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == tmin && c.fl == fl0 &&
                                   c.open_row == or0 && c.open_cnt == oc0 && (c.log != nullptr ? 1u : 0u) == lg0;
-                if (__builtin_amdgcn_ballot_w64(!same) == 0)
-                    uni = run_fast(c, W, pre_all + (size_t)rom_id * kRomSlot, ended, end_t);
+                const uint32_t partial = __builtin_amdgcn_ballot_w64(!same) != 0 ? 1u : 0u;
+                if (same) uni = run_fast(c, W, pre_all + (size_t)rom_id * kRomSlot, ended, end_t, partial);
             }
             const bool ran_uniform = __any(uni);
-            const uint32_t tmin = ran_uniform ? 0u : wave_min(active ? c.cyc : 0xFFFFFFFFu);
             const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;
             if (go) {
                 if (c.cyc >= c.cap) {

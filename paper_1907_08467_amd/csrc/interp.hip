@@ -610,32 +610,39 @@ __device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_read
 struct Fast {
     uint32_t pc, bank, cyc, cap, orow, ocnt;
     int32_t fl;
-    bool logon;
+    uint32_t logon;
     uint32_t partial;   // 1: other running lanes are elsewhere; stop at the next line start
     uint32_t stop;
 };
 
 __device__ __forceinline__ bool all_lanes(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
 
-// TIA write of per-lane `v` to scalar register `reg` at scalar cycle t.
-// Returns the per-lane "VSYNC turned on" flag; sets `wsync`.
-__device__ __forceinline__ bool fast_tia(Cpu& c, const Wave& W, Fast& F, uint32_t reg, uint32_t v, uint32_t t,
-                                         bool& wsync) {
-    uint8_t* R = W.tia + c.tia_off;
-    switch (reg) {
-    case 0x00: {
-        const bool on = (v & 2) && !(c.vsync & 2);
-        c.vsync = v;
-        return on;
+// Stores the scalar path leaves to the per-lane path: VSYNC (it may end the
+// frame), the horizontal-motion registers, HMOVE, and timer writes.  They
+// are rare, and keeping them out leaves the per-lane VSYNC, motion and timer
+// state untouched inside the scalar loop.
+__device__ __forceinline__ uint32_t fast_store_ok(uint32_t a) {
+    if (a & 0x1000) return 1;                             // cartridge: bank hotspots only
+    if (!(a & 0x80)) {                                    // TIA
+        const uint32_t reg = a & 0x3F;
+        return (reg != 0x00 && reg != 0x20 && reg != 0x21 && reg != 0x2A && reg != 0x2B) ? 1u : 0u;
     }
-    case 0x02: wsync = true; return false;
-    case 0x20: c.hmp0 = v; return false;
-    case 0x21: c.hmp1 = v; return false;
-    case 0x2B: c.hmp0 = 0; c.hmp1 = 0; return false;
-    default: break;
+    if (!(a & 0x200)) return 1;                           // RAM
+    return (a & 0x14) != 0x14 ? 1u : 0u;                  // RIOT: everything but the timer
+}
+
+// TIA write of per-lane `v` to scalar register `reg` at scalar cycle t (a
+// register fast_store_ok accepts).  Sets `wsync`.  Returns false, before
+// changing anything, when the row-log entry would not fit (the per-lane path
+// then records the error).
+__device__ __forceinline__ uint32_t fast_tia(Cpu& c, const Wave& W, Fast& F, uint32_t reg, uint32_t v, uint32_t t,
+                                             uint32_t& wsync) {
+    if (reg == 0x02) {
+        wsync = 1;
+        return 1;
     }
     uint32_t code;
-    uint32_t v0 = v, v1 = 0;
+    uint32_t v0 = v;
     const uint32_t ln = (t + 1) / 76;
     const uint32_t h = 3 * (t + 1 - 76 * ln);
     if (reg >= 0x06 && reg <= 0x0F) code = reg - 0x06;
@@ -645,16 +652,14 @@ __device__ __forceinline__ bool fast_tia(Cpu& c, const Wave& W, Fast& F, uint32_
     else if (reg == 0x10 || reg == 0x11) {
         code = reg == 0x10 ? R_P0X : R_P1X;
         v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
-    } else if (reg == 0x2A) {
-        code = R_HMOVE;
-        const int32_t d0 = sext8(c.hmp0 & 0xF0) >> 4, d1 = sext8(c.hmp1 & 0xF0) >> 4;
-        v0 = (uint32_t)(((int32_t)R[R_P0X] - d0 + 160) % 160);
-        v1 = (uint32_t)(((int32_t)R[R_P1X] - d1 + 160) % 160);
     } else {
-        return false;
+        return 1;   // audio, missiles, ball, NUSIZ, VDEL, ... are not rendered
     }
+    uint8_t* R = W.tia + c.tia_off;
     if (F.logon) {
         const int32_t row = (int32_t)ln - F.fl - kFirstRow;
+        const uint32_t entry = (h >= 68 && row >= 0 && row < kRows) ? 1u : 0u;
+        if (entry && (int32_t)F.orow - 1 == row && F.ocnt >= (uint32_t)kRowEntries) return 0;
         int32_t target = h >= 68 ? row : row - 1;
         if (target > kRows - 1) target = kRows - 1;
         while ((int32_t)F.orow <= target) {    // F.orow holds the open row + 1 (0 = none)
@@ -665,23 +670,14 @@ __device__ __forceinline__ bool fast_tia(Cpu& c, const Wave& W, Fast& F, uint32_
             F.orow++;
             F.ocnt = 0;
         }
-        if (h >= 68 && row >= 0 && row < kRows) {
-            if (F.ocnt >= (uint32_t)kRowEntries) {
-                c.err |= ERR_LOG;
-            } else {
-                *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * F.ocnt) =
-                    (h - 68) | (code << 8) | (v0 << 16) | (v1 << 24);
-                F.ocnt++;
-            }
+        if (entry) {
+            *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * F.ocnt) =
+                (h - 68) | (code << 8) | (v0 << 16);
+            F.ocnt++;
         }
     }
-    if (code == R_HMOVE) {
-        R[R_P0X] = (uint8_t)v0;
-        R[R_P1X] = (uint8_t)v1;
-    } else {
-        R[code] = (uint8_t)v0;
-    }
-    return false;
+    R[code] = (uint8_t)v0;
+    return 1;
 }
 
 // Read of scalar address a (13 bits) at scalar cycle t.
@@ -701,27 +697,20 @@ __device__ __forceinline__ uint32_t fast_rd(Cpu& c, const Wave& W, Fast& F, uint
     return riot_read(c, W, a, t);
 }
 
-// Write of per-lane v to scalar address a at scalar cycle t.
-__device__ __forceinline__ bool fast_wr(Cpu& c, const Wave& W, Fast& F, uint32_t a, uint32_t v, uint32_t t,
-                                        bool& wsync) {
+// Write of per-lane v to scalar address a (fast_store_ok) at scalar cycle t.
+// Returns false when the per-lane path must take the instruction.
+__device__ __forceinline__ uint32_t fast_wr(Cpu& c, const Wave& W, Fast& F, uint32_t a, uint32_t v, uint32_t t,
+                                            uint32_t& wsync) {
     if (a & 0x1000) {
         if (W.f8) {
             if ((a & 0xFFF) == 0xFF8) F.bank = 0;
             else if ((a & 0xFFF) == 0xFF9) F.bank = 1;
         }
-        return false;
+        return 1;
     }
     if (!(a & 0x80)) return fast_tia(c, W, F, a & 0x3F, v & 0xFF, t, wsync);
-    if (!(a & 0x200)) {
-        W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
-        return false;
-    }
-    if ((a & 0x14) == 0x14) {
-        c.tv = v & 0xFF;
-        c.tshift = (0x0A060300u >> (8 * (a & 3))) & 0xFF;
-        c.tbase = (int64_t)(c.base + t) + 1;
-    }
-    return false;
+    if (!(a & 0x200)) W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
+    return 1;   // other RIOT writes (ports) change nothing emulated
 }
 
 // Per-lane ALU part of the read-class operations (operand v).
@@ -759,8 +748,7 @@ __device__ __forceinline__ uint32_t fast_rmw(Cpu& c, uint32_t mn, uint32_t x) {
 enum : uint32_t {
     FS_NEXT = 0,     // executed; F holds the next pc and cycle
     FS_EXIT = 1,     // not executed: the per-lane path takes this instruction
-    FS_LANE = 2,     // executed; lanes parted, c.pc / c.cyc hold each lane's
-    FS_VSYNC = 3     // executed; VSYNC turned on in the lanes with `vs` set (at cycle tv)
+    FS_LANE = 2      // executed; lanes parted, c.pc / c.cyc hold each lane's
 };
 
 constexpr bool read_mn(int mn) {
@@ -776,25 +764,18 @@ __device__ __forceinline__ uint32_t store_value(const Cpu& c) {
 }
 
 // End of an instruction that may have written a TIA register: next pc and
-// cycle (a WSYNC write stalls to the next line start), and VSYNC detection.
-__device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t t, uint32_t wsync, bool on,
-                                                uint32_t& vs, uint32_t& tv) {
+// cycle (a WSYNC write stalls to the next line start).
+__device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t t, uint32_t wsync) {
     F.pc = next;
     F.cyc = wsync ? 76 * (t / 76 + 1) : t + 1;
     F.stop = wsync & F.partial;
-    if (__builtin_amdgcn_ballot_w64(on) != 0) {
-        vs = on ? 1u : 0u;
-        tv = t;
-        return FS_VSYNC;
-    }
     return FS_NEXT;
 }
 
 // One instruction with opcode OP (a compile-time constant, so addressing
 // mode, operation and base cycles are folded) for every lane in exec.
 template <int OP>
-__device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t b1, uint32_t b2, uint32_t& vs,
-                                        uint32_t& tv) {
+__device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t b1, uint32_t b2) {
     constexpr OpInfo I = decode(OP);
     constexpr int MD = I.md, MN = I.mn;
     constexpr uint32_t N = (uint32_t)I.cyc;
@@ -884,15 +865,21 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             F.cyc += N;
             return FS_NEXT;
         } else if constexpr (store_mn(MN)) {
-            bool wsync = false;
-            const bool on = fast_wr(c, W, F, a, store_value<MN>(c), t, wsync);
-            return fast_finish(F, next, t, wsync ? 1u : 0u, on, vs, tv);
+            if (!fast_store_ok(a)) return FS_EXIT;
+            uint32_t wsync = 0;
+            if (!fast_wr(c, W, F, a, store_value<MN>(c), t, wsync)) return FS_EXIT;
+            return fast_finish(F, next, t, wsync);
         } else {
             static_assert(rmw_mn(MN), "read-modify-write");
-            bool wsync = false;
+            // a TIA register reads back as an input port or 0: RMW on one is
+            // left to the per-lane path, as are the stores fast_store_ok refuses
+            if (!(a & 0x1000) && !(a & 0x80)) return FS_EXIT;
+            if (!fast_store_ok(a)) return FS_EXIT;
             const uint32_t v = fast_rd(c, W, F, a, t);
-            const bool on = fast_wr(c, W, F, a, fast_rmw(c, MN, v), t, wsync);
-            return fast_finish(F, next, t, wsync ? 1u : 0u, on, vs, tv);
+            const uint32_t r = fast_rmw(c, MN, v);
+            uint32_t wsync = 0;
+            fast_wr(c, W, F, a, r, t, wsync);
+            return fast_finish(F, next, t, wsync);
         }
     } else if constexpr (MD == ZPX || MD == ZPY || MD == ABX || MD == ABY) {
         const uint32_t idx = (MD == ZPX || MD == ABX) ? c.x : c.y;
@@ -964,7 +951,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
 }
 
 #define VCS_FAST_CASE(o) \
-    case (o): st = fop<(o)>(c, W, F, b1, b2, vs, tv); break;
+    case (o): st = fop<(o)>(c, W, F, b1, b2); break;
 #define VCS_FAST_4(o) VCS_FAST_CASE(o) VCS_FAST_CASE((o) + 1) VCS_FAST_CASE((o) + 2) VCS_FAST_CASE((o) + 3)
 #define VCS_FAST_16(o) VCS_FAST_4(o) VCS_FAST_4((o) + 4) VCS_FAST_4((o) + 8) VCS_FAST_4((o) + 12)
 #define VCS_FAST_64(o) VCS_FAST_16(o) VCS_FAST_16((o) + 16) VCS_FAST_16((o) + 32) VCS_FAST_16((o) + 48)
@@ -989,23 +976,47 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
     F.fl = rfl(c.fl);
     F.orow = (uint32_t)(rfl(c.open_row) + 1);
     F.ocnt = rfl(c.open_cnt);
-    F.logon = rfl(c.log != nullptr ? 1u : 0u) != 0;
+    F.logon = rfl(c.log != nullptr ? 1u : 0u);
     uint32_t done_n = 0;       // instructions executed on this path
     uint32_t st = FS_EXIT;
-    uint32_t vs = 0, tv = 0;
-    bool capped = false;
+    uint32_t capped = 0;
+    // Two loops: the inner one handles only the most frequent opcodes of
+    // typical cartridge code, so few values merge at its back edge and the
+    // compiler keeps the state in place; any other opcode goes through the
+    // full dispatch once, then the inner loop resumes.
     for (;;) {
-        if (F.cyc >= F.cap) {
-            capped = true;
-            break;
+        uint32_t op = 0, b1 = 0, b2 = 0;
+        uint32_t cold = 0;
+        for (;;) {
+            if (F.cyc >= F.cap) {
+                capped = 1;
+                break;
+            }
+            if ((F.pc & 0x1FFF) - 0x1000u > 0xFFDu) {   // outside the cartridge, or too close to its end
+                st = FS_EXIT;
+                break;
+            }
+            const uint32_t q = pre[(F.bank << 12) | (F.pc & 0xFFF)];
+            op = q & 0xFF;
+            b1 = (q >> 8) & 0xFF;
+            b2 = (q >> 16) & 0xFF;
+            if (op == 0x85) st = fop<0x85>(c, W, F, b1, b2);           // STA zp
+            else if (op == 0xA5) st = fop<0xA5>(c, W, F, b1, b2);      // LDA zp
+            else if (op == 0xD0) st = fop<0xD0>(c, W, F, b1, b2);      // BNE
+            else if (op == 0xCA) st = fop<0xCA>(c, W, F, b1, b2);      // DEX
+            else if (op == 0x25) st = fop<0x25>(c, W, F, b1, b2);      // AND zp
+            else if (op == 0x65) st = fop<0x65>(c, W, F, b1, b2);      // ADC zp
+            else if (op == 0x45) st = fop<0x45>(c, W, F, b1, b2);      // EOR zp
+            else if (op == 0xA9) st = fop<0xA9>(c, W, F, b1, b2);      // LDA #
+            else {
+                cold = 1;
+                break;
+            }
+            if (st != FS_NEXT) break;
+            ++done_n;
+            if (F.stop) break;
         }
-        const uint32_t off = F.pc & 0xFFF;
-        if (!(F.pc & 0x1000) || off > 0xFFD) {
-            st = FS_EXIT;
-            break;
-        }
-        const uint32_t q = pre[(F.bank << 12) | off];
-        const uint32_t op = q & 0xFF, b1 = (q >> 8) & 0xFF, b2 = (q >> 16) & 0xFF;
+        if (!cold) break;
         switch (op) {
             VCS_FAST_64(0x00)
             VCS_FAST_64(0x40)
@@ -1021,11 +1032,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
         ended = true;
         end_t = F.cyc - 1;
     }
-    if (st == FS_LANE || st == FS_VSYNC) ++done_n;
-    if (st == FS_VSYNC && vs) {               // these lanes' frames end; the others go on
-        ended = true;
-        end_t = tv;
-    }
+    if (st == FS_LANE) ++done_n;
     if (st != FS_LANE) {                      // pc and cycle are still common to all lanes
         c.pc = F.pc;
         c.cyc = F.cyc;

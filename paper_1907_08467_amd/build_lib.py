@@ -10,8 +10,13 @@ SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvcs355.so")
 SOURCES = ["interp.hip", "render.hip", "envops.hip", "api.hip"]
+# Control flow that the compiler can prove wave-uniform (the interpreter's
+# scalar loop) is left as plain scalar branches instead of being rewritten into
+# the structured form divergent code needs, which would add a copy of every
+# live value at each merge point.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-structurizecfg-skip-uniform-regions=true",
          "-I", os.path.join(ROOT, "include")]
 
 

@@ -198,9 +198,12 @@ __device__ __forceinline__ uint32_t riot_read(const Cpu& c, const Wave& W, uint3
     }
     const int64_t e = (int64_t)(c.base + t) - c.tbase;
     const int64_t lim = (int64_t)(c.tv + 1) << c.tshift;
-    const bool expired = e >= lim;
-    if (a & 1) return expired ? 0x80u : 0u;
-    return expired ? (uint32_t)((0xFF - (e - lim)) & 0xFF) : (uint32_t)(c.tv - (uint32_t)(e >> c.tshift)) & 0xFF;
+    // both outcomes computed and masked: no per-lane branch
+    const uint32_t m = 0u - (uint32_t)(e >= lim);
+    if (a & 1) return m & 0x80u;
+    const uint32_t after = (uint32_t)(0xFF - (e - lim)) & 0xFF;
+    const uint32_t before = (uint32_t)(c.tv - (uint32_t)(e >> c.tshift)) & 0xFF;
+    return (after & m) | (before & ~m);
 }
 
 __device__ __forceinline__ void cart_touch(Cpu& c, const Wave& W, uint32_t a) {
@@ -713,14 +716,65 @@ __device__ __forceinline__ uint32_t fast_wr(Cpu& c, const Wave& W, Fast& F, uint
     return 1;   // other RIOT writes (ports) change nothing emulated
 }
 
-// Per-lane ALU part of the read-class operations (operand v).
-__device__ __forceinline__ void fast_alu(Cpu& c, uint32_t mn, uint32_t v) {
+// Decimal mode of the lanes in exec for ADC/SBC: 0 all binary, 1 all
+// decimal, 2 mixed (the per-lane path then takes the instruction).  Keeping
+// the choice uniform keeps the scalar loop free of per-lane branches.
+__device__ __forceinline__ uint32_t dec_mode(const Cpu& c) {
+    const uint64_t d = __builtin_amdgcn_ballot_w64((c.p & FD) != 0);
+    if (d == 0) return 0;
+    return d == __builtin_amdgcn_ballot_w64(true) ? 1u : 2u;
+}
+
+__device__ __forceinline__ void adc_bin(Cpu& c, uint32_t v) {
+    const uint32_t bin = c.a + v + (c.p & FC);
+    const uint32_t ovf = (c.a ^ bin) & (v ^ bin) & 0x80;
+    c.p = (c.p & ~(FC | FV)) | (bin > 0xFF ? FC : 0) | (ovf ? FV : 0);
+    c.a = bin & 0xFF;
+    c.p = nz(c.p, c.a);
+}
+
+// the decimal ADC and SBC of the per-lane path, for lanes known to be in
+// decimal mode (their arithmetic compiles to selects)
+__device__ __forceinline__ void adc_dec(Cpu& c, uint32_t v) {
+    const uint32_t cin = c.p & FC;
+    const uint32_t bin = c.a + v + cin;
+    int32_t lo = (int32_t)((c.a & 0x0F) + (v & 0x0F) + cin);
+    lo = lo > 9 ? ((lo + 6) & 0x0F) + 0x10 : lo;
+    int32_t sum = (int32_t)(c.a & 0xF0) + (int32_t)(v & 0xF0) + lo;
+    const int32_t ss = sext8(c.a & 0xF0) + sext8(v & 0xF0) + lo;
+    sum = sum >= 0xA0 ? sum + 0x60 : sum;
+    c.p = (c.p & ~(FC | FV | FN | FZ)) | (sum >= 0x100 ? FC : 0) | ((ss < -128 || ss > 127) ? FV : 0) |
+          (ss & 0x80 ? FN : 0) | ((bin & 0xFF) == 0 ? FZ : 0);
+    c.a = (uint32_t)sum & 0xFF;
+}
+
+__device__ __forceinline__ void sbc_any(Cpu& c, uint32_t v, uint32_t dec) {
+    const uint32_t cin = c.p & FC;
+    const uint32_t inv = (~v) & 0xFF;
+    const uint32_t bin = c.a + inv + cin;
+    const uint32_t ovf = (c.a ^ bin) & (inv ^ bin) & 0x80;
+    uint32_t res = bin & 0xFF;
+    if (dec) {
+        int32_t lo = (int32_t)(c.a & 0x0F) - (int32_t)(v & 0x0F) + (int32_t)cin - 1;
+        lo = lo < 0 ? ((lo - 6) & 0x0F) - 0x10 : lo;
+        int32_t d = (int32_t)(c.a & 0xF0) - (int32_t)(v & 0xF0) + lo;
+        d = d < 0 ? d - 0x60 : d;
+        res = (uint32_t)d & 0xFF;
+    }
+    c.p = (c.p & ~(FC | FV)) | (bin > 0xFF ? FC : 0) | (ovf ? FV : 0);
+    c.p = nz(c.p, bin & 0xFF);
+    c.a = res;
+}
+
+// Per-lane ALU part of the read-class operations (operand v); `dm` is the
+// uniform decimal mode (dec_mode) for ADC and SBC.
+__device__ __forceinline__ void fast_alu(Cpu& c, uint32_t mn, uint32_t v, uint32_t dm = 0) {
     switch (mn) {
     case LDA: c.a = v; c.p = nz(c.p, v); break;
     case LDX: c.x = v; c.p = nz(c.p, v); break;
     case LDY: c.y = v; c.p = nz(c.p, v); break;
-    case ADC: do_adc(c, v); break;
-    case SBC: do_sbc(c, v); break;
+    case ADC: if (dm) adc_dec(c, v); else adc_bin(c, v); break;
+    case SBC: sbc_any(c, v, dm); break;
     case AND: c.a &= v; c.p = nz(c.p, c.a); break;
     case ORA: c.a |= v; c.p = nz(c.p, c.a); break;
     case EOR: c.a ^= v; c.p = nz(c.p, c.a); break;
@@ -783,7 +837,12 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
     if constexpr (MN == ILL || MN == BRK || MN == RTI || MD == IZX || MD == IZY || MD == IND) {
         return FS_EXIT;
     } else if constexpr (MD == IMM) {
-        fast_alu(c, MN, b1);
+        uint32_t dm = 0;
+        if constexpr (MN == ADC || MN == SBC) {
+            dm = dec_mode(c);
+            if (dm == 2) return FS_EXIT;
+        }
+        fast_alu(c, MN, b1, dm);
         F.pc = next;
         F.cyc += N;
         return FS_NEXT;
@@ -860,7 +919,12 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             F.cyc += N;
             return FS_NEXT;
         } else if constexpr (read_mn(MN)) {
-            fast_alu(c, MN, fast_rd(c, W, F, a, t));
+            uint32_t dm = 0;
+            if constexpr (MN == ADC || MN == SBC) {
+                dm = dec_mode(c);
+                if (dm == 2) return FS_EXIT;
+            }
+            fast_alu(c, MN, fast_rd(c, W, F, a, t), dm);
             F.pc = next;
             F.cyc += N;
             return FS_NEXT;
@@ -907,9 +971,14 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             n += cr;
         }
         if constexpr (read_mn(MN)) {
-            const uint32_t v = in_ram ? (uint32_t)W.ram[c.ram_off + (a & 0x7F)]
-                                      : (uint32_t)W.rom[(F.bank << 12) | (a & 0xFFF)];
-            fast_alu(c, MN, v);
+            uint32_t dm = 0;
+            if constexpr (MN == ADC || MN == SBC) {
+                dm = dec_mode(c);
+                if (dm == 2) return FS_EXIT;
+            }
+            // one LDS read from RAM or cartridge, whichever each lane's address is in
+            const uint8_t* src = in_ram ? W.ram + c.ram_off + (a & 0x7F) : W.rom + ((F.bank << 12) | (a & 0xFFF));
+            fast_alu(c, MN, *src, dm);
         } else if constexpr (store_mn(MN)) {
             W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)store_value<MN>(c);
         } else {

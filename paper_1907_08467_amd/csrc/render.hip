@@ -68,29 +68,62 @@ __device__ __forceinline__ void apply(Regs& r, uint32_t e) {
     }
 }
 
-__device__ __forceinline__ uint32_t player_bit(uint32_t pos, uint32_t grp, uint32_t refp, uint32_t x) {
-    int32_t d = (int32_t)x - (int32_t)pos;
-    if (d < 0) d += 160;
-    if (d >= 8) return 0;
-    const uint32_t bit = (refp & 8) ? (uint32_t)d : 7u - (uint32_t)d;
-    return (grp >> bit) & 1;
+// Segments are drawn 16 pixels at a time with bit masks: a 16-bit mask per
+// object (bit i = pixel x0 + i), widened to byte masks and combined with one
+// bitfield select per priority level.  A segment is split into runs at the
+// in-row register writes that land inside it.
+
+// four mask bits -> four byte masks (bit j -> 0xFF in byte j)
+__device__ __forceinline__ uint32_t byte_masks(uint32_t n) { return ((n * 0x00204081u) & 0x01010101u) * 0xFFu; }
+
+__device__ __forceinline__ uint32_t rev4(uint32_t n) {
+    return ((n & 1) << 3) | ((n & 2) << 1) | ((n & 4) >> 1) | ((n & 8) >> 3);
 }
 
-__device__ __forceinline__ uint32_t pixel(const Regs& r, uint32_t x) {
-    if (r.outside || (r.vblank & 2)) return 0;
-    const uint32_t right = x >= 80;
-    const uint32_t q = right ? ((r.ctrlpf & 1) ? 19 - ((x - 80) >> 2) : (x - 80) >> 2) : (x >> 2);
-    const uint32_t pf = (r.pfm >> q) & 1;
-    const uint32_t p0 = player_bit(r.p0x, r.grp0, r.refp0, x);
-    const uint32_t p1 = player_bit(r.p1x, r.grp1, r.refp1, x);
+// (m & a) | (~m & b)
+__device__ __forceinline__ uint32_t pick(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
+
+// pixels of player (pos, grp, refp) among x0 .. x0+15: the sprite's pixel d
+// (0..7) sits at x = pos + d (mod 160) and shows bit d of GRP when reflected,
+// bit 7-d otherwise
+__device__ __forceinline__ uint32_t player_mask16(uint32_t pos, uint32_t grp, uint32_t refp, uint32_t x0) {
+    const uint32_t spr = (refp & 8) ? grp : (__builtin_bitreverse32(grp) >> 24);
+    uint32_t r = pos + 160 - x0;          // (pos - x0) mod 160
+    if (r >= 160) r -= 160;
+    uint32_t m = 0;
+    if (r < 16) m = spr << r;
+    if (r > 152) m |= spr >> (160 - r);
+    return m & 0xFFFF;
+}
+
+// the 16 pixels x0 .. x0+15 drawn with registers r (x0 a multiple of 16, so
+// the segment lies in one half of the line)
+__device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0) {
+    if (r.outside || (r.vblank & 2)) return make_uint4(0, 0, 0, 0);
+    const bool right = x0 >= 80;
+    uint32_t n;
+    if (!right) n = (r.pfm >> (x0 >> 2)) & 0xF;
+    else if (!(r.ctrlpf & 1)) n = (r.pfm >> ((x0 - 80) >> 2)) & 0xF;
+    else n = rev4((r.pfm >> (16 - ((x0 - 80) >> 2))) & 0xF);
+    const uint32_t mpf = ((n & 1) | ((n & 2) << 3) | ((n & 4) << 6) | ((n & 8) << 9)) * 0xF;
+    const uint32_t m0 = player_mask16(r.p0x, r.grp0, r.refp0, x0);
+    const uint32_t m1 = player_mask16(r.p1x, r.grp1, r.refp1, x0);
     const uint32_t pfc = (r.ctrlpf & 2) ? (right ? r.colup1 : r.colup0) : r.colupf;
-    uint32_t c;
-    if (r.ctrlpf & 4) c = pf ? pfc : (p0 ? r.colup0 : (p1 ? r.colup1 : r.colubk));
-    else c = p0 ? r.colup0 : (p1 ? r.colup1 : (pf ? pfc : r.colubk));
-    return c & 0xFE;
+    const uint32_t c0 = (r.colup0 & 0xFE) * 0x01010101u, c1 = (r.colup1 & 0xFE) * 0x01010101u;
+    const uint32_t cp = (pfc & 0xFE) * 0x01010101u, cb = (r.colubk & 0xFE) * 0x01010101u;
+    const bool pf_first = (r.ctrlpf & 4) != 0;
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t b0 = byte_masks((m0 >> (4 * k)) & 0xF), b1 = byte_masks((m1 >> (4 * k)) & 0xF);
+        const uint32_t bp = byte_masks((mpf >> (4 * k)) & 0xF);
+        w[k] = pf_first ? pick(bp, cp, pick(b0, c0, pick(b1, c1, cb))) : pick(b0, c0, pick(b1, c1, pick(bp, cp, cb)));
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// 16 pixels of row `row` starting at x0, packed little-endian into a uint4
+// 16 pixels of row `row` starting at x0, packed little-endian into a uint4:
+// the row snapshot, then each logged write from its x position on
 __device__ __forceinline__ uint4 render_segment(const uint8_t* frame_log, int row, uint32_t x0) {
     const uint8_t* rec = frame_log + row * kRowBytes;
     const uint4 s = *reinterpret_cast<const uint4*>(rec);
@@ -98,27 +131,35 @@ __device__ __forceinline__ uint4 render_segment(const uint8_t* frame_log, int ro
     unpack(r, s);
     const uint32_t cnt = (s.w >> 24) & 0x1F;
     const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + 16);
-    uint32_t ei = 0;
-    uint32_t w[4] = {0, 0, 0, 0};
     if (r.outside && cnt == 0) return make_uint4(0, 0, 0, 0);
+    uint32_t ei = 0;
     uint32_t e = cnt ? ents[0] : 0;
-    // entries before the segment
-    while (ei < cnt && (e & 0xFF) <= x0) {
+    while (ei < cnt && (e & 0xFF) <= x0) {          // writes that take effect before the segment
         apply(r, e);
         ++ei;
         e = ei < cnt ? ents[ei] : 0;
     }
-#pragma unroll
-    for (uint32_t i = 0; i < 16; ++i) {
-        const uint32_t x = x0 + i;
-        while (ei < cnt && (e & 0xFF) <= x) {
+    uint4 out = make_uint4(0, 0, 0, 0);
+    uint32_t start = 0;                             // first pixel of the current run
+    for (;;) {
+        const bool more = ei < cnt && (e & 0xFF) < x0 + 16;
+        const uint32_t end = more ? (e & 0xFF) - x0 : 16;
+        const uint4 px = draw16(r, x0);
+        const uint32_t run = ((1u << end) - 1) & ~((1u << start) - 1);
+        out.x = pick(byte_masks(run & 0xF), px.x, out.x);
+        out.y = pick(byte_masks((run >> 4) & 0xF), px.y, out.y);
+        out.z = pick(byte_masks((run >> 8) & 0xF), px.z, out.z);
+        out.w = pick(byte_masks((run >> 12) & 0xF), px.w, out.w);
+        if (!more) break;
+        const uint32_t xe = e & 0xFF;
+        while (ei < cnt && (e & 0xFF) == xe) {      // every write at this pixel, in order
             apply(r, e);
             ++ei;
             e = ei < cnt ? ents[ei] : 0;
         }
-        w[i >> 2] |= pixel(r, x) << (8 * (i & 3));
+        start = end;
     }
-    return make_uint4(w[0], w[1], w[2], w[3]);
+    return out;
 }
 
 // bytewise maximum of two packed 4 x u8 words

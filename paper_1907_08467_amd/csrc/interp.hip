@@ -634,53 +634,87 @@ __device__ __forceinline__ uint32_t fast_store_ok(uint32_t a) {
     return (a & 0x14) != 0x14 ? 1u : 0u;                  // RIOT: everything but the timer
 }
 
-// TIA write of per-lane `v` to scalar register `reg` at scalar cycle t (a
-// register fast_store_ok accepts).  Sets `wsync`.  Returns false, before
-// changing anything, when the row-log entry would not fit (the per-lane path
-// then records the error).
-__device__ __forceinline__ uint32_t fast_tia(Cpu& c, const Wave& W, Fast& F, uint32_t reg, uint32_t v, uint32_t t,
-                                             uint32_t& wsync) {
-    if (reg == 0x02) {
-        wsync = 1;
-        return 1;
+// Store classes of a static address, kept in the predecoded ROM word of a
+// store instruction (its byte 3) so the scalar path needs no address decode.
+constexpr uint32_t SC_RAM = 0, SC_WSYNC = 1, SC_IGNORE = 2, SC_EXIT = 3, SC_CART = 4, SC_TIA = 0x20;
+
+// Class of a store to a (13 bits): RAM, WSYNC, a rendered TIA register (SC_TIA
+// | register code), a write that changes nothing emulated, a cartridge access,
+// or one the scalar path leaves to the per-lane path (fast_store_ok).
+__device__ __forceinline__ uint32_t store_class(uint32_t a) {
+    if (a & 0x1000) return SC_CART;
+    if (!(a & 0x80)) {
+        const uint32_t reg = a & 0x3F;
+        if (reg == 0x02) return SC_WSYNC;
+        if (reg == 0x00 || reg == 0x20 || reg == 0x21 || reg == 0x2A || reg == 0x2B) return SC_EXIT;
+        if (reg >= 0x06 && reg <= 0x0F) return SC_TIA | (reg - 0x06);
+        if (reg == 0x01) return SC_TIA | R_VBLANK;
+        if (reg == 0x1B) return SC_TIA | R_GRP0;
+        if (reg == 0x1C) return SC_TIA | R_GRP1;
+        if (reg == 0x10) return SC_TIA | R_P0X;
+        if (reg == 0x11) return SC_TIA | R_P1X;
+        return SC_IGNORE;   // audio, missiles, ball, NUSIZ, VDEL, ... are not rendered
     }
-    uint32_t code;
-    uint32_t v0 = v;
+    if (!(a & 0x200)) return SC_RAM;
+    return (a & 0x14) == 0x14 ? SC_EXIT : SC_IGNORE;
+}
+
+// Write of per-lane value v to the rendered TIA register `code` at scalar
+// cycle t, with its row-log entry.  Returns 0, before changing anything,
+// when the row-log entry would not fit (the per-lane path then records the
+// error).
+__device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F, uint32_t code, uint32_t v,
+                                                  uint32_t t) {
     const uint32_t ln = (t + 1) / 76;
     const uint32_t h = 3 * (t + 1 - 76 * ln);
-    if (reg >= 0x06 && reg <= 0x0F) code = reg - 0x06;
-    else if (reg == 0x01) code = R_VBLANK;
-    else if (reg == 0x1B) code = R_GRP0;
-    else if (reg == 0x1C) code = R_GRP1;
-    else if (reg == 0x10 || reg == 0x11) {
-        code = reg == 0x10 ? R_P0X : R_P1X;
-        v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
-    } else {
-        return 1;   // audio, missiles, ball, NUSIZ, VDEL, ... are not rendered
-    }
+    uint32_t v0 = v;
+    if (code == R_P0X || code == R_P1X) v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
     uint8_t* R = W.tia + c.tia_off;
     if (F.logon) {
+        // rows before the one the write lands in (its own row too when the
+        // write lands in the visible part) get their snapshots first
         const int32_t row = (int32_t)ln - F.fl - kFirstRow;
-        const uint32_t entry = (h >= 68 && row >= 0 && row < kRows) ? 1u : 0u;
-        if (entry && (int32_t)F.orow - 1 == row && F.ocnt >= (uint32_t)kRowEntries) return 0;
-        int32_t target = h >= 68 ? row : row - 1;
-        if (target > kRows - 1) target = kRows - 1;
-        while ((int32_t)F.orow <= target) {    // F.orow holds the open row + 1 (0 = none)
-            if (F.orow > 0 && F.ocnt) c.log[(F.orow - 1) * kRowBytes + 15] = (uint8_t)F.ocnt;
+        const int32_t vis = h >= 68 ? 1 : 0;
+        int32_t target = row - 1 + vis;
+        target = target > kRows - 1 ? kRows - 1 : target;
+        if ((int32_t)F.orow <= target) {
+            if (F.orow > 0) {
+                if (F.ocnt) c.log[(F.orow - 1) * kRowBytes + 15] = (uint8_t)F.ocnt;
+            }
             const uint32_t* src = reinterpret_cast<const uint32_t*>(R);
-            *reinterpret_cast<uint4*>(c.log + F.orow * kRowBytes) =
-                make_uint4(src[0], src[1], src[2], src[3] & 0x00FFFFFFu);
-            F.orow++;
+            const uint4 snap = make_uint4(src[0], src[1], src[2], src[3] & 0x00FFFFFFu);
+            do {    // F.orow holds the open row + 1 (0 = none)
+                *reinterpret_cast<uint4*>(c.log + F.orow * kRowBytes) = snap;
+                F.orow++;
+            } while ((int32_t)F.orow <= target);
             F.ocnt = 0;
         }
-        if (entry) {
-            *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * F.ocnt) =
-                (h - 68) | (code << 8) | (v0 << 16);
-            F.ocnt++;
+        if (vis) {
+            if ((uint32_t)row < (uint32_t)kRows) {
+                // the row is the open one here; a full row is left to the per-lane path
+                if (F.ocnt >= (uint32_t)kRowEntries) return 0;
+                *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * F.ocnt) =
+                    (h - 68) | (code << 8) | (v0 << 16);
+                F.ocnt++;
+            }
         }
     }
     R[code] = (uint8_t)v0;
     return 1;
+}
+
+// TIA write of per-lane `v` to scalar register `reg` at scalar cycle t (a
+// register fast_store_ok accepts).  Sets `wsync`.  Returns 0 when the
+// per-lane path must take the write (a full row log).
+__device__ __forceinline__ uint32_t fast_tia(Cpu& c, const Wave& W, Fast& F, uint32_t reg, uint32_t v, uint32_t t,
+                                             uint32_t& wsync) {
+    const uint32_t sc = store_class(reg);
+    if (sc == SC_WSYNC) {
+        wsync = 1;
+        return 1;
+    }
+    if (sc < SC_TIA) return 1;
+    return fast_tia_code(c, W, F, sc & 0x1F, v, t);
 }
 
 // Read of scalar address a (13 bits) at scalar cycle t.
@@ -829,7 +863,7 @@ __device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t
 // One instruction with opcode OP (a compile-time constant, so addressing
 // mode, operation and base cycles are folded) for every lane in exec.
 template <int OP>
-__device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t b1, uint32_t b2) {
+__device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t b1, uint32_t b2, uint32_t aux) {
     constexpr OpInfo I = decode(OP);
     constexpr int MD = I.md, MN = I.mn;
     constexpr uint32_t N = (uint32_t)I.cyc;
@@ -929,10 +963,25 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             F.cyc += N;
             return FS_NEXT;
         } else if constexpr (store_mn(MN)) {
-            if (!fast_store_ok(a)) return FS_EXIT;
-            uint32_t wsync = 0;
-            if (!fast_wr(c, W, F, a, store_value<MN>(c), t, wsync)) return FS_EXIT;
-            return fast_finish(F, next, t, wsync);
+            // aux is store_class(a), from the predecoded word
+            const uint32_t v = store_value<MN>(c);
+            if (aux == SC_RAM) {
+                W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
+            } else if (aux >= SC_TIA) {
+                if (!fast_tia_code(c, W, F, aux & 0x1F, v & 0xFF, t)) return FS_EXIT;
+            } else if (aux == SC_WSYNC) {
+                return fast_finish(F, next, t, 1);
+            } else if (aux == SC_EXIT) {
+                return FS_EXIT;
+            } else if (aux == SC_CART) {
+                if (W.f8) {
+                    if ((a & 0xFFF) == 0xFF8) F.bank = 0;
+                    else if ((a & 0xFFF) == 0xFF9) F.bank = 1;
+                }
+            }
+            F.pc = next;
+            F.cyc += N;
+            return FS_NEXT;
         } else {
             static_assert(rmw_mn(MN), "read-modify-write");
             // a TIA register reads back as an input port or 0: RMW on one is
@@ -1020,7 +1069,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
 }
 
 #define VCS_FAST_CASE(o) \
-    case (o): st = fop<(o)>(c, W, F, b1, b2); break;
+    case (o): st = fop<(o)>(c, W, F, b1, b2, aux); break;
 #define VCS_FAST_4(o) VCS_FAST_CASE(o) VCS_FAST_CASE((o) + 1) VCS_FAST_CASE((o) + 2) VCS_FAST_CASE((o) + 3)
 #define VCS_FAST_16(o) VCS_FAST_4(o) VCS_FAST_4((o) + 4) VCS_FAST_4((o) + 8) VCS_FAST_4((o) + 12)
 #define VCS_FAST_64(o) VCS_FAST_16(o) VCS_FAST_16((o) + 16) VCS_FAST_16((o) + 32) VCS_FAST_16((o) + 48)
@@ -1054,7 +1103,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
     // compiler keeps the state in place; any other opcode goes through the
     // full dispatch once, then the inner loop resumes.
     for (;;) {
-        uint32_t op = 0, b1 = 0, b2 = 0;
+        uint32_t op = 0, b1 = 0, b2 = 0, aux = 0;
         uint32_t cold = 0;
         for (;;) {
             if (F.cyc >= F.cap) {
@@ -1069,19 +1118,24 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
             op = q & 0xFF;
             b1 = (q >> 8) & 0xFF;
             b2 = (q >> 16) & 0xFF;
-            if (op == 0x85) st = fop<0x85>(c, W, F, b1, b2);           // STA zp
-            else if (op == 0xA5) st = fop<0xA5>(c, W, F, b1, b2);      // LDA zp
-            else if (op == 0xD0) st = fop<0xD0>(c, W, F, b1, b2);      // BNE
-            else if (op == 0xCA) st = fop<0xCA>(c, W, F, b1, b2);      // DEX
-            else if (op == 0x25) st = fop<0x25>(c, W, F, b1, b2);      // AND zp
-            else if (op == 0x65) st = fop<0x65>(c, W, F, b1, b2);      // ADC zp
-            else if (op == 0x45) st = fop<0x45>(c, W, F, b1, b2);      // EOR zp
-            else if (op == 0xA9) st = fop<0xA9>(c, W, F, b1, b2);      // LDA #
+            aux = q >> 24;
+#define VCS_HOT(o)                                            \
+    if (op == (o)) {                                          \
+        if ((st = fop<(o)>(c, W, F, b1, b2, aux)) != FS_NEXT) break; \
+    }
+            VCS_HOT(0x85)                    // STA zp
+            else VCS_HOT(0xA5)               // LDA zp
+            else VCS_HOT(0xD0)               // BNE
+            else VCS_HOT(0xCA)               // DEX
+            else VCS_HOT(0x25)               // AND zp
+            else VCS_HOT(0x65)               // ADC zp
+            else VCS_HOT(0x45)               // EOR zp
+            else VCS_HOT(0xA9)               // LDA #
             else {
                 cold = 1;
                 break;
             }
-            if (st != FS_NEXT) break;
+#undef VCS_HOT
             ++done_n;
             if (F.stop) break;
         }
@@ -1396,8 +1450,10 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
     }
 }
 
-// Predecoded ROM: for every bank offset, opcode | b1 << 8 | b2 << 16 (the
-// instruction that starts there; entries past offset $FFD are never used).
+// Predecoded ROM: for every bank offset, opcode | b1 << 8 | b2 << 16 |
+// aux << 24 for the instruction that starts there, aux being the store class
+// of the address of a zero-page or absolute STA/STX/STY (0 otherwise).
+// Entries past offset $FFD are never used.
 __global__ void k_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_roms * (uint32_t)kRomSlot) return;
@@ -1405,7 +1461,10 @@ __global__ void k_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre)
     const uint8_t* rom = roms + (size_t)r * kRomSlot + (bank << 12);
     const uint32_t op = rom[off];
     const uint32_t b1 = off + 1 < 4096 ? rom[off + 1] : 0, b2 = off + 2 < 4096 ? rom[off + 2] : 0;
-    pre[i] = op | (b1 << 8) | (b2 << 16);
+    uint32_t aux = 0;
+    if (op == 0x84 || op == 0x85 || op == 0x86) aux = store_class(b1);
+    else if (op == 0x8C || op == 0x8D || op == 0x8E) aux = store_class((b1 | (b2 << 8)) & 0x1FFF);
+    pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24);
 }
 
 void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre, hipStream_t s) {

@@ -23,6 +23,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
+# HBM bytes per launch on the plain 4096-env step, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a 256 MiB copy's readings (read x2.000, write x1.000);
+# reported only while the kernel source is the one they were taken on
+# (sha256 prefix), otherwise null.
+MEASURED_TRAFFIC = {
+    "k_interp": ("interp.hip", "95fcb41f56526262", (1152.0 * 2.0 + 176040.8) * 1024),
+    "k_render_frames": ("render.hip", "5c2c68120efc3504", (94333.8 * 2.0 + 268934.1) * 1024),
+    "k_render_obs": ("render.hip", "5c2c68120efc3504", (94332.6 * 2.0 + 297234.0) * 1024),
+}
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
@@ -73,6 +82,14 @@ def cpu_baseline(w, roms, env_rom, steps):
             "sample": f"{w.n_envs} envs x {steps} steps x frameskip {w.frameskip} ({frames} raw frames), "
                       f"every frame rendered + obs, same cartridge, seed and actions",
             "seconds": dt}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    src, sha, nbytes = MEASURED_TRAFFIC[kernel]
+    path = os.path.join(ROOT, "paper_1907_08467_amd", "csrc", src)
+    with open(path, "rb") as f:
+        return nbytes if hashlib.sha256(f.read()).hexdigest()[:16] == sha else None
 
 
 def select_launch(env, args, n, want_frames, want_obs):
@@ -171,8 +188,11 @@ def bench_plain(args):
                                "random actions (seed 1), no sticky actions",
                    "num_envs": n, "frameskip": w.frameskip, "render": "all frames",
                    "launch": launch, "launch_from": launch_from},
-        "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
-        "render_roofline": render_roofline(kern, n, w.frameskip, True),
+        "roofline": dict(interp_roofline(kern, instr_last, n, w.frameskip),
+                         traffic=measured_traffic("k_interp") if n == 4096 else None),
+        "render_roofline": dict(render_roofline(kern, n, w.frameskip, True),
+                                traffic={k: measured_traffic(k) if n == 4096 else None
+                                         for k in ("k_render_frames", "k_render_obs")}),
         "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
         "emulated_instr_per_step": instr_last,
         "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,

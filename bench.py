@@ -4,7 +4,11 @@ Workload: the plain batched configuration -- 4096 envs of one seeded 4 KB
 synthetic cartridge, frameskip 4, every frame rendered to 210x160 and kept in
 HBM plus the 84x84 gray max-of-two observation, uniform random actions
 (PCG64 seed 1), no sticky actions.  Actions for every timed step are resident
-in HBM before the timed region starts.
+in HBM before the timed region starts.  K eager step calls are timed first
+(with per-kernel HIP events), then K steps run as HIP graphs of G steps
+whose renders overlap the next step's interpreter; the graph rate is the
+value, the eager rate is reported beside it.  --workload batching / serve
+print the batching-form and served-form lines instead.
 
 Prints one JSON line: raw emulated frames/s (= env steps x frameskip / s), the
 roofline of the dominant kernel (timed with HIP events on the launch stream)
@@ -49,6 +53,10 @@ def parse():
                    help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
                         "serve: 131072 resident envs behind the env server")
     p.add_argument("--serve-seconds", type=float, default=20.0)
+    p.add_argument("--graph", type=int, default=4,
+                   help="plain workload: time steps captured G at a time in HIP graphs (two pipelines, each step's "
+                        "render overlapping the next step's interpreter) after the eager steps, and report them as "
+                        "the value; 0 = eager steps only")
     p.add_argument("--launch", type=str, default="auto",
                    help="'auto' (autotuner) or tile_envs,workers,render_block, e.g. 64,0,256")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -144,11 +152,14 @@ def bench_plain(args):
     w = config(2)
     if args.envs != w.n_envs:
         w.n_envs = args.envs
-    env, roms, env_rom = gpu_env(w)
+    G = args.graph
+    env, roms, env_rom = gpu_env(w, pipelines=2 if G else 1)
     dev = torch.device("cuda", 0)
     n, K, W = w.n_envs, args.steps, args.warmup
+    if G:
+        K = max(G, K - K % G)
     launch, launch_from = select_launch(env, args, n, True, True)
-    acts = torch.from_numpy(w.actions(steps=K + W)).to(dev)
+    acts = torch.from_numpy(w.actions(steps=2 * K + W)).to(dev)
     obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
     rew = torch.empty(n, dtype=torch.int32, device=dev)
     done = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -170,9 +181,27 @@ def bench_plain(args):
     env.timing(False)
     instr_last, instr_uniform = env.last_step_stats()
     kern = kernel_table(env)
-    value = n * w.frameskip * K / dt
+    value = eager_value = n * w.frameskip * K / dt
+    eager_ms = dt / K * 1e3
+    print(f"timed {K} eager steps in {dt:.3f}s", file=sys.stderr, flush=True)
+    graph_res = None
+    if G:
+        graph = env.capture(n=n, steps=G, want_frames=True, want_obs=True)
+        for s in range(0, 2 * G, G):        # two untimed launches
+            graph.actions.copy_(acts[W + s:W + s + G])
+            graph.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(0, K, G):
+            graph.actions.copy_(acts[W + K + s:W + K + s + G])
+            graph.launch()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        value = n * w.frameskip * K / dt
+        graph_res = {"value": value, "ms_per_step": dt / K * 1e3, "steps_per_graph": G}
+        print(f"timed {K} graph steps in {dt:.3f}s", file=sys.stderr, flush=True)
     first, bits = env.poll_errors()
-    print(f"timed {K} steps in {dt:.3f}s; errors {bits:#x}", file=sys.stderr, flush=True)
+    print(f"errors {bits:#x}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,13 +210,17 @@ def bench_plain(args):
     return {
         "metric": "raw emulated frames/s on 1 MI355X (p50/p99 step latency in served mode)",
         "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u8", "data": "synthetic",
+        "ms_per_step": n * w.frameskip / value * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"plain batched step: {n} envs x 1 seeded 4 KB synthetic cartridge, frameskip "
                                f"{w.frameskip}, every 210x160 frame rendered to HBM + 84x84 max-of-two gray obs, "
                                "random actions (seed 1), no sticky actions",
                    "num_envs": n, "frameskip": w.frameskip, "render": "all frames",
-                   "launch": launch, "launch_from": launch_from},
+                   "launch": launch, "launch_from": launch_from,
+                   "steps_as": f"HIP graphs of {G} steps, render overlapping the next interpreter" if G
+                   else "eager step calls"},
+        "eager": {"value": eager_value, "ms_per_step": eager_ms},
+        "graph": graph_res,
         "roofline": dict(interp_roofline(kern, instr_last, n, w.frameskip),
                          traffic=measured_traffic("k_interp") if n == 4096 else None),
         "render_roofline": dict(render_roofline(kern, n, w.frameskip, True),
@@ -217,7 +250,7 @@ def bench_batching(args):
     res = {}
     finals = {}
     for form in ("plain", "batching"):
-        env, roms, env_rom = gpu_env(w)
+        env, roms, env_rom = gpu_env(w, pipelines=1 if form == "plain" else 2)
         if form == "plain":
             env.set_launch(64, 0, 256)
             launch, launch_from = env.get_launch(), "fixed"
@@ -278,7 +311,8 @@ def bench_batching(args):
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"batching form: {n} envs over 16 synthetic ROMs (8 x 4 KB, 8 x F8) in Zipf 1.2 "
                                "populations, frameskip 4, last two frames rendered into the 84x84 obs, "
-                               f"random actions (seed 3); {G}-step HIP graphs, autotuned launch",
+                               f"random actions (seed 3); {G}-step HIP graphs on two pipelines (each step's render "
+                               "overlapping the next interpreter), autotuned launch",
                    "num_envs": n, "frameskip": w.frameskip, "render": "last two", "launch": b["launch"],
                    "launch_from": b["launch_from"], "graph_steps": G},
         "roofline": b["roofline"], "render_roofline": b["render_roofline"], "kernels_ms": b["kernels_ms"],

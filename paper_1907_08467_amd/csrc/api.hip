@@ -306,10 +306,11 @@ int check_launch(const vcs_launch* l) {
     return VCS_OK;
 }
 
-// Enqueue one step on stream s with the scratch of pipeline `pipe` (the body
-// of vcs_step; arguments checked).
-int enqueue_step(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
-                 int32_t* reward, uint8_t* done, uint8_t* frames, hipStream_t s) {
+// The emulation part of one step on stream s with the scratch of pipeline
+// `pipe` (arguments checked): counters, id validation and tiles, the
+// interpreter (frames, row logs, reward, done) and the eager reset.
+int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
+                int32_t* reward, uint8_t* done, uint8_t* frames, hipStream_t s) {
     Pipe& P = c->pipes[pipe];
     const Tile* tiles = c->d_tiles_all;
     const uint32_t* n_tiles = c->d_n_tiles_all;
@@ -357,6 +358,33 @@ int enqueue_step(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* a
     launch_interp(ia, grid, s);
     end_timed(c, s);
 
+    // a done env restarts from the cache now (state, and its observation);
+    // the render below leaves done envs' observations alone
+    ResetArgs rs{};
+    rs.envs = c->d_envs;
+    rs.ids = ids;
+    rs.n = n;
+    rs.num_envs = c->cfg.num_envs;
+    rs.info = P.d_info;
+    rs.valid = nullptr;
+    rs.cache_state = c->d_cache_state;
+    rs.cache_obs = c->d_cache_obs;
+    rs.K = c->cfg.reset_cache_k;
+    rs.seed = c->cfg.seed;
+    rs.obs = obs;
+    begin_timed(c, 3, s);
+    launch_reset(rs, s);
+    end_timed(c, s);
+    HIP_OK(hipGetLastError());
+    return VCS_OK;
+}
+
+// Render of one step from pipeline `pipe`'s row logs: frames output and
+// observations.  Needs only that step's interpreter launch; the env state is
+// not touched, so it may overlap the next step's interpreter on another
+// pipeline.
+int enqueue_render(vcs_ctx* c, uint32_t pipe, uint32_t n, uint8_t* obs, uint8_t* frames, hipStream_t s) {
+    Pipe& P = c->pipes[pipe];
     RenderArgs ra{};
     ra.logs = P.d_logs;
     ra.n_slots = c->n_slots;
@@ -376,23 +404,16 @@ int enqueue_step(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* a
         launch_render_obs(ra, c->launch.render_block, s);
         end_timed(c, s);
     }
-    ResetArgs rs{};
-    rs.envs = c->d_envs;
-    rs.ids = ids;
-    rs.n = n;
-    rs.num_envs = c->cfg.num_envs;
-    rs.info = P.d_info;
-    rs.valid = nullptr;
-    rs.cache_state = c->d_cache_state;
-    rs.cache_obs = c->d_cache_obs;
-    rs.K = c->cfg.reset_cache_k;
-    rs.seed = c->cfg.seed;
-    rs.obs = obs;
-    begin_timed(c, 3, s);
-    launch_reset(rs, s);
-    end_timed(c, s);
     HIP_OK(hipGetLastError());
     return VCS_OK;
+}
+
+// One whole step on stream s.
+int enqueue_step(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
+                 int32_t* reward, uint8_t* done, uint8_t* frames, hipStream_t s) {
+    int rc = enqueue_sim(c, pipe, ids, actions, n, obs, reward, done, frames, s);
+    if (!rc) rc = enqueue_render(c, pipe, n, obs, frames, s);
+    return rc;
 }
 
 int check_step_args(vcs_ctx* c, uint32_t n, const uint8_t* actions, const int32_t* reward, const uint8_t* done) {
@@ -1018,15 +1039,51 @@ int vcs_graph_create(vcs_ctx* c, const int32_t* ids, const uint8_t* actions, uin
     }
     const bool timing = c->timing;
     c->timing = false;
+    // With two or more pipelines, step j runs on pipeline j % 2 and its render
+    // goes on a second stream: it overlaps step j+1's interpreter, and step
+    // j+2 (same pipeline scratch) waits for it.
+    const bool overlap = c->pipes.size() >= 2 && steps >= 2;
+    hipStream_t r = nullptr;
+    std::vector<hipEvent_t> ev;
+    auto evt = [&]() -> hipEvent_t {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        ev.push_back(e);
+        return e;
+    };
+    if (overlap && hipStreamCreateWithFlags(&r, hipStreamNonBlocking) != hipSuccess) rc = fail(VCS_E_HIP, "stream");
+    std::vector<hipEvent_t> rendered(steps, nullptr);
     for (uint32_t j = 0; j < steps && !rc; ++j) {
-        rc = enqueue_step(c, 0, ids, actions + (size_t)j * n, n, obs ? obs + (size_t)j * n * kObsBytes : nullptr,
-                          reward + (size_t)j * n, done + (size_t)j * n,
-                          frames ? frames + (size_t)j * n * c->n_slots * kFrameBytes : nullptr, s);
+        uint8_t* ob = obs ? obs + (size_t)j * n * kObsBytes : nullptr;
+        uint8_t* fr = frames ? frames + (size_t)j * n * c->n_slots * kFrameBytes : nullptr;
+        if (!overlap) {
+            rc = enqueue_step(c, 0, ids, actions + (size_t)j * n, n, ob, reward + (size_t)j * n, done + (size_t)j * n,
+                              fr, s);
+            continue;
+        }
+        const uint32_t p = j % 2;
+        if (j >= 2 && hipStreamWaitEvent(s, rendered[j - 2], 0) != hipSuccess) rc = fail(VCS_E_HIP, "wait");
+        if (!rc) rc = enqueue_sim(c, p, ids, actions + (size_t)j * n, n, ob, reward + (size_t)j * n, done + (size_t)j * n,
+                                  fr, s);
+        hipEvent_t simd = rc ? nullptr : evt();
+        if (!rc && (!simd || hipEventRecord(simd, s) != hipSuccess || hipStreamWaitEvent(r, simd, 0) != hipSuccess))
+            rc = fail(VCS_E_HIP, "event");
+        if (!rc) rc = enqueue_render(c, p, n, ob, fr, r);
+        if (!rc) {
+            rendered[j] = evt();
+            if (!rendered[j] || hipEventRecord(rendered[j], r) != hipSuccess) rc = fail(VCS_E_HIP, "event");
+        }
+    }
+    if (overlap && !rc) {   // join the render stream back into the captured stream
+        for (uint32_t j = steps - 2; j < steps && !rc; ++j)
+            if (hipStreamWaitEvent(s, rendered[j], 0) != hipSuccess) rc = fail(VCS_E_HIP, "join");
     }
     c->timing = timing;
     hipGraph_t g = nullptr;
     he = hipStreamEndCapture(s, &g);
     (void)hipStreamDestroy(s);
+    if (r) (void)hipStreamDestroy(r);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (rc || he != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return rc ? rc : fail(VCS_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));

@@ -86,23 +86,27 @@ def test_autotune_keeps_results():
     compare_states(o, g, range(n), "post-tune")
 
 
-@pytest.mark.parametrize("listed", [False, True], ids=["all-envs", "listed-ids"])
-def test_graph_replays(listed):
+@pytest.mark.parametrize("listed,pipes,steps", [(False, 1, 2), (True, 1, 2), (False, 2, 3), (True, 2, 4)],
+                         ids=["all-envs", "listed-ids", "all-envs-overlapped", "listed-ids-overlapped"])
+def test_graph_replays(listed, pipes, steps):
+    """With two pipelines the captured steps alternate pipelines and each
+    step's render overlaps the next step's interpreter."""
     n_envs = 150
-    say(f"case: captured 2-step graph, {n_envs} envs, listed={listed}")
-    o, g = make_pair(mixed_roms(), uneven_assignment(n_envs, 2), seed=21, sticky_threshold=0x20000000)
+    say(f"case: captured {steps}-step graph, {n_envs} envs, listed={listed}, pipelines={pipes}")
+    o, g = make_pair(mixed_roms(), uneven_assignment(n_envs, 2), gpu_kw={"pipelines": pipes}, seed=21,
+                     sticky_threshold=0x20000000)
     g.set_launch(16, 0, 256)
     rng = np.random.default_rng(4)
     ids = rng.permutation(n_envs)[:97].astype(np.int32) if listed else None
     n = ids.size if listed else n_envs
-    graph = g.capture(n=n, steps=2, env_ids=ids, want_frames=True)
+    graph = g.capture(n=n, steps=steps, env_ids=ids, want_frames=True)
     side = torch.zeros(1 << 20, device="cuda")
     for rep in range(5):
-        acts = rng.integers(0, 18, (2, n)).astype(np.uint8)
+        acts = rng.integers(0, 18, (steps, n)).astype(np.uint8)
         obs, rew, done, frames = graph.launch(torch.from_numpy(acts).cuda())
         side.add_(1.0)                      # unrelated device work between replays
         torch.cuda.synchronize()
-        for j in range(2):
+        for j in range(steps):
             oo, orr, od, of = o.step(acts[j], env_ids=ids, want_frames=True)
             tag = f"graph replay {rep} step {j}"
             assert np.array_equal(done[j].cpu().numpy(), od), tag + ": done"

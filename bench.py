@@ -96,6 +96,8 @@ def measured_traffic(kernel):
     import hashlib
     src, sha, nbytes = MEASURED_TRAFFIC[kernel]
     path = os.path.join(ROOT, "paper_1907_08467_amd", "csrc", src)
+    if not os.path.exists(path):
+        return None
     with open(path, "rb") as f:
         return nbytes if hashlib.sha256(f.read()).hexdigest()[:16] == sha else None
 

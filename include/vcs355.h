@@ -206,7 +206,7 @@ int vcs_get_launch(vcs_ctx* ctx, vcs_launch* out);
 /* Autotuner.  Times `steps` steps (after one untimed step) of envs 0..n-1
    (n = 0: max_batch) with seeded random actions for each candidate shape,
    one knob at a time: tile_envs (64 and every smaller width that keeps at most
-   8 tiles per compute unit), then workers (1, 2, 4, 8 per compute unit, below
+   12 tiles per compute unit), then workers (1, 2, 4, 8 per compute unit, below
    the tile count), then render_block.  Every candidate starts from the same
    env states; afterwards the states, the error bits and the counters are
    restored, so later steps give the results they would have given without

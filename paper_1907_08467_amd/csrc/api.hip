@@ -355,7 +355,7 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
         grid = c->launch.workers;
     }
     begin_timed(c, 0, s);
-    launch_interp(ia, grid, s);
+    launch_interp(ia, grid, c->launch.tile_envs, s);
     end_timed(c, s);
 
     // a done env restarts from the cache now (state, and its observation);
@@ -647,7 +647,7 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     ia.done = nullptr;
     ia.err_word = c->d_err;
     ia.instr_total = nullptr;
-    launch_interp(ia, n_ct, nullptr);
+    launch_interp(ia, n_ct, kLanes, nullptr);
     RenderArgs ra{};
     ra.logs = d_clog;
     ra.n_slots = 2;
@@ -969,10 +969,11 @@ int vcs_autotune(vcs_ctx* c, uint32_t n, uint32_t steps, int want_frames, int wa
         }
         return VCS_OK;
     };
-    // 1) envs per wave (one workgroup per tile): widths that keep <= 8 waves per CU
+    // 1) envs per wave (one workgroup per tile): widths whose tiles fit on the
+    //    chip at once (up to 12 waves per CU with tiles of 32 envs or fewer)
     for (uint32_t w = 64; w >= 1 && !rc; w >>= 1) {
         const uint64_t tiles = (n + w - 1) / w + c->n_roms;
-        if (w != 64 && tiles > 8ull * c->n_cu) break;
+        if (w != 64 && tiles > 12ull * c->n_cu) break;
         vcs_launch l{w, 0, start.render_block};
         rc = consider(l);
     }

@@ -1199,10 +1199,14 @@ __device__ __forceinline__ uint32_t take_tile(uint32_t* queue) {
     return __builtin_amdgcn_readfirstlane(t);
 }
 
+// LL = envs a tile may hold (64 or 32): RAM and TIA registers get LL + 1
+// slots in LDS (lanes at LL and above, always idle, share the last one), so
+// narrow tiles take less LDS and more waves fit on a compute unit.
+template <int LL>
 __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t* __restrict__ pre_all) {
     __shared__ uint32_t s_rom[kRomSlot / 4 + 4];
-    __shared__ uint32_t s_ram[kLanes * kRamStride / 4];
-    __shared__ uint32_t s_tia[kLanes * kTiaStride / 4];
+    __shared__ uint32_t s_ram[(LL + 1) * kRamStride / 4];
+    __shared__ uint32_t s_tia[(LL + 1) * kTiaStride / 4];
 
     const uint32_t n_tiles = *A.n_tiles;
     uint32_t tile_id = A.queue ? take_tile(A.queue) : blockIdx.x;
@@ -1227,8 +1231,8 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
         bool active = env >= 0;
 
         Cpu c;
-        c.ram_off = lane * kRamStride;
-        c.tia_off = lane * kTiaStride;
+        c.ram_off = (lane < LL ? lane : LL) * kRamStride;
+        c.tia_off = (lane < LL ? lane : LL) * kTiaStride;
         DevEnv* E = active ? &A.envs[env] : nullptr;
         uint64_t base_line = 0;
         uint32_t prev_action = 0, act = 0, step_idx = 0, score0 = 0, nfr = A.nframes;
@@ -1472,8 +1476,11 @@ void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre, hipSt
     hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, roms, n_roms, pre);
 }
 
-void launch_interp(const InterpArgs& a, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_interp, dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, hipStream_t s) {
+    if (tile_envs <= 32)
+        hipLaunchKernelGGL(k_interp<32>, dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+    else
+        hipLaunchKernelGGL(k_interp<64>, dim3(grid), dim3(kLanes), 0, s, a, a.pre);
 }
 
 }  // namespace vcs

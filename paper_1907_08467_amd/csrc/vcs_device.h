@@ -135,7 +135,7 @@ struct ResetArgs {
 };
 
 // host launchers (one per kernel)
-void launch_interp(const InterpArgs& a, uint32_t grid, hipStream_t s);
+void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, hipStream_t s);  // tile_envs: widest tile
 void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre, hipStream_t s);
 void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s);
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s);

@@ -49,9 +49,10 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
-    p.add_argument("--workload", choices=["plain", "batching", "serve"], default="plain",
+    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent"], default="plain",
                    help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
-                        "serve: 131072 resident envs behind the env server")
+                        "serve: 131072 resident envs behind the env server; divergent: 32768 envs over 8 "
+                        "branchy ROMs with sticky actions, with the per-step rate over the run")
     p.add_argument("--serve-seconds", type=float, default=20.0)
     p.add_argument("--graph", type=int, default=4,
                    help="plain workload: time steps captured G at a time in HIP graphs (two pipelines, each step's "
@@ -325,6 +326,50 @@ def bench_batching(args):
     }
 
 
+def bench_divergent(args):
+    """32768 envs over 8 divergent ROMs (4 x 4 KB, 4 x F8), sticky actions
+    p = 0.25, every frame rendered: raw frames/s and the per-step time over the
+    run (the paper's FPS-against-step curve: envs start in step from the reset
+    cache and drift apart)."""
+    import torch
+    from paper_1907_08467_amd.inputs.workloads import config
+    w = config(3)
+    n, K = w.n_envs, args.steps
+    env, roms, env_rom = gpu_env(w)
+    dev = torch.device("cuda", 0)
+    launch, launch_from = select_launch(env, args, n, True, True)
+    env.reset()                                # every env back to a cache state: the curve starts correlated
+    acts = torch.from_numpy(w.actions(steps=K)).to(dev)
+    obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
+    rew = torch.empty(n, dtype=torch.int32, device=dev)
+    done = torch.empty(n, dtype=torch.uint8, device=dev)
+    frames = torch.empty((n, w.frameskip, 210, 160), dtype=torch.uint8, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for s in range(K):
+        env.step(acts[s], out=(obs, rew, done, frames))
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(K)]
+    total = sum(ms) * 1e-3
+    value = n * w.frameskip * K / total
+    bits = env.poll_errors()[1]
+    pts = sorted(set([0, 1, 2, 5, 10, 20, 50, 100, 200, 500, K - 1]) & set(range(K)))
+    return {
+        "metric": "raw emulated frames/s on 1 MI355X (p50/p99 step latency in served mode)",
+        "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": 0,
+        "ms_per_step": total / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"divergent batch: {n} envs over 8 synthetic ROMs (4 x 4 KB, 4 x F8 bank-switched) "
+                               "with data-dependent branches, sticky actions p = 0.25, frameskip 4, every frame "
+                               "rendered + obs, eager steps from a fresh reset", "num_envs": n,
+                   "launch": launch, "launch_from": launch_from},
+        "fps_by_step": {str(s): n * w.frameskip / (ms[s] * 1e-3) for s in pts},
+        "errors": bits, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def bench_serve(args):
     """131072 resident envs, 64 closed-loop actors, continuous batching."""
     import torch
@@ -386,7 +431,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the envs are independent and "
               "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)
         sys.exit(2)
-    fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve}[args.workload]
+    fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
+          "divergent": bench_divergent}[args.workload]
     print(json.dumps(fn(args)))
 
 

@@ -32,9 +32,9 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 # reported only while the kernel source is the one they were taken on
 # (sha256 prefix), otherwise null.
 MEASURED_TRAFFIC = {
-    "k_interp": ("interp.hip", "95fcb41f56526262", (1152.0 * 2.0 + 176040.8) * 1024),
-    "k_render_frames": ("render.hip", "5c2c68120efc3504", (94333.8 * 2.0 + 268934.1) * 1024),
-    "k_render_obs": ("render.hip", "5c2c68120efc3504", (94332.6 * 2.0 + 297234.0) * 1024),
+    "k_interp": ("interp.hip", "624c9e9c266bcded", (1139.0 * 2.0 + 176040.4) * 1024),
+    "k_render_frames": ("render.hip", "5c2c68120efc3504", (94335.0 * 2.0 + 268935.7) * 1024),
+    "k_render_obs": ("render.hip", "5c2c68120efc3504", (94333.4 * 2.0 + 297231.5) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9

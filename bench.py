@@ -49,11 +49,13 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
-    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent"], default="plain",
+    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack"], default="plain",
                    help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
                         "serve: 131072 resident envs behind the env server; divergent: 32768 envs over 8 "
-                        "branchy ROMs with sticky actions, with the per-step rate over the run")
+                        "branchy ROMs with sticky actions, with the per-step rate over the run; stack: the frame "
+                        "stack of 16384 envs")
     p.add_argument("--serve-seconds", type=float, default=20.0)
+    p.add_argument("--serve-pipelines", type=int, default=3)
     p.add_argument("--graph", type=int, default=4,
                    help="plain workload: time steps captured G at a time in HIP graphs (two pipelines, each step's "
                         "render overlapping the next step's interpreter) after the eager steps, and report them as "
@@ -370,6 +372,56 @@ def bench_divergent(args):
     }
 
 
+def bench_stack(args):
+    """Frame stack of the last four observations for 16384 envs (the paper's
+    memory-wall point), 8-bit and 4-bit storage: push throughput against HBM."""
+    import torch
+    from paper_1907_08467_amd.env import FrameStack
+    from paper_1907_08467_amd.inputs.workloads import config
+    w = config(2)
+    w.n_envs = 16384
+    env, roms, env_rom = gpu_env(w)
+    dev = torch.device("cuda", 0)
+    n, K = w.n_envs, args.steps
+    acts = torch.from_numpy(w.actions(steps=8)).to(dev)
+    obs_steps = []
+    for s in range(8):                         # real observations and done flags to push
+        o, _, d, _ = env.step(acts[s])
+        obs_steps.append((o.clone(), d.clone()))
+    res = {}
+    for bits in (8, 4):
+        fs = FrameStack(env, depth=4, bits=bits)
+        out = torch.empty((n, 4, 84, 84), dtype=torch.uint8, device=dev)
+        fs.push(obs_steps[0][0], torch.ones_like(obs_steps[0][1]), out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(K):
+            o, d = obs_steps[k % 8]
+            fs.push(o, d, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        slot = 84 * 84 * bits // 8
+        # per env: obs read, one slot written, four slots read, four obs written
+        nbytes = n * (84 * 84 + slot + 4 * slot + 4 * 84 * 84)
+        res[f"{bits}bit"] = {"ms_per_push": ms, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+                             "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "ring_bytes": n * 4 * slot, "algorithmic_bytes_per_push": nbytes}
+        fs.close()
+    b = res["8bit"]
+    return {
+        "metric": "frame-stack pushes/s (envs x pushes / s) on 1 MI355X", "value": n / (b["ms_per_push"] * 1e-3),
+        "unit": "env-pushes/s", "n_gpus": 1, "steps": K, "warmup": 1, "ms_per_step": b["ms_per_push"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"frame stack: last 4 84x84 observations of {n} envs, pushed after each step",
+                   "num_envs": n, "depth": 4},
+        "roofline": {"bound": "hbm", "kernel": "k_stack", "achieved": b["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": b["frac"], "traffic": None},
+        "forms": res, "cpu_baseline": None,
+    }
+
+
 def bench_serve(args):
     """131072 resident envs, 64 closed-loop actors, continuous batching."""
     import torch
@@ -378,7 +430,7 @@ def bench_serve(args):
     w = config(5)
     n = w.n_envs
     budget = 16 << 30
-    pipes = 2
+    pipes = args.serve_pipelines
     cap = slots_for_budget(budget - (512 << 20), n, 16, 2, pipes)   # 512 MiB kept for tile tables and tuning
     env, roms, env_rom = gpu_env(w, max_batch=cap, pipelines=pipes, hbm_budget_bytes=budget)
     dev = torch.device("cuda", 0)
@@ -432,7 +484,7 @@ def main():
               "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)
         sys.exit(2)
     fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
-          "divergent": bench_divergent}[args.workload]
+          "divergent": bench_divergent, "stack": bench_stack}[args.workload]
     print(json.dumps(fn(args)))
 
 

@@ -232,6 +232,29 @@ int vcs_graph_create(vcs_ctx* ctx, const int32_t* env_ids_dev, const uint8_t* ac
 int vcs_graph_launch(vcs_graph* graph, void* stream);
 void vcs_graph_destroy(vcs_graph* graph);
 
+/* ---- frame stack (paper, Section 5, "Memory limitations": agents keep each
+   env's last four 84x84 observations; compression is named there as future
+   work) ----------------------------------------------------------------
+   A stack holds the last `depth` (1..16) observations of every env of the
+   context in device memory, as 8-bit gray (bits = 8) or packed to the top
+   nibble of each pixel, two pixels per byte (bits = 4: half the memory).
+   Created all zero; allocated within the context's budget; destroy it before
+   the context. */
+typedef struct vcs_stack vcs_stack;
+int vcs_stack_create(vcs_ctx* ctx, uint32_t depth, uint32_t bits, vcs_stack** out);
+/* Push observations obs_dev[n][84][84] of envs env_ids_dev[0..n) (NULL = envs
+   0..n-1; ids must be distinct within a call, as for vcs_step).  An env with
+   done_dev[i] != 0 (done_dev may be NULL) starts a new stack: all slots take
+   this observation.  out_dev (NULL to skip) receives [n][depth][84][84]
+   u8, oldest first, each pixel as stored widened to 8 bits (identity for
+   bits = 8, q * 17 for a 4-bit q).  Out-of-range ids are skipped.  Enqueued
+   on `stream`; no synchronisation.  Typical use: after vcs_assign / vcs_reset
+   push the reset observations with done = 1, then push every step's obs and
+   done. */
+int vcs_stack_push(vcs_stack* stack, const int32_t* env_ids_dev, uint32_t n, const uint8_t* obs_dev,
+                   const uint8_t* done_dev, uint8_t* out_dev, void* stream);
+void vcs_stack_destroy(vcs_stack* stack);
+
 const char* vcs_last_error(void);
 
 #ifdef __cplusplus

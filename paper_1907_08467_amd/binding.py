@@ -89,12 +89,16 @@ def _declare(L):
     L.vcs_graph_launch.argtypes = [_vp, _vp]
     L.vcs_graph_destroy.argtypes = [_vp]
     L.vcs_graph_destroy.restype = None
+    L.vcs_stack_create.argtypes = [_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_vp)]
+    L.vcs_stack_push.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp]
+    L.vcs_stack_destroy.argtypes = [_vp]
+    L.vcs_stack_destroy.restype = None
     L.vcs_last_error.argtypes = []
     L.vcs_last_error.restype = ctypes.c_char_p
     for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_step_pipe", "vcs_get_state",
                  "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions", "vcs_last_step_stats",
                  "vcs_timing", "vcs_kernel_time", "vcs_set_launch", "vcs_get_launch", "vcs_autotune",
-                 "vcs_graph_create", "vcs_graph_launch"):
+                 "vcs_graph_create", "vcs_graph_launch", "vcs_stack_create", "vcs_stack_push"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -240,6 +244,20 @@ def vcs_graph_launch(g, stream):
 
 def vcs_graph_destroy(g):
     lib.vcs_graph_destroy(g)
+
+
+def vcs_stack_create(h, depth, bits):
+    st = _vp()
+    check(lib.vcs_stack_create(h, depth, bits, ctypes.byref(st)), "vcs_stack_create")
+    return st
+
+
+def vcs_stack_push(st, ids_ptr, n, obs_ptr, done_ptr, out_ptr, stream):
+    check(lib.vcs_stack_push(st, ids_ptr, n, obs_ptr, done_ptr, out_ptr, stream), "vcs_stack_push")
+
+
+def vcs_stack_destroy(st):
+    lib.vcs_stack_destroy(st)
 
 
 def vcs_last_error():

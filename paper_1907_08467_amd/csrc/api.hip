@@ -1119,4 +1119,57 @@ void vcs_graph_destroy(vcs_graph* g) {
     delete g;
 }
 
+struct vcs_stack {
+    vcs_ctx* c = nullptr;
+    uint8_t* ring = nullptr;
+    uint8_t* head = nullptr;
+    uint32_t depth = 0, bits = 0;
+    size_t ring_bytes = 0;
+};
+
+int vcs_stack_create(vcs_ctx* c, uint32_t depth, uint32_t bits, vcs_stack** out) {
+    if (!c || !out) return fail(VCS_E_INVAL, "null argument");
+    *out = nullptr;
+    if (depth < 1 || depth > 16) return fail(VCS_E_INVAL, "depth must be in [1, 16]");
+    if (bits != 8 && bits != 4) return fail(VCS_E_INVAL, "bits must be 8 or 4");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    vcs_stack* S = new vcs_stack();
+    S->c = c;
+    S->depth = depth;
+    S->bits = bits;
+    S->ring_bytes = (size_t)c->cfg.num_envs * depth * (bits == 4 ? kObsBytes / 2 : kObsBytes);
+    int rc = alloc_n(c, &S->ring, S->ring_bytes, "frame stack");
+    if (!rc) rc = alloc_n(c, &S->head, c->cfg.num_envs, "frame stack heads");
+    if (!rc && (hipMemset(S->ring, 0, S->ring_bytes) != hipSuccess ||
+                hipMemset(S->head, 0, c->cfg.num_envs) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+        rc = fail(VCS_E_HIP, "frame stack clear failed");
+    if (rc) {
+        vcs_stack_destroy(S);
+        return rc;
+    }
+    *out = S;
+    return VCS_OK;
+}
+
+int vcs_stack_push(vcs_stack* S, const int32_t* ids, uint32_t n, const uint8_t* obs, const uint8_t* done,
+                   uint8_t* out, void* stream) {
+    if (!S) return fail(VCS_E_INVAL, "null stack");
+    if (n > S->c->cfg.num_envs) return fail(VCS_E_INVAL, "n exceeds num_envs");
+    if (n == 0) return VCS_OK;
+    if (!obs) return fail(VCS_E_INVAL, "obs is required");
+    launch_stack(S->ring, S->head, ids, n, S->c->cfg.num_envs, S->depth, S->bits, obs, done, out,
+                 (hipStream_t)stream);
+    HIP_OK(hipGetLastError());
+    return VCS_OK;
+}
+
+void vcs_stack_destroy(vcs_stack* S) {
+    if (!S) return;
+    (void)hipSetDevice(S->c->cfg.device);
+    (void)hipDeviceSynchronize();
+    dev_free(S->c, S->ring, S->ring_bytes);
+    dev_free(S->c, S->head, S->c->cfg.num_envs);
+    delete S;
+}
+
 }  // extern "C"

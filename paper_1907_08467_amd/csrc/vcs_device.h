@@ -141,6 +141,8 @@ void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t 
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s);
 void launch_reset(const ResetArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+void launch_stack(uint8_t* ring, uint8_t* head, const int32_t* ids, uint32_t n, uint32_t num_envs, uint32_t depth,
+                  uint32_t bits, const uint8_t* obs, const uint8_t* done, uint8_t* out, hipStream_t s);
 void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, hipStream_t s);
 void launch_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, const uint16_t* env_rom,
                      uint32_t* claim, const uint32_t* tag, uint32_t* counts, uint8_t* valid, StepInfo* info,

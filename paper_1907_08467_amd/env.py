@@ -177,3 +177,34 @@ class StepGraph:
             self.close()
         except Exception:
             pass
+
+
+class FrameStack:
+    """The last `depth` observations of every env of `env`, kept in device
+    memory (8-bit, or 4-bit packed); push() after each step."""
+
+    def __init__(self, env, depth=4, bits=8):
+        self.env, self.depth, self.bits = env, depth, bits
+        self._s = B.vcs_stack_create(env._h, depth, bits)
+
+    def push(self, obs, done=None, env_ids=None, out=None, want_out=True):
+        """obs: uint8 cuda [n, 84, 84]; done: uint8 cuda [n] or None.
+        Returns the stacked observations [n, depth, 84, 84] (or None)."""
+        ids, ids_ptr = self.env._ids(env_ids)
+        n = obs.shape[0]
+        if out is None and want_out:
+            out = torch.empty((n, self.depth, 84, 84), dtype=torch.uint8, device=self.env.device)
+        B.vcs_stack_push(self._s, ids_ptr, n, obs.data_ptr(), done.data_ptr() if done is not None else None,
+                         out.data_ptr() if out is not None else None, self.env._stream())
+        return out
+
+    def close(self):
+        if getattr(self, "_s", None):
+            B.vcs_stack_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

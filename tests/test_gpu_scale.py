@@ -95,3 +95,32 @@ def test_divergent_32768_sampled():
 def test_batching_65536_sampled():
     """65536 envs, 16 ROMs in Zipf populations, last two frames rendered."""
     run_sampled(4, steps=30, per_rom=6, check_every=15)
+
+
+def test_plain_batch_4096_all_envs_states():
+    """Every one of the 4096 envs against the oracle (which runs without
+    rendering here): rewards and done flags every step, full machine-state
+    records at the end."""
+    import torch
+    from paper_1907_08467_amd.env import VcsEnv
+    w = config(2)
+    steps = 24
+    say("case:", w.name, f"all envs, {steps} steps, states at the end")
+    roms = [(r.data, r.scheme) for r in w.roms()]
+    env_rom = w.env_rom()
+    cfg = dict(frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode)
+    g = VcsEnv(roms, env_rom, GRAY, **cfg)
+    o = oracle.Oracle(w.n_envs, GRAY, **cfg)
+    o.load_roms(roms)
+    o.assign(env_rom)
+    acts = w.actions(steps=steps)
+    for s in range(steps):
+        _, gr, gd, _ = g.step(torch.from_numpy(acts[s]).cuda(), want_obs=False)
+        _, orr, od, _ = o.step(acts[s], render=False)
+        gr, gd = gr.cpu().numpy(), gd.cpu().numpy()
+        bad = np.nonzero((gr != orr) | (gd != od))[0]
+        assert bad.size == 0, f"step {s}: reward/done differ for envs {bad[:8].tolist()}"
+    for e in range(w.n_envs):
+        a_, b_ = g.get_state(e), o.get_state(e)
+        assert np.array_equal(a_, b_), f"state of env {e}: {diff_records(a_, b_)}"
+    say(f"all {w.n_envs} env states agree after {steps} steps")

@@ -39,6 +39,10 @@ MEASURED_TRAFFIC = {
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+# policy CNN: output positions per env, output channels, reduction length
+POLICY_GEMMS = [(400, 32, 256), (81, 64, 512), (49, 64, 576), (1, 512, 3136), (1, 19, 512)]
+POLICY_FLOPS_PER_ENV = sum(2 * m * n * k for m, n, k in POLICY_GEMMS)
 
 
 def parse():
@@ -49,11 +53,11 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
-    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack"], default="plain",
+    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference"], default="plain",
                    help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
                         "serve: 131072 resident envs behind the env server; divergent: 32768 envs over 8 "
                         "branchy ROMs with sticky actions, with the per-step rate over the run; stack: the frame "
-                        "stack of 16384 envs")
+                        "stack of 16384 envs; inference: 4096 envs whose actions come from the policy CNN")
     p.add_argument("--serve-seconds", type=float, default=20.0)
     p.add_argument("--serve-pipelines", type=int, default=3)
     p.add_argument("--graph", type=int, default=4,
@@ -422,6 +426,107 @@ def bench_stack(args):
     }
 
 
+def cpu_baseline_inference(w, roms, env_rom, layers, steps, n):
+    """The oracle's inference loop: oracle policy -> oracle step -> oracle stack."""
+    import oracle
+    from oracle.policy import forward, greedy
+    from oracle.stack import FrameStack as OracleStack
+    from paper_1907_08467_amd.inputs.palette import GRAY
+    o = oracle.Oracle(n, GRAY, frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode)
+    o.load_roms(roms)
+    o.assign(env_rom[:n])
+    fs = OracleStack(n, depth=4, bits=8)
+    st = fs.push(o.reset(), np.ones(n, np.uint8))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = greedy(forward(st, layers))
+        ob, _, d, _ = o.step(a)
+        st = fs.push(ob, d)
+    dt = time.perf_counter() - t0
+    frames = n * w.frameskip * steps
+    return {"value": frames / dt, "unit": "raw frames/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"{n} envs x {steps} steps x frameskip {w.frameskip}: float64 policy forward (numpy), "
+                      "oracle step with obs, oracle frame stack", "seconds": dt}
+
+
+def bench_inference(args):
+    """Inference path with a policy in the loop (the paper's 'inference only'
+    load condition, Section 4): per step the policy CNN reads every env's
+    frame stack and picks its action, the envs step with those actions and
+    the stack takes the new observations; nothing leaves the device."""
+    import torch
+    from paper_1907_08467_amd.env import FrameStack, Policy
+    from paper_1907_08467_amd.inputs.policy_weights import policy_weights
+    from paper_1907_08467_amd.inputs.workloads import config
+    w = config(2)
+    env, roms, env_rom = gpu_env(w)
+    dev = torch.device("cuda", 0)
+    n, K, W = w.n_envs, args.steps, args.warmup
+    layers = policy_weights(7)
+    pol = Policy(env, [l[0] for l in layers], [l[2] for l in layers])
+    fs = FrameStack(env, depth=4, bits=8)
+    obs = env.reset()
+    rew = torch.empty(n, dtype=torch.int32, device=dev)
+    done = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = torch.empty((n, 4, 84, 84), dtype=torch.uint8, device=dev)
+    act = torch.empty(n, dtype=torch.uint8, device=dev)
+    fs.push(obs, torch.ones(n, dtype=torch.uint8, device=dev), out=st)
+
+    def one_step():
+        pol.act(st, actions=act)
+        env.step(act, out=(obs, rew, done, None))
+        fs.push(obs, done, out=st)
+
+    for _ in range(W):
+        one_step()
+    torch.cuda.synchronize()
+    env.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        one_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    env.timing(False)
+    kern = kernel_table(env)
+    value = n * w.frameskip * K / dt
+    print(f"timed {K} inference steps in {dt:.3f}s", file=sys.stderr, flush=True)
+    # the policy alone on the last stacks, HIP events on the stream it runs on
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        pol.act(st, actions=act)
+    e1.record()
+    torch.cuda.synchronize()
+    pol_ms = e0.elapsed_time(e1) / K
+    flops = POLICY_FLOPS_PER_ENV * n
+    tflops = flops / (pol_ms * 1e-3) / 1e12
+    hist = torch.bincount(act.long(), minlength=18).cpu().tolist()
+    bits = env.poll_errors()[1]
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("cpu baseline: oracle inference loop", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_inference(w, roms, env_rom, layers, steps=8, n=256)
+    pol.close()
+    fs.close()
+    return {
+        "metric": "raw emulated frames/s on 1 MI355X, actions from a policy CNN on the device (inference only)",
+        "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8 emulation, bf16 policy (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": f"inference only: {n} envs x 1 seeded 4 KB synthetic cartridge, frameskip "
+                               f"{w.frameskip}; per step a conv 8x8/4-4x4/2-3x3/1 + 512 + 19 policy (random "
+                               "He-uniform weights, seed 7) on each env's 4-frame 8-bit stack, greedy actions",
+                   "num_envs": n, "frameskip": w.frameskip, "stack": "4 x 84x84, 8-bit"},
+        "roofline": {"bound": "mfma", "kernel": "k_conv (5 layers, one act call)", "achieved": tflops,
+                     "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
+                     "traffic": None, "work_per_launch": f"{POLICY_FLOPS_PER_ENV} flop/env x {n} envs"},
+        "policy_ms": pol_ms,
+        "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
+        "action_histogram_last_step": hist, "errors": bits,
+        "cpu_baseline": cpu,
+    }
+
+
 def bench_serve(args):
     """131072 resident envs, 64 closed-loop actors, continuous batching."""
     import torch
@@ -484,7 +589,7 @@ def main():
               "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)
         sys.exit(2)
     fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
-          "divergent": bench_divergent, "stack": bench_stack}[args.workload]
+          "divergent": bench_divergent, "stack": bench_stack, "inference": bench_inference}[args.workload]
     print(json.dumps(fn(args)))
 
 

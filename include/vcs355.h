@@ -255,6 +255,34 @@ int vcs_stack_push(vcs_stack* stack, const int32_t* env_ids_dev, uint32_t n, con
                    const uint8_t* done_dev, uint8_t* out_dev, void* stream);
 void vcs_stack_destroy(vcs_stack* stack);
 
+/* ---- policy network on the inference path (paper, Section 4: the
+   "inference only" load condition, where a policy DNN picks the actions and
+   emulation and inference both run on the GPU) ----------------------------
+   Fixed architecture (the paper gives none; this is the convolutional trunk
+   of the A2C/DQN agents it builds on): input the u8 stack [4][84][84] / 255;
+   conv 32 x 8x8 stride 4, conv 64 x 4x4 stride 2, conv 64 x 3x3 stride 1,
+   dense 3136 -> 512, each followed by ReLU; dense 512 -> 19 (18 action
+   logits, then a value).  bf16 weights and activations, fp32 accumulation on
+   the matrix cores, fp32 biases and logits.
+   weights_host[l]: bf16 bit patterns, row-major [N_l][K_l]: N = 32, 64, 64,
+   512, 19; K = 256, 512, 576, 3136, 512.  Layer 1's reduction index is
+   (channel * 8 + ky) * 8 + kx; the others' (ky * KW + kx) * Cin + channel
+   (for the dense 3136 -> 512 layer: (y * 7 + x) * 64 + channel of the 7x7x64
+   map).  biases_host[l]: float [N_l].  Both are copied; scratch for
+   max_batch envs is allocated within the context's budget.  Destroy the
+   policy before its context. */
+typedef struct vcs_policy vcs_policy;
+int vcs_policy_create(vcs_ctx* ctx, const uint16_t* const* weights_host, const float* const* biases_host,
+                      vcs_policy** out);
+/* Forward pass for stack_dev[n][4][84][84] (n <= max_batch): logits_dev
+   (NULL to skip) receives [n][32] floats (entries 0..17 the action logits,
+   18 the value, the rest unspecified); actions_dev (NULL to skip) receives,
+   per env, the index of the first maximal logit among the 18.  Enqueued on
+   `stream`. */
+int vcs_policy_act(vcs_policy* policy, const uint8_t* stack_dev, uint32_t n, float* logits_dev, uint8_t* actions_dev,
+                   void* stream);
+void vcs_policy_destroy(vcs_policy* policy);
+
 const char* vcs_last_error(void);
 
 #ifdef __cplusplus

@@ -93,12 +93,17 @@ def _declare(L):
     L.vcs_stack_push.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp]
     L.vcs_stack_destroy.argtypes = [_vp]
     L.vcs_stack_destroy.restype = None
+    L.vcs_policy_create.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]
+    L.vcs_policy_act.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp]
+    L.vcs_policy_destroy.argtypes = [_vp]
+    L.vcs_policy_destroy.restype = None
     L.vcs_last_error.argtypes = []
     L.vcs_last_error.restype = ctypes.c_char_p
     for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_step_pipe", "vcs_get_state",
                  "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions", "vcs_last_step_stats",
                  "vcs_timing", "vcs_kernel_time", "vcs_set_launch", "vcs_get_launch", "vcs_autotune",
-                 "vcs_graph_create", "vcs_graph_launch", "vcs_stack_create", "vcs_stack_push"):
+                 "vcs_graph_create", "vcs_graph_launch", "vcs_stack_create", "vcs_stack_push",
+                 "vcs_policy_create", "vcs_policy_act"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -258,6 +263,28 @@ def vcs_stack_push(st, ids_ptr, n, obs_ptr, done_ptr, out_ptr, stream):
 
 def vcs_stack_destroy(st):
     lib.vcs_stack_destroy(st)
+
+
+def vcs_policy_create(h, weights, biases):
+    """weights: 5 contiguous uint16 numpy arrays (bf16 bits), biases: 5 float32 arrays."""
+    import numpy as np
+    ws = [np.ascontiguousarray(w, np.uint16) for w in weights]
+    bs = [np.ascontiguousarray(b, np.float32) for b in biases]
+    if len(ws) != 5 or len(bs) != 5:
+        raise ValueError("the policy has 5 layers")
+    wp = (_vp * 5)(*[w.ctypes.data for w in ws])
+    bp = (_vp * 5)(*[b.ctypes.data for b in bs])
+    p = _vp()
+    check(lib.vcs_policy_create(h, wp, bp, ctypes.byref(p)), "vcs_policy_create")
+    return p
+
+
+def vcs_policy_act(p, stack_ptr, n, logits_ptr, actions_ptr, stream):
+    check(lib.vcs_policy_act(p, stack_ptr, n, logits_ptr, actions_ptr, stream), "vcs_policy_act")
+
+
+def vcs_policy_destroy(p):
+    lib.vcs_policy_destroy(p)
 
 
 def vcs_last_error():

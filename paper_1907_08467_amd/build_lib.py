@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvcs355.so")
-SOURCES = ["interp.hip", "render.hip", "envops.hip", "stack.hip", "api.hip"]
+SOURCES = ["interp.hip", "render.hip", "envops.hip", "stack.hip", "policy.hip", "api.hip"]
 # Control flow that the compiler can prove wave-uniform (the interpreter's
 # scalar loop) is left as plain scalar branches instead of being rewritten into
 # the structured form divergent code needs, which would add a copy of every

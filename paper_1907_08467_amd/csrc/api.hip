@@ -1172,4 +1172,105 @@ void vcs_stack_destroy(vcs_stack* S) {
     delete S;
 }
 
+namespace {
+// the policy network's layers: input side, kernel, stride, channels
+struct LayerShape {
+    uint32_t H, Cin, KW, stride, OH, N, Npad;
+};
+constexpr LayerShape kLayers[5] = {
+    {84, 4, 8, 4, 20, 32, 32},     // conv 32 x 8x8 / 4 on the u8 stack
+    {20, 32, 4, 2, 9, 64, 64},     // conv 64 x 4x4 / 2
+    {9, 64, 3, 1, 7, 64, 64},      // conv 64 x 3x3 / 1
+    {7, 64, 7, 1, 1, 512, 512},    // 3136 -> 512 as a 7x7 convolution
+    {1, 512, 1, 1, 1, 19, 32},     // 512 -> 18 logits + value
+};
+constexpr uint32_t layer_k(const LayerShape& L) { return L.KW * L.KW * L.Cin; }
+}  // namespace
+
+struct vcs_policy {
+    vcs_ctx* c = nullptr;
+    uint16_t* w[5] = {};
+    float* b[5] = {};
+    uint16_t* act[4] = {};   // outputs of layers 1-4
+    float* logits = nullptr;
+    uint32_t max_n = 0;
+    std::vector<std::pair<void*, size_t>> allocs;
+};
+
+int vcs_policy_create(vcs_ctx* c, const uint16_t* const* w_host, const float* const* b_host, vcs_policy** out) {
+    if (!c || !w_host || !b_host || !out) return fail(VCS_E_INVAL, "null argument");
+    *out = nullptr;
+    for (int l = 0; l < 5; ++l)
+        if (!w_host[l] || !b_host[l]) return fail(VCS_E_INVAL, "null weight or bias array");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    vcs_policy* P = new vcs_policy();
+    P->c = c;
+    P->max_n = c->max_batch;
+    int rc = VCS_OK;
+    auto take = [&](void** p, size_t bytes, const char* what) {
+        if (!rc) rc = dev_alloc(c, p, bytes, what);
+        if (!rc) P->allocs.push_back({*p, bytes});
+    };
+    for (int l = 0; l < 5 && !rc; ++l) {
+        const LayerShape& L = kLayers[l];
+        const size_t K = layer_k(L);
+        take(reinterpret_cast<void**>(&P->w[l]), (size_t)L.Npad * K * 2, "policy weights");
+        take(reinterpret_cast<void**>(&P->b[l]), (size_t)L.Npad * 4, "policy biases");
+        if (rc) break;
+        // rows past N are zero; the device copy is in operand order
+        std::vector<uint16_t> wz((size_t)L.Npad * K, 0);
+        std::vector<float> bz(L.Npad, 0.f);
+        for (uint32_t cch = 0; cch < L.N; ++cch)
+            for (size_t k = 0; k < K; ++k)
+                wz[policy_swizzle_index(cch, (uint32_t)k, L.Npad / 16)] = w_host[l][(size_t)cch * K + k];
+        std::memcpy(bz.data(), b_host[l], (size_t)L.N * 4);
+        if (hipMemcpy(P->w[l], wz.data(), wz.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(P->b[l], bz.data(), bz.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(VCS_E_HIP, "policy weight upload failed");
+    }
+    for (int l = 0; l < 4 && !rc; ++l) {
+        const LayerShape& L = kLayers[l];
+        take(reinterpret_cast<void**>(&P->act[l]), (size_t)P->max_n * L.OH * L.OH * L.N * 2, "policy activations");
+    }
+    take(reinterpret_cast<void**>(&P->logits), (size_t)P->max_n * 32 * 4, "policy logits");
+    if (rc) {
+        vcs_policy_destroy(P);
+        return rc;
+    }
+    *out = P;
+    return VCS_OK;
+}
+
+int vcs_policy_act(vcs_policy* P, const uint8_t* stack, uint32_t n, float* logits, uint8_t* actions, void* stream) {
+    if (!P) return fail(VCS_E_INVAL, "null policy");
+    if (n > P->max_n) return fail(VCS_E_INVAL, "n exceeds max_batch");
+    if (n == 0) return VCS_OK;
+    if (!stack || (!logits && !actions)) return fail(VCS_E_INVAL, "stack and an output are required");
+    hipStream_t s = (hipStream_t)stream;
+    float* lg = logits ? logits : P->logits;
+    const void* in = stack;
+    for (int l = 0; l < 5; ++l) {
+        const LayerShape& L = kLayers[l];
+        PolicyLayerArgs a{};
+        a.in = in;
+        a.w = P->w[l];
+        a.bias = P->b[l];
+        a.out = l < 4 ? static_cast<void*>(P->act[l]) : static_cast<void*>(lg);
+        a.M = n * L.OH * L.OH;
+        launch_policy_layer(l, a, s);
+        in = a.out;
+    }
+    if (actions) launch_argmax(lg, n, actions, s);
+    HIP_OK(hipGetLastError());
+    return VCS_OK;
+}
+
+void vcs_policy_destroy(vcs_policy* P) {
+    if (!P) return;
+    (void)hipSetDevice(P->c->cfg.device);
+    (void)hipDeviceSynchronize();
+    for (auto& a : P->allocs) dev_free(P->c, a.first, a.second);
+    delete P;
+}
+
 }  // extern "C"

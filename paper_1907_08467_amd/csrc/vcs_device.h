@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace vcs {
 
 constexpr int kLanes = 64;             // envs per tile = one wave64
@@ -141,6 +143,25 @@ void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t 
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s);
 void launch_reset(const ResetArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+
+// one layer of the policy network (layer = 0..4)
+struct PolicyLayerArgs {
+    const void* in;        // layer 0: u8 [n][4][84][84]; others: bf16 NHWC [n][H][H][Cin]
+    const uint16_t* w;     // bf16 bits in operand order (policy_swizzle_index)
+    const float* bias;     // [Npad]
+    void* out;             // bf16 NHWC [n][OH][OH][N] (hidden) or f32 [n][32] (head)
+    uint32_t M;            // n * OH * OH output positions, > 0
+};
+void launch_policy_layer(int layer, const PolicyLayerArgs& a, hipStream_t s);
+// Where weight (channel c, reduction index k) of a layer with K = 32 KS
+// reduction indices and NT 16-channel tiles goes in operand order: fragment
+// (k-step k / 32, tile c / 16) is 64 lanes x 8 values, lane (c % 16) + 16 ((k % 32) / 8)
+// holding values k % 8.
+inline size_t policy_swizzle_index(uint32_t c, uint32_t k, uint32_t NT) {
+    const uint32_t s = k / 32, j = c / 16, lane = (c % 16) + 16 * ((k % 32) / 8), t = k % 8;
+    return (((size_t)s * NT + j) * 64 + lane) * 8 + t;
+}
+void launch_argmax(const float* logits, uint32_t n, uint8_t* actions, hipStream_t s);
 void launch_stack(uint8_t* ring, uint8_t* head, const int32_t* ids, uint32_t n, uint32_t num_envs, uint32_t depth,
                   uint32_t bits, const uint8_t* obs, const uint8_t* done, uint8_t* out, hipStream_t s);
 void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, hipStream_t s);

@@ -208,3 +208,41 @@ class FrameStack:
             self.close()
         except Exception:
             pass
+
+
+class Policy:
+    """The inference-path policy network of `env`'s context (bf16 weights,
+    fp32 accumulation on the matrix cores).  weights/biases: the 5 layers in
+    the library's layouts (bf16 bit patterns as uint16, float32 biases)."""
+
+    def __init__(self, env, weights, biases):
+        self.env = env
+        self._p = B.vcs_policy_create(env._h, weights, biases)
+
+    def act(self, stack, logits=None, actions=None, want_logits=False):
+        """stack: uint8 cuda [n, 4, 84, 84].  Returns (actions uint8 [n],
+        logits float32 [n, 32] or None); entries 0..17 of a logits row are
+        the action logits, 18 the value."""
+        if stack.dtype != torch.uint8 or stack.dim() != 4 or tuple(stack.shape[1:]) != (4, 84, 84) \
+                or not stack.is_contiguous():
+            raise ValueError("stack must be a contiguous uint8 tensor [n, 4, 84, 84]")
+        n = stack.shape[0]
+        dev = self.env.device
+        if actions is None:
+            actions = torch.empty(n, dtype=torch.uint8, device=dev)
+        if logits is None and want_logits:
+            logits = torch.empty((n, 32), dtype=torch.float32, device=dev)
+        B.vcs_policy_act(self._p, stack.data_ptr(), n, logits.data_ptr() if logits is not None else None,
+                         actions.data_ptr(), self.env._stream())
+        return actions, logits
+
+    def close(self):
+        if getattr(self, "_p", None):
+            B.vcs_policy_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-STATE_BYTES = 256
+STATE_BYTES = 384
 RENDER_ALL, RENDER_LAST2 = 0, 1
 ERR_ILLEGAL, ERR_FRAME_CAP, ERR_BAD_ACTION = 1, 2, 4
 

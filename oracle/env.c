@@ -116,7 +116,7 @@ void oracle_preprocess(const uint8_t* f_prev, const uint8_t* f_last, const uint8
 typedef struct {
     uint8_t* data;
     uint32_t size, scheme;
-    uint8_t* cache_state;   /* [K][256] */
+    uint8_t* cache_state;   /* [K][ORC_STATE_BYTES] */
     uint8_t* cache_obs;     /* [K][84*84] */
 } ORom;
 
@@ -167,7 +167,7 @@ int oracle_load_roms(oracle_ctx* c, uint32_t n_roms, const uint8_t* const* roms,
     if (!c || !roms || !bytes || !schemes || n_roms == 0 || n_roms > 65535) return ORC_E_INVAL;
     for (uint32_t r = 0; r < n_roms; r++) {
         if (!roms[r]) return ORC_E_INVAL;
-        if (!((schemes[r] == 0 && bytes[r] == 4096) || (schemes[r] == 1 && bytes[r] == 8192))) return ORC_E_ROM;
+        if (!m_rom_size_ok(bytes[r], schemes[r])) return ORC_E_ROM;
     }
     free_roms(c);
     c->roms = (ORom*)calloc(n_roms, sizeof(ORom));
@@ -211,7 +211,7 @@ static void build_cache_entry(oracle_ctx* c, uint32_t r, uint32_t k) {
         oracle_preprocess(fb[(total - 2) & 1], fb[(total - 1) & 1], c->cfg.gray_lut, obs);
     else
         oracle_preprocess(NULL, fb[(total - 1) & 1], c->cfg.gray_lut, obs);
-    m_to_record(&m, rom->cache_state + (size_t)k * 256);
+    m_to_record(&m, rom->cache_state + (size_t)k * ORC_STATE_BYTES);
     (void)last_rendered;
     free(fb[0]);
 }
@@ -224,7 +224,7 @@ static void reset_env(oracle_ctx* c, uint32_t e, uint8_t* obs_out) {
     uint32_t k = (uint32_t)((oracle_rng(c->cfg.seed, e, RESET, m->episode_idx) >> 32) % K);
     uint32_t step = m->step_idx, episode = m->episode_idx;
     ORom* rom = &c->roms[r];
-    m_from_record(m, rom->cache_state + (size_t)k * 256);
+    m_from_record(m, rom->cache_state + (size_t)k * ORC_STATE_BYTES);
     m->rom = rom->data;
     m->rom_size = rom->size;
     m->scheme = rom->scheme;
@@ -246,7 +246,7 @@ int oracle_assign(oracle_ctx* c, const uint16_t* env_rom) {
     for (uint32_t r = 0; r < c->n_roms; r++) {
         free(c->roms[r].cache_state);
         free(c->roms[r].cache_obs);
-        c->roms[r].cache_state = (uint8_t*)calloc(K, 256);
+        c->roms[r].cache_state = (uint8_t*)calloc(K, ORC_STATE_BYTES);
         c->roms[r].cache_obs = (uint8_t*)calloc(K, 84 * 84);
         if (!c->roms[r].cache_state || !c->roms[r].cache_obs) return ORC_E_NOMEM;
     }
@@ -394,7 +394,7 @@ int oracle_set_state(oracle_ctx* c, uint32_t env, const uint8_t* in) {
 
 int oracle_get_cache(oracle_ctx* c, uint32_t rom, uint32_t k, uint8_t* state, uint8_t* obs) {
     if (!c || !c->assigned || rom >= c->n_roms || k >= c->cfg.reset_cache_k) return ORC_E_INVAL;
-    if (state) memcpy(state, c->roms[rom].cache_state + (size_t)k * 256, 256);
+    if (state) memcpy(state, c->roms[rom].cache_state + (size_t)k * ORC_STATE_BYTES, ORC_STATE_BYTES);
     if (obs) memcpy(obs, c->roms[rom].cache_obs + (size_t)k * 84 * 84, 84 * 84);
     return ORC_OK;
 }
@@ -412,6 +412,7 @@ int oracle_poll_errors(oracle_ctx* c, uint32_t* first_env, uint32_t* bits) {
 
 int oracle_power_on(const uint8_t* rom, uint32_t bytes, uint32_t scheme, uint8_t* state) {
     if (!rom || !state) return ORC_E_INVAL;
+    if (!m_rom_size_ok(bytes, scheme)) return ORC_E_ROM;
     OMachine m;
     m_power_on(&m, rom, bytes, scheme);
     m_to_record(&m, state);
@@ -447,7 +448,7 @@ int oracle_batch_instructions(uint8_t* states, uint32_t n_states, const uint8_t*
     if (!states || !rom) return ORC_E_INVAL;
 #pragma omp parallel for schedule(static) num_threads(oracle_get_threads())
     for (long i = 0; i < (long)n_states; i++)
-        oracle_run_instructions(states + (size_t)i * 256, rom, bytes, scheme, n_instr, 0);
+        oracle_run_instructions(states + (size_t)i * ORC_STATE_BYTES, rom, bytes, scheme, n_instr, 0);
     return ORC_OK;
 }
 

@@ -26,8 +26,22 @@
  *    line ends the frame instead (FRAME_CAP); an undocumented opcode ends it
  *    too (ILLEGAL); both freeze the machine.
  *  - Power-on: A=X=Y=0, SP=$FD, P=$24, RAM and TIA zero, positions 0, timer
- *    interval 1024 with INTIM reading 0 from cycle 0 (phase 0), F8 bank 1, PC
- *    from the reset vector of the current bank, cycle 0.
+ *    interval 1024 with INTIM reading 0 from cycle 0 (phase 0), the last
+ *    4 KB bank of F8/F6/F4 cartridges, E0 slices 4, 5, 6 in segments 0-2,
+ *    3F slice 0, PC from the reset vector, cycle 0.
+ *  - Cartridges (see the bank-switching section below): 2 or 4 KB flat;
+ *    F8/F6/F4 with 2/4/8 banks of 4 KB picked by any data access to
+ *    $FF8-$FF9 / $FF6-$FF9 / $FF4-$FFB (switch first, then the access);
+ *    their Superchip forms with 128 B of extra RAM written at $1000-$107F and
+ *    read at $1080-$10FF; E0 (8 x 1 KB slices, segment 3 fixed to slice 7,
+ *    segment k of 0-2 set to slice n by an access to $FE0 + 8k + n); 3F
+ *    (2 KB slices: the upper half fixed to the last one, the lower half set
+ *    to slice v mod S by a write of v to $00-$3F, which also reaches the TIA).
+ *  - Undocumented opcodes: the stable ones (SLO, RLA, SRE, RRA, SAX, LAX,
+ *    DCP, ISC, ANC, ALR, ARR, SBX, LAS, SBC #, and the NOPs of every width,
+ *    which perform their read) run with the operations, cycle counts and
+ *    flags of the NMOS 6502's combined ALU/RMW behaviour; the twelve JAMs and
+ *    the unstable ANE, LXA, SHA, SHX, SHY and TAS fault (ILLEGAL).
  */
 #include "machine.h"
 
@@ -39,7 +53,9 @@ enum {
     ADC, AND, ASL, BCC, BCS, BEQ, BIT, BMI, BNE, BPL, BRK, BVC, BVS, CLC, CLD, CLI, CLV,
     CMP, CPX, CPY, DEC, DEX, DEY, EOR, INC, INX, INY, JMP, JSR, LDA, LDX, LDY, LSR, NOP,
     ORA, PHA, PHP, PLA, PLP, ROL, ROR, RTI, RTS, SBC, SEC, SED, SEI, STA, STX, STY, TAX,
-    TAY, TSX, TXA, TXS, TYA, ILL
+    TAY, TSX, TXA, TXS, TYA,
+    SLO, RLA, SRE, RRA, SAX, LAX, DCP, ISC, ANC, ALR, ARR, SBX, LAS,
+    ILL
 };
 enum { IMP, ACC, IMM, ZP, ZPX, ZPY, ABS, ABX, ABY, IZX, IZY, IND, REL };
 
@@ -108,11 +124,46 @@ static void build_table(void) {
     def(0x9A, TXS, IMP); def(0x98, TYA, IMP);
     def(0xCA, DEX, IMP); def(0x88, DEY, IMP); def(0xE8, INX, IMP); def(0xC8, INY, IMP);
     def(0xEA, NOP, IMP);
+
+    /* undocumented, stable: the read-modify-write + ALU pairs share the
+       eight-mode pattern of the ALU group (cc = 3) */
+    const int combo_mn[8] = {SLO, RLA, SRE, RRA, -1, -1, DCP, ISC};
+    for (int g = 0; g < 8; g++) {
+        if (combo_mn[g] < 0) continue;
+        int base = (g << 5) | 3;
+        def(base | 0x00, combo_mn[g], IZX);
+        def(base | 0x04, combo_mn[g], ZP);
+        def(base | 0x0C, combo_mn[g], ABS);
+        def(base | 0x10, combo_mn[g], IZY);
+        def(base | 0x14, combo_mn[g], ZPX);
+        def(base | 0x18, combo_mn[g], ABY);
+        def(base | 0x1C, combo_mn[g], ABX);
+    }
+    def(0x83, SAX, IZX); def(0x87, SAX, ZP); def(0x8F, SAX, ABS); def(0x97, SAX, ZPY);
+    def(0xA3, LAX, IZX); def(0xA7, LAX, ZP); def(0xAF, LAX, ABS); def(0xB3, LAX, IZY);
+    def(0xB7, LAX, ZPY); def(0xBF, LAX, ABY);
+    def(0xBB, LAS, ABY);
+    def(0x0B, ANC, IMM); def(0x2B, ANC, IMM); def(0x4B, ALR, IMM); def(0x6B, ARR, IMM);
+    def(0xCB, SBX, IMM); def(0xEB, SBC, IMM);
+    /* NOPs: implied, immediate, zero page, zero page,X, absolute, absolute,X */
+    const int nop_imp[6] = {0x1A, 0x3A, 0x5A, 0x7A, 0xDA, 0xFA};
+    const int nop_imm[5] = {0x80, 0x82, 0x89, 0xC2, 0xE2};
+    const int nop_zp[3] = {0x04, 0x44, 0x64};
+    const int nop_zpx[6] = {0x14, 0x34, 0x54, 0x74, 0xD4, 0xF4};
+    const int nop_abx[6] = {0x1C, 0x3C, 0x5C, 0x7C, 0xDC, 0xFC};
+    for (int i = 0; i < 6; i++) { def(nop_imp[i], NOP, IMP); def(nop_zpx[i], NOP, ZPX); def(nop_abx[i], NOP, ABX); }
+    for (int i = 0; i < 5; i++) def(nop_imm[i], NOP, IMM);
+    for (int i = 0; i < 3; i++) def(nop_zp[i], NOP, ZP);
+    def(0x0C, NOP, ABS);
     table_ready = 1;
 }
 
-static int is_store(int mn) { return mn == STA || mn == STX || mn == STY; }
+static int is_store(int mn) { return mn == STA || mn == STX || mn == STY || mn == SAX; }
 static int is_rmw(int mn) { return mn == ASL || mn == LSR || mn == ROL || mn == ROR || mn == INC || mn == DEC; }
+/* undocumented read-modify-write + ALU pairs */
+static int is_combo(int mn) {
+    return mn == SLO || mn == RLA || mn == SRE || mn == RRA || mn == DCP || mn == ISC;
+}
 
 /* Base cycle count of an instruction (MOS programming manual, Appendix A). */
 static int base_cycles(int mn, int mode) {
@@ -126,6 +177,12 @@ static int base_cycles(int mn, int mode) {
     }
     if (mode == REL) return 2;
     if (mode == IMP) return 2;
+    if (is_combo(mn)) {
+        switch (mode) {
+        case ZP: return 5; case ZPX: return 6; case ABS: return 6; case ABX: case ABY: return 7;
+        case IZX: case IZY: return 8;
+        }
+    }
     if (is_rmw(mn)) {
         switch (mode) {
         case ACC: return 2; case ZP: return 5; case ZPX: return 6; case ABS: return 6; case ABX: return 7;
@@ -146,17 +203,74 @@ static int base_cycles(int mn, int mode) {
 
 /* ---------------------------------------------------------------- devices */
 
+/* ------------------------------------------------------- bank switching */
+
+static int linear_banks(uint32_t scheme) {
+    switch (scheme) {
+    case SCH_F8: case SCH_F8SC: return 2;
+    case SCH_F6: case SCH_F6SC: return 4;
+    case SCH_F4: case SCH_F4SC: return 8;
+    default: return 1;
+    }
+}
+static int has_superchip(uint32_t scheme) {
+    return scheme == SCH_F8SC || scheme == SCH_F6SC || scheme == SCH_F4SC;
+}
+
+/* ROM sizes each scheme takes */
+int m_rom_size_ok(uint32_t size, uint32_t scheme) {
+    switch (scheme) {
+    case SCH_4K: return size == 2048 || size == 4096;
+    case SCH_E0: return size == 8192;
+    case SCH_3F: return size == 4096 || size == 8192 || size == 16384 || size == 32768;
+    default: return scheme < SCH_COUNT && size == 4096u * (uint32_t)linear_banks(scheme);
+    }
+}
+
+/* the ROM byte that cartridge address a (A12 set) shows under the current bank state */
 static uint8_t rom_byte(const OMachine* m, uint16_t a) {
-    uint32_t off = a & 0xFFF;
-    if (m->scheme == 1) off |= (uint32_t)m->bank << 12;
+    uint32_t lo = a & 0xFFF;
+    uint32_t off;
+    if (m->scheme == SCH_E0) {
+        uint32_t seg = lo >> 10;
+        uint32_t slice = seg == 3 ? 7 : (m->bank >> (3 * seg)) & 7;
+        off = slice * 1024 + (lo & 0x3FF);
+    } else if (m->scheme == SCH_3F) {
+        off = lo < 0x800 ? (uint32_t)m->bank * 2048 + lo : m->rom_size - 2048 + (lo - 0x800);
+    } else if (m->scheme == SCH_4K) {
+        off = lo % m->rom_size;                      /* a 2 KB ROM shows twice */
+    } else {
+        off = (uint32_t)m->bank * 4096 + lo;
+    }
     return m->rom[off];
 }
 
-/* F8: any data access to $xFF8 / $xFF9 selects bank 0 / 1 (before the read). */
+/* Hotspots of a data access to cartridge address a (before the access). */
 static void cart_access(OMachine* m, uint16_t a) {
-    if (m->scheme != 1) return;
-    if ((a & 0xFFF) == 0xFF8) m->bank = 0;
-    if ((a & 0xFFF) == 0xFF9) m->bank = 1;
+    uint32_t lo = a & 0xFFF;
+    int nb = linear_banks(m->scheme);
+    if (nb > 1) {
+        uint32_t first = nb == 2 ? 0xFF8 : (nb == 4 ? 0xFF6 : 0xFF4);
+        if (lo >= first && lo < first + (uint32_t)nb) m->bank = (uint16_t)(lo - first);
+    } else if (m->scheme == SCH_E0 && lo >= 0xFE0 && lo <= 0xFF7) {
+        uint32_t seg = (lo - 0xFE0) / 8, slice = lo & 7;
+        m->bank = (uint16_t)((m->bank & ~(7u << (3 * seg))) | (slice << (3 * seg)));
+    }
+}
+
+/* data read of cartridge address a: hotspots, the Superchip RAM window, ROM */
+static uint8_t cart_read(OMachine* m, uint16_t a) {
+    cart_access(m, a);
+    uint32_t lo = a & 0xFFF;
+    if (has_superchip(m->scheme) && lo < 0x100)
+        return lo < 0x80 ? 0x00 : m->xram[lo & 0x7F];   /* the write port reads as 0 */
+    return rom_byte(m, a);
+}
+
+static void cart_write(OMachine* m, uint16_t a, uint8_t v) {
+    cart_access(m, a);
+    uint32_t lo = a & 0xFFF;
+    if (has_superchip(m->scheme) && lo < 0x80) m->xram[lo] = v;   /* writes to the read port do nothing */
 }
 
 static uint8_t tia_read(const OMachine* m, uint16_t reg) {
@@ -240,13 +354,14 @@ static void tia_write(OMachine* m, uint16_t reg, uint8_t v) {
 /* data-access bus (side effects: bank switching, TIA and timer writes) */
 static uint8_t bus_read(OMachine* m, uint16_t addr) {
     uint16_t a = addr & 0x1FFF;
-    if (a & 0x1000) { cart_access(m, a); return rom_byte(m, a); }
+    if (a & 0x1000) return cart_read(m, a);
     if ((a & 0x80) == 0) return tia_read(m, a);
     if ((a & 0x200) == 0) return m->ram[a & 0x7F];
     return riot_read(m, a);
 }
 
-/* instruction-fetch bus: the same map, no side effects */
+/* instruction-fetch bus: the same map without side effects; the cartridge
+   area always shows ROM (the Superchip RAM window is for data only) */
 static uint8_t bus_peek(const OMachine* m, uint16_t addr) {
     uint16_t a = addr & 0x1FFF;
     if (a & 0x1000) return rom_byte(m, a);
@@ -257,8 +372,13 @@ static uint8_t bus_peek(const OMachine* m, uint16_t addr) {
 
 static void bus_write(OMachine* m, uint16_t addr, uint8_t v) {
     uint16_t a = addr & 0x1FFF;
-    if (a & 0x1000) { cart_access(m, a); return; }
-    if ((a & 0x80) == 0) { tia_write(m, a, v); return; }
+    if (a & 0x1000) { cart_write(m, a, v); return; }
+    if ((a & 0x80) == 0) {
+        /* 3F: a write to $00-$3F (not its mirrors) also picks the lower slice */
+        if (m->scheme == SCH_3F && a <= 0x3F) m->bank = (uint16_t)(v % (m->rom_size / 2048));
+        tia_write(m, a, v);
+        return;
+    }
     if ((a & 0x200) == 0) { m->ram[a & 0x7F] = v; return; }
     riot_write(m, a, v);
 }
@@ -387,6 +507,33 @@ static void op_compare(OMachine* m, uint8_t reg, uint8_t v) {
     set_nz(m, d);
 }
 
+/* ARR: A AND operand, rotated right through the carry.  Binary mode: N, Z
+   from the result, C = bit 6, V = bit 6 XOR bit 5.  Decimal mode (NMOS): N
+   is the incoming carry, Z from the rotated value, V = bit 6 changed by the
+   rotate, then each nibble is BCD-corrected from the unrotated AND (low: +6
+   when low nibble + its bit 0 exceeds 5; high: +$60 and C set when high
+   nibble + its bit 4 exceeds $50, else C clear). */
+static void op_arr(OMachine* m, uint8_t imm) {
+    uint8_t t = (uint8_t)(m->a & imm);
+    int cin = m->p & FL_C;
+    uint8_t r = (uint8_t)((t >> 1) | (cin << 7));
+    if (!(m->p & FL_D)) {
+        m->a = r;
+        set_nz(m, r);
+        m->p = (uint8_t)(m->p & ~(FL_C | FL_V));
+        if (r & 0x40) m->p |= FL_C;
+        if (((r >> 6) ^ (r >> 5)) & 1) m->p |= FL_V;
+        return;
+    }
+    m->p = (uint8_t)(m->p & ~(FL_N | FL_Z | FL_V | FL_C));
+    if (cin) m->p |= FL_N;
+    if (r == 0) m->p |= FL_Z;
+    if ((t ^ r) & 0x40) m->p |= FL_V;
+    if ((t & 0x0F) + (t & 0x01) > 5) r = (uint8_t)((r & 0xF0) | ((r + 6) & 0x0F));
+    if ((t & 0xF0) + (t & 0x10) > 0x50) { r = (uint8_t)(r + 0x60); m->p |= FL_C; }
+    m->a = r;
+}
+
 static int branch_taken(const OMachine* m, int mn) {
     switch (mn) {
     case BPL: return !(m->p & FL_N);
@@ -475,7 +622,7 @@ int m_step_instruction(OMachine* m) {
         taken = branch_taken(m, mn);
         target = (uint16_t)(next_pc + (int8_t)b1);
         if (taken) n += 1 + ((target & 0xFF00) != (next_pc & 0xFF00));
-    } else if (cross && !is_store(mn) && !is_rmw(mn)) {
+    } else if (cross && !is_store(mn) && !is_rmw(mn) && !is_combo(mn)) {
         n += 1;                        /* page-crossing penalty of indexed reads */
     }
 
@@ -513,6 +660,31 @@ int m_step_instruction(OMachine* m) {
         if (mode == ACC) m->a = shift_op(m, mn, m->a);
         else { v = bus_read(m, ea); bus_write(m, ea, shift_op(m, mn, v)); }
         break;
+    case SLO: v = bus_read(m, ea); v = shift_op(m, ASL, v); bus_write(m, ea, v);
+        m->a |= v; set_nz(m, m->a); break;
+    case RLA: v = bus_read(m, ea); v = shift_op(m, ROL, v); bus_write(m, ea, v);
+        m->a &= v; set_nz(m, m->a); break;
+    case SRE: v = bus_read(m, ea); v = shift_op(m, LSR, v); bus_write(m, ea, v);
+        m->a ^= v; set_nz(m, m->a); break;
+    case RRA: v = bus_read(m, ea); v = shift_op(m, ROR, v); bus_write(m, ea, v);
+        op_adc(m, v); break;                   /* the carry out of the rotate feeds the add */
+    case DCP: v = bus_read(m, ea); v = (uint8_t)(v - 1); bus_write(m, ea, v);
+        op_compare(m, m->a, v); break;
+    case ISC: v = bus_read(m, ea); v = (uint8_t)(v + 1); bus_write(m, ea, v);
+        op_sbc(m, v); break;
+    case SAX: bus_write(m, ea, (uint8_t)(m->a & m->x)); break;
+    case LAX: m->a = m->x = bus_read(m, ea); set_nz(m, m->a); break;
+    case LAS: m->sp &= bus_read(m, ea); m->a = m->x = m->sp; set_nz(m, m->a); break;
+    case ANC: m->a &= b1; set_nz(m, m->a); m->p = (uint8_t)((m->p & ~FL_C) | (m->a >> 7)); break;
+    case ALR: m->a &= b1; m->p = (uint8_t)((m->p & ~FL_C) | (m->a & 1)); m->a >>= 1; set_nz(m, m->a); break;
+    case ARR: op_arr(m, b1); break;
+    case SBX: {
+        uint8_t t = (uint8_t)(m->a & m->x);
+        m->p = (uint8_t)((m->p & ~FL_C) | (t >= b1 ? FL_C : 0));
+        m->x = (uint8_t)(t - b1);
+        set_nz(m, m->x);
+        break;
+    }
     case INX: m->x++; set_nz(m, m->x); break;
     case INY: m->y++; set_nz(m, m->y); break;
     case DEX: m->x--; set_nz(m, m->x); break;
@@ -530,7 +702,7 @@ int m_step_instruction(OMachine* m) {
     case CLV: m->p &= (uint8_t)~FL_V; break;
     case CLD: m->p &= (uint8_t)~FL_D; break;
     case SED: m->p |= FL_D; break;
-    case NOP: break;
+    case NOP: if (mode != IMP && mode != IMM) (void)bus_read(m, ea); break;   /* the read happens */
     case PHA: push(m, m->a); break;
     case PHP: push(m, (uint8_t)(m->p | FL_B | FL_U)); break;
     case PLA: m->a = pull(m); set_nz(m, m->a); break;
@@ -629,7 +801,9 @@ void m_power_on(OMachine* m, const uint8_t* rom, uint32_t size, uint32_t scheme)
     m->rom = rom;
     m->rom_size = size;
     m->scheme = scheme;
-    m->bank = scheme == 1 ? 1 : 0;
+    if (scheme == SCH_E0) m->bank = 4 | (5 << 3) | (6 << 6);
+    else if (scheme == SCH_3F) m->bank = 0;
+    else m->bank = (uint16_t)(linear_banks(scheme) - 1);     /* the last 4 KB bank */
     m->sp = 0xFD;
     m->p = 0x24;
     m->tim_interval = 1024;            /* INTIM reads 0 from cycle 0, interval 1024 */
@@ -650,8 +824,9 @@ void m_to_record(const OMachine* src, uint8_t* out) {
     OMachine m = *src;
     /* the timer as a read at `cycle` would see it (advance over a WSYNC halt) */
     while (m.beam_cycle < m.cycle) { timer_cycle(&m); m.beam_cycle++; }
-    memset(out, 0, 256);
-    out[0] = m.a; out[1] = m.x; out[2] = m.y; out[3] = m.sp; out[4] = m.p; out[5] = m.bank;
+    memset(out, 0, 384);
+    out[0] = m.a; out[1] = m.x; out[2] = m.y; out[3] = m.sp; out[4] = m.p; out[5] = (uint8_t)m.bank;
+    out[31] = (uint8_t)(m.bank >> 8);
     put16(out + 6, m.pc);
     put64(out + 8, m.cycle);
     put64(out + 16, m.frame_line0);
@@ -670,10 +845,12 @@ void m_to_record(const OMachine* src, uint8_t* out) {
     out[192] = m.prev_action;
     out[194] = m.err;
     put64(out + 200, m.instr_count);
+    memcpy(out + 256, m.xram, 128);
 }
 
 void m_from_record(OMachine* m, const uint8_t* in) {
-    m->a = in[0]; m->x = in[1]; m->y = in[2]; m->sp = in[3]; m->p = in[4]; m->bank = in[5];
+    m->a = in[0]; m->x = in[1]; m->y = in[2]; m->sp = in[3]; m->p = in[4];
+    m->bank = (uint16_t)(in[5] | (in[31] << 8));
     m->pc = get16(in + 6);
     m->cycle = get64(in + 8);
     m->beam_cycle = m->cycle;
@@ -694,4 +871,5 @@ void m_from_record(OMachine* m, const uint8_t* in) {
     m->prev_action = in[192];
     m->err = in[194];
     m->instr_count = get64(in + 200);
+    memcpy(m->xram, in + 256, 128);
 }

@@ -18,8 +18,11 @@ typedef struct {
     /* cartridge */
     const uint8_t* rom;
     uint32_t rom_size;
-    uint32_t scheme;            /* 0 = 4 KB, 1 = F8 (2 x 4 KB) */
-    uint8_t bank;
+    uint32_t scheme;            /* SCH_* below */
+    uint16_t bank;              /* bank state: 4 KB bank (4K/F8/F6/F4 and their
+                                   Superchip forms), E0 slices s0 | s1 << 3 | s2 << 6,
+                                   or the 3F slice of the lower 2 KB */
+    uint8_t xram[128];          /* Superchip RAM */
     /* 6507 */
     uint8_t a, x, y, sp, p;
     uint16_t pc;
@@ -50,11 +53,24 @@ typedef struct {
     int timer_written, wsync_hit, vsync_on;
 } OMachine;
 
+/* cartridge schemes */
+#define SCH_4K 0
+#define SCH_F8 1
+#define SCH_F6 2
+#define SCH_F4 3
+#define SCH_F8SC 4
+#define SCH_F6SC 5
+#define SCH_F4SC 6
+#define SCH_E0 7
+#define SCH_3F 8
+#define SCH_COUNT 9
+
 /* frame end reasons */
 #define END_VSYNC 1
 #define END_CAP 2
 #define END_ILLEGAL 3
 
+int m_rom_size_ok(uint32_t size, uint32_t scheme);
 void m_power_on(OMachine* m, const uint8_t* rom, uint32_t size, uint32_t scheme);
 int m_step_instruction(OMachine* m);      /* 0 or an END_* code */
 int m_run_frame(OMachine* m, uint8_t* fb, uint64_t* end_cycle);

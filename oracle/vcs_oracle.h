@@ -16,20 +16,22 @@
  * the public hardware definition and the conventions written next to each
  * function in machine.c and env.c.
  *
- * Machine-state record (256 bytes, little-endian), the exchange format that
+ * Machine-state record (384 bytes, little-endian), the exchange format that
  * both this oracle and the GPU library write independently:
- *    0 A   1 X   2 Y   3 SP   4 P   5 bank   6..7 PC
+ *    0 A   1 X   2 Y   3 SP   4 P   5 bank state bits 0-7   6..7 PC
  *    8..15  cycle      next instruction start cycle since power-on
  *   16..23  frame_line0   scanline of the write that began the current frame
  *   24 INTIM value a read at `cycle` would see   25 timer-expired flag (0/1)
  *   26..27 timer interval (1, 8, 64, 1024)
  *   28..29 timer phase: cycles since the last decrement (0 once expired)
+ *   31 bank state bits 8-15
  *   32..159 RAM ($80..$FF)
  *  160 VSYNC 161 VBLANK 162 COLUP0 163 COLUP1 164 COLUPF 165 COLUBK
  *  166 CTRLPF 167 REFP0 168 REFP1 169 PF0 170 PF1 171 PF2 172 GRP0
  *  173 GRP1 174 HMP0 175 HMP1 176 P0 position 177 P1 position
  *  180..183 rom_id   184..187 step_idx   188..191 episode_idx
  *  192 prev_action   193 (0)   194 err bits   200..207 instructions executed
+ *  256..383 Superchip RAM (0 for other cartridges)
  *  all other bytes 0.
  *
  * Parity status: every function is pinned by the tests under tests/ (ISA
@@ -48,7 +50,7 @@
 extern "C" {
 #endif
 
-#define ORC_STATE_BYTES 256
+#define ORC_STATE_BYTES 384
 #define ORC_FRAME_H 210
 #define ORC_FRAME_W 160
 #define ORC_OBS 84

@@ -1,4 +1,5 @@
-"""A small two-pass assembler for the documented NMOS 6502 instruction set.
+"""A small two-pass assembler for the NMOS 6502 instruction set (documented
+opcodes, plus the stable undocumented ones for test programs).
 
 Input tooling only: it turns hand-written test programs and the generated
 synthetic cartridges into bytes.  It holds no part of the emulator; both the
@@ -25,8 +26,8 @@ Syntax (one statement per line, ``;`` starts a comment)::
 Expressions: ``$hex``, ``%bin``, decimal, symbols, ``*`` (location counter),
 ``+``/``-``, unary ``<`` (low byte) and ``>`` (high byte).
 
-Opcode encodings follow the MOS MCS6500 programming manual's instruction
-matrix (documented opcodes only).
+Documented opcode encodings follow the MOS MCS6500 programming manual's
+instruction matrix; the undocumented ones the published NMOS opcode matrix.
 """
 
 from __future__ import annotations
@@ -72,6 +73,28 @@ OPCODES: dict[str, dict[str, int]] = {
     "tax": dict(imp=0xAA), "tay": dict(imp=0xA8), "tsx": dict(imp=0xBA),
     "txa": dict(imp=0x8A), "txs": dict(imp=0x9A), "tya": dict(imp=0x98),
 }
+
+# The stable undocumented NMOS opcodes (one encoding each; the duplicate
+# encodings such as ANC $2B, SBC $EB and the other NOPs are emitted with
+# .byte).  Mnemonics as in the common unintended-opcode tables.
+UNDOC_OPCODES: dict[str, dict[str, int]] = {
+    "slo": dict(zp=0x07, zpx=0x17, abs=0x0F, absx=0x1F, absy=0x1B, indx=0x03, indy=0x13),
+    "rla": dict(zp=0x27, zpx=0x37, abs=0x2F, absx=0x3F, absy=0x3B, indx=0x23, indy=0x33),
+    "sre": dict(zp=0x47, zpx=0x57, abs=0x4F, absx=0x5F, absy=0x5B, indx=0x43, indy=0x53),
+    "rra": dict(zp=0x67, zpx=0x77, abs=0x6F, absx=0x7F, absy=0x7B, indx=0x63, indy=0x73),
+    "sax": dict(zp=0x87, zpy=0x97, abs=0x8F, indx=0x83),
+    "lax": dict(zp=0xA7, zpy=0xB7, abs=0xAF, absy=0xBF, indx=0xA3, indy=0xB3),
+    "dcp": dict(zp=0xC7, zpx=0xD7, abs=0xCF, absx=0xDF, absy=0xDB, indx=0xC3, indy=0xD3),
+    "isc": dict(zp=0xE7, zpx=0xF7, abs=0xEF, absx=0xFF, absy=0xFB, indx=0xE3, indy=0xF3),
+    "anc": dict(imm=0x0B), "alr": dict(imm=0x4B), "arr": dict(imm=0x6B), "sbx": dict(imm=0xCB),
+    "las": dict(absy=0xBB),
+    "nop": dict(imm=0x80, zp=0x04, zpx=0x14, abs=0x0C, absx=0x1C),
+}
+
+
+def _modes(mnem: str) -> dict[str, int]:
+    return {**UNDOC_OPCODES.get(mnem, {}), **OPCODES.get(mnem, {})}
+
 
 MODE_LEN = dict(imp=1, acc=1, imm=2, zp=2, zpx=2, zpy=2, abs=3, absx=3, absy=3,
                 indx=2, indy=2, ind=3, rel=2)
@@ -186,7 +209,7 @@ class Assembler:
         return label, line.strip()
 
     def _operand_mode(self, mnem: str, opnd: str, force_abs: bool, syms, pc, strict):
-        modes = OPCODES[mnem]
+        modes = _modes(mnem)
         o = opnd.strip()
         if o == "" or o.lower() == "a":
             if "acc" in modes:
@@ -273,7 +296,7 @@ class Assembler:
                         continue
                     force_abs = op.endswith(".w")
                     mnem = op[:-2] if force_abs else op
-                    if mnem not in OPCODES:
+                    if mnem not in OPCODES and mnem not in UNDOC_OPCODES:
                         raise AsmError(f"unknown mnemonic {op!r}")
                     if pass_no == 1:
                         mode, expr = self._operand_mode(mnem, arg, force_abs, syms, pc, False)
@@ -281,7 +304,7 @@ class Assembler:
                     else:
                         mode = sizing[ln]
                         _, expr = self._operand_mode(mnem, arg, force_abs, syms, pc, False)
-                    opc = OPCODES[mnem].get(mode)
+                    opc = _modes(mnem).get(mode)
                     if opc is None:
                         raise AsmError(f"{mnem} has no {mode} mode")
                     data = [opc]

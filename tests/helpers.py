@@ -21,11 +21,12 @@ def u64(rec, o):
 
 def decode(rec):
     rec = np.asarray(rec, dtype=np.uint8)
-    d = dict(a=int(rec[0]), x=int(rec[1]), y=int(rec[2]), sp=int(rec[3]), p=int(rec[4]), bank=int(rec[5]),
+    d = dict(a=int(rec[0]), x=int(rec[1]), y=int(rec[2]), sp=int(rec[3]), p=int(rec[4]), bank=int(rec[5]) | (int(rec[31]) << 8),
              pc=u16(rec, 6), cycle=u64(rec, 8), frame_line0=u64(rec, 16), intim=int(rec[24]),
              expired=int(rec[25]), interval=u16(rec, 26), phase=u16(rec, 28), ram=rec[32:160].copy(),
              rom_id=u32(rec, 180), step_idx=u32(rec, 184), episode_idx=u32(rec, 188),
-             prev_action=int(rec[192]), err=int(rec[194]), instr=u64(rec, 200))
+             prev_action=int(rec[192]), err=int(rec[194]), instr=u64(rec, 200),
+             xram=rec[256:384].copy())
     for i, n in enumerate(TIA_NAMES):
         d[n] = int(rec[160 + i])
     return d
@@ -33,10 +34,12 @@ def decode(rec):
 
 def set_fields(rec, **kw):
     rec = np.array(rec, dtype=np.uint8, copy=True)
-    off1 = dict(a=0, x=1, y=2, sp=3, p=4, bank=5)
+    off1 = dict(a=0, x=1, y=2, sp=3, p=4)
     for k, v in kw.items():
         if k in off1:
             rec[off1[k]] = v
+        elif k == "bank":
+            rec[5], rec[31] = v & 0xFF, v >> 8
         elif k == "pc":
             rec[6], rec[7] = v & 0xFF, v >> 8
         elif k == "cycle":

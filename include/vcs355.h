@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define VCS_STATE_BYTES 256      /* machine-state record, see vcs_get_state */
+#define VCS_STATE_BYTES 384      /* machine-state record, see vcs_get_state */
 #define VCS_FRAME_H 210
 #define VCS_FRAME_W 160
 #define VCS_OBS 84
@@ -56,7 +56,20 @@ enum {
     VCS_E_BUDGET = -6   /* the allocation would exceed hbm_budget_bytes */
 };
 
-enum { VCS_BANK_4K = 0, VCS_BANK_F8 = 1 };
+/* cartridge schemes (vcs_load_roms) */
+enum {
+    VCS_BANK_4K = 0,     /* 2 or 4 KB, no banks (2 KB shows twice) */
+    VCS_BANK_F8 = 1,     /* 8 KB: 2 x 4 KB banks, hotspots $1FF8-$1FF9 */
+    VCS_BANK_F6 = 2,     /* 16 KB: 4 banks, hotspots $1FF6-$1FF9 */
+    VCS_BANK_F4 = 3,     /* 32 KB: 8 banks, hotspots $1FF4-$1FFB */
+    VCS_BANK_F8SC = 4,   /* F8/F6/F4 with the Superchip's 128 B of RAM: */
+    VCS_BANK_F6SC = 5,   /*   written at $1000-$107F, read at $1080-$10FF */
+    VCS_BANK_F4SC = 6,
+    VCS_BANK_E0 = 7,     /* 8 KB: 8 x 1 KB slices; $1C00-$1FFF fixed to slice 7,
+                            segment k (0-2) set to slice n by an access to $1FE0 + 8k + n */
+    VCS_BANK_3F = 8      /* 4, 8, 16 or 32 KB of 2 KB slices; $1800-$1FFF fixed to the
+                            last one, $1000-$17FF set to slice v mod S by writing v to $00-$3F */
+};
 enum { VCS_RENDER_ALL = 0, VCS_RENDER_LAST2 = 1 };
 
 /* per-env error bits (vcs_poll_errors) */
@@ -98,9 +111,12 @@ typedef struct vcs_ctx vcs_ctx;
 int vcs_create(const vcs_config* cfg, vcs_ctx** out);
 void vcs_destroy(vcs_ctx* ctx);
 
-/* Copy n_roms cartridges to the device.  rom_bytes[r] is 4096 (VCS_BANK_4K) or
-   8192 (VCS_BANK_F8, two 4 KB banks selected by accesses to $1FF8/$1FF9).
-   The host buffers are copied; the caller keeps ownership. */
+/* Copy n_roms cartridges to the device.  rom_bytes[r] must be a size the
+   scheme takes (see VCS_BANK_*; VCS_E_ROM otherwise).  Bank hotspots switch
+   on any data access, before it; instruction fetches see ROM even in the
+   Superchip RAM window, and a read of its write port returns 0.  Power-on
+   bank: the last 4 KB bank (F8/F6/F4), E0 slices 4, 5, 6, 3F slice 0.  The
+   host buffers are copied; the caller keeps ownership. */
 int vcs_load_roms(vcs_ctx* ctx, uint32_t n_roms, const uint8_t* const* rom_host,
                   const uint32_t* rom_bytes, const uint32_t* scheme);
 
@@ -136,19 +152,21 @@ int vcs_step(vcs_ctx* ctx, const int32_t* env_ids_dev, const uint8_t* actions_de
 int vcs_step_pipe(vcs_ctx* ctx, uint32_t pipe, const int32_t* env_ids_dev, const uint8_t* actions_dev, uint32_t n,
                   uint8_t* obs_dev, int32_t* reward_dev, uint8_t* done_dev, uint8_t* frames_dev, void* stream);
 
-/* Machine-state record (256 bytes, little-endian) of one env:
-     0 A  1 X  2 Y  3 SP  4 P  5 bank  6..7 PC
+/* Machine-state record (384 bytes, little-endian) of one env:
+     0 A  1 X  2 Y  3 SP  4 P  5 bank state bits 0-7  6..7 PC
      8..15 cycle (start of the next instruction, since power-on)
     16..23 scanline of the write that began the current frame
     24 INTIM a read at `cycle` would return   25 timer expired (0/1)
     26..27 timer interval (1, 8, 64, 1024)   28..29 cycles since the last
-           decrement (0 once expired)
+           decrement (0 once expired)   31 bank state bits 8-15 (the state:
+           the 4 KB bank; E0 slices s0 | s1 << 3 | s2 << 6; 3F the lower slice)
     32..159 RAM $80..$FF
    160 VSYNC 161 VBLANK 162 COLUP0 163 COLUP1 164 COLUPF 165 COLUBK 166 CTRLPF
    167 REFP0 168 REFP1 169 PF0 170 PF1 171 PF2 172 GRP0 173 GRP1 174 HMP0
    175 HMP1 176 P0 position 177 P1 position
    180..183 rom_id 184..187 step count 188..191 episode count 192 previous
-   action 194 error bits 200..207 instructions executed; other bytes 0.
+   action 194 error bits 200..207 instructions executed 256..383
+   Superchip RAM; other bytes 0.
    get/set synchronise the device. */
 int vcs_get_state(vcs_ctx* ctx, uint32_t env_id, uint8_t* out_host);
 int vcs_set_state(vcs_ctx* ctx, uint32_t env_id, const uint8_t* in_host);

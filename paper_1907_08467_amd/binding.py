@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(HERE, "libvcs355.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vcs355.h")
 
 VCS_OK, VCS_E_INVAL, VCS_E_NOMEM, VCS_E_ROM, VCS_E_HIP, VCS_E_STATE, VCS_E_BUDGET = 0, -1, -2, -3, -4, -5, -6
-VCS_BANK_4K, VCS_BANK_F8 = 0, 1
+VCS_BANK_4K, VCS_BANK_F8, VCS_BANK_F6, VCS_BANK_F4, VCS_BANK_F8SC, VCS_BANK_F6SC, VCS_BANK_F4SC, VCS_BANK_E0, \
+    VCS_BANK_3F = range(9)
 VCS_RENDER_ALL, VCS_RENDER_LAST2 = 0, 1
 ERR_ILLEGAL, ERR_FRAME_CAP, ERR_BAD_ACTION, ERR_BAD_ID, ERR_LOG = 1, 2, 4, 8, 16
-STATE_BYTES = 256
+STATE_BYTES = 384
 
 
 class VcsConfig(ctypes.Structure):

@@ -66,9 +66,13 @@ struct vcs_ctx {
     uint32_t n_roms = 0;
     uint8_t* d_roms = nullptr;
     uint32_t* d_pre = nullptr;
-    uint32_t* d_schemes = nullptr;
+    size_t pre_words = 0;
+    CartMap* d_cmap = nullptr;
+    uint32_t* d_pre_off = nullptr;
     std::vector<uint32_t> h_schemes;
+    std::vector<RomInfo> h_rinfo;
     std::vector<uint8_t> h_roms;   // [n_roms][kRomSlot]
+    uint32_t rom_lds = 8192;       // cartridge bytes the interpreter stages in LDS
 
     // envs
     DevEnv* d_envs = nullptr;
@@ -151,11 +155,14 @@ DevEnv power_on(const vcs_ctx* c, uint32_t r) {
     DevEnv e;
     std::memset(&e, 0, sizeof(e));
     const uint8_t* rom = c->h_roms.data() + (size_t)r * kRomSlot;
-    const uint32_t bank = c->h_schemes[r] == VCS_BANK_F8 ? 1 : 0;
+    const RomInfo& R = c->h_rinfo[r];
+    // power-on bank: the last 4 KB bank; E0 slices 4, 5, 6; 3F slice 0
+    const uint32_t bank = R.kind == CART_E0 ? (4u | (5u << 3) | (6u << 6)) : R.kind == CART_3F ? 0u : R.n_vbanks - 1;
     e.sp = 0xFD;
     e.p = 0x24;
     e.bank = (uint8_t)bank;
-    e.pc = (uint16_t)(rom[(bank << 12) | 0xFFC] | (rom[(bank << 12) | 0xFFD] << 8));
+    e.bank_hi = (uint8_t)(bank >> 8);
+    e.pc = (uint16_t)(rom[cart_rom_off(R, bank, 0x1FFC)] | (rom[cart_rom_off(R, bank, 0x1FFD)] << 8));
     e.tv = 0;
     e.tshift = 10;
     e.tbase = 0;
@@ -167,6 +174,7 @@ DevEnv power_on(const vcs_ctx* c, uint32_t r) {
 void to_record(const DevEnv& e, uint8_t* out) {
     std::memset(out, 0, VCS_STATE_BYTES);
     out[0] = e.a; out[1] = e.x; out[2] = e.y; out[3] = e.sp; out[4] = e.p; out[5] = e.bank;
+    out[31] = e.bank_hi;
     std::memcpy(out + 6, &e.pc, 2);
     std::memcpy(out + 8, &e.cycle, 8);
     std::memcpy(out + 16, &e.frame_line0, 8);
@@ -192,11 +200,13 @@ void to_record(const DevEnv& e, uint8_t* out) {
     out[192] = e.prev_action;
     out[194] = e.err;
     std::memcpy(out + 200, &e.instr, 8);
+    std::memcpy(out + 256, e.xram, 128);
 }
 
 int from_record(const uint8_t* in, DevEnv* e) {
     std::memset(e, 0, sizeof(*e));
     e->a = in[0]; e->x = in[1]; e->y = in[2]; e->sp = in[3]; e->p = in[4]; e->bank = in[5];
+    e->bank_hi = in[31];
     std::memcpy(&e->pc, in + 6, 2);
     std::memcpy(&e->cycle, in + 8, 8);
     std::memcpy(&e->frame_line0, in + 16, 8);
@@ -230,6 +240,7 @@ int from_record(const uint8_t* in, DevEnv* e) {
     e->prev_action = in[192];
     e->err = in[194];
     std::memcpy(&e->instr, in + 200, 8);
+    std::memcpy(e->xram, in + 256, 128);
     return 0;
 }
 
@@ -331,7 +342,8 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
     ia.n_tiles = n_tiles;
     ia.envs = c->d_envs;
     ia.roms = c->d_roms;
-    ia.schemes = c->d_schemes;
+    ia.cmap = c->d_cmap;
+    ia.pre_off = c->d_pre_off;
     ia.pre = c->d_pre;
     ia.actions = actions;
     ia.nframes_per_out = nullptr;
@@ -355,7 +367,7 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
         grid = c->launch.workers;
     }
     begin_timed(c, 0, s);
-    launch_interp(ia, grid, c->launch.tile_envs, s);
+    launch_interp(ia, grid, c->launch.tile_envs, c->rom_lds, s);
     end_timed(c, s);
 
     // a done env restarts from the cache now (state, and its observation);
@@ -502,24 +514,59 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
                   const uint32_t* scheme) {
     if (!c || !rom_host || !rom_bytes || !scheme) return fail(VCS_E_INVAL, "null argument");
     if (n_roms == 0 || n_roms > 65535) return fail(VCS_E_INVAL, "n_roms must be in [1, 65535]");
+    std::vector<RomInfo> info(n_roms);
+    size_t pre_words = 0;
+    uint32_t max_bytes = 0;
     for (uint32_t r = 0; r < n_roms; ++r) {
         if (!rom_host[r]) return fail(VCS_E_INVAL, "null ROM pointer");
-        const bool ok4 = scheme[r] == VCS_BANK_4K && rom_bytes[r] == 4096;
-        const bool ok8 = scheme[r] == VCS_BANK_F8 && rom_bytes[r] == 8192;
-        if (!ok4 && !ok8) return fail(VCS_E_ROM, "ROM " + std::to_string(r) + ": need 4096 B (4K) or 8192 B (F8)");
+        const uint32_t sch = scheme[r], b = rom_bytes[r];
+        RomInfo& R = info[r];
+        R = RomInfo{};
+        bool ok = false;
+        if (sch == VCS_BANK_4K) {
+            ok = b == 2048 || b == 4096;
+            R.kind = CART_LINEAR;
+            R.n_vbanks = 1;
+        } else if (sch >= VCS_BANK_F8 && sch <= VCS_BANK_F4SC) {
+            const uint32_t nb = (sch == VCS_BANK_F8 || sch == VCS_BANK_F8SC) ? 2 : (sch == VCS_BANK_F6 || sch == VCS_BANK_F6SC) ? 4 : 8;
+            ok = b == 4096 * nb;
+            R.kind = CART_LINEAR;
+            R.n_vbanks = nb;
+            R.hs_n = nb;
+            R.hs_first = nb == 2 ? 0xFF8 : nb == 4 ? 0xFF6 : 0xFF4;
+            R.sc = sch >= VCS_BANK_F8SC ? 1 : 0;
+        } else if (sch == VCS_BANK_E0) {
+            ok = b == 8192;
+            R.kind = CART_E0;
+            R.n_vbanks = 512;
+        } else if (sch == VCS_BANK_3F) {
+            ok = b == 4096 || b == 8192 || b == 16384 || b == 32768;
+            R.kind = CART_3F;
+            R.n_vbanks = b / 2048;
+            R.tf_mask = b / 2048 - 1;
+            R.tf_last = b - 2048;
+        }
+        if (!ok)
+            return fail(VCS_E_ROM, "ROM " + std::to_string(r) + ": scheme " + std::to_string(sch) + " does not take " +
+                                       std::to_string(b) + " bytes");
+        R.pre_off = (uint32_t)pre_words;
+        pre_words += (size_t)R.n_vbanks * 4096;
+        max_bytes = std::max(max_bytes, b);
     }
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
     dev_free(c, c->d_roms, (size_t)c->n_roms * kRomSlot);
-    dev_free(c, c->d_pre, (size_t)c->n_roms * kRomSlot * sizeof(uint32_t));
-    dev_free(c, c->d_schemes, (size_t)c->n_roms * 4);
+    dev_free(c, c->d_pre, c->pre_words * sizeof(uint32_t));
+    dev_free(c, c->d_cmap, (size_t)c->n_roms * sizeof(CartMap));
+    dev_free(c, c->d_pre_off, (size_t)c->n_roms * 4);
     for (auto& P : c->pipes) {
         dev_free(c, P.d_stepw, (size_t)c->stepw_words * 4);
         dev_free(c, P.d_tiles, (size_t)c->tiles_cap * sizeof(Tile));
         P.d_tiles = nullptr;
         P.d_stepw = nullptr; P.d_counts = nullptr; P.d_instr = nullptr; P.d_queue = nullptr;
     }
-    c->d_roms = nullptr; c->d_pre = nullptr; c->d_schemes = nullptr;
+    c->d_roms = nullptr; c->d_pre = nullptr; c->d_cmap = nullptr; c->d_pre_off = nullptr;
+    c->pre_words = 0;
     c->stepw_words = 0;
     c->tiles_cap = 0;
     ++c->generation;
@@ -527,10 +574,18 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     c->n_roms = n_roms;
     c->h_roms.assign((size_t)n_roms * kRomSlot, 0);
     c->h_schemes.assign(scheme, scheme + n_roms);
-    for (uint32_t r = 0; r < n_roms; ++r) std::memcpy(c->h_roms.data() + (size_t)r * kRomSlot, rom_host[r], rom_bytes[r]);
+    c->h_rinfo = info;
+    c->rom_lds = max_bytes > 8192 ? 32768u : 8192u;
+    for (uint32_t r = 0; r < n_roms; ++r) {
+        uint8_t* dst = c->h_roms.data() + (size_t)r * kRomSlot;
+        std::memcpy(dst, rom_host[r], rom_bytes[r]);
+        if (rom_bytes[r] == 2048) std::memcpy(dst + 2048, rom_host[r], 2048);   // a 2 KB ROM shows twice
+    }
     int rc = alloc_n(c, &c->d_roms, (size_t)n_roms * kRomSlot, "ROMs");
-    if (!rc) rc = alloc_n(c, &c->d_pre, (size_t)n_roms * kRomSlot, "predecoded ROMs");
-    if (!rc) rc = alloc_n(c, &c->d_schemes, n_roms, "ROM schemes");
+    if (!rc) rc = alloc_n(c, &c->d_pre, pre_words, "predecoded ROMs");
+    if (!rc) c->pre_words = pre_words;
+    if (!rc) rc = alloc_n(c, &c->d_cmap, n_roms, "ROM mappings");
+    if (!rc) rc = alloc_n(c, &c->d_pre_off, n_roms, "ROM mappings");
     const uint32_t instr_off = (3 * n_roms + 1) & ~1u;   // 8-byte aligned counters
     c->stepw_words = instr_off + 5;
     c->instr_off = instr_off;
@@ -545,8 +600,16 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     if (rc) return rc;
     for (auto& P : c->pipes) HIP_OK(hipMemset(P.d_stepw, 0, (size_t)c->stepw_words * 4));
     HIP_OK(hipMemcpy(c->d_roms, c->h_roms.data(), c->h_roms.size(), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(c->d_schemes, c->h_schemes.data(), n_roms * 4, hipMemcpyHostToDevice));
-    launch_predecode(c->d_roms, n_roms, c->d_pre, nullptr);
+    std::vector<CartMap> cmap(n_roms);
+    std::vector<uint32_t> pre_off(n_roms);
+    for (uint32_t r = 0; r < n_roms; ++r) {
+        cmap[r] = pack_cart(c->h_rinfo[r]);
+        pre_off[r] = c->h_rinfo[r].pre_off;
+    }
+    HIP_OK(hipMemcpy(c->d_cmap, cmap.data(), n_roms * sizeof(CartMap), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->d_pre_off, pre_off.data(), n_roms * 4, hipMemcpyHostToDevice));
+    for (uint32_t r = 0; r < n_roms; ++r)
+        launch_predecode(c->d_roms + (size_t)r * kRomSlot, c->h_rinfo[r], c->d_pre + c->h_rinfo[r].pre_off, nullptr);
     HIP_OK(hipGetLastError());
     HIP_OK(hipDeviceSynchronize());
     return VCS_OK;
@@ -629,7 +692,8 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     ia.n_tiles = d_cnt;
     ia.envs = c->d_cache_state;
     ia.roms = c->d_roms;
-    ia.schemes = c->d_schemes;
+    ia.cmap = c->d_cmap;
+    ia.pre_off = c->d_pre_off;
     ia.pre = c->d_pre;
     ia.actions = nullptr;
     ia.nframes_per_out = d_nfr;
@@ -647,7 +711,7 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     ia.done = nullptr;
     ia.err_word = c->d_err;
     ia.instr_total = nullptr;
-    launch_interp(ia, n_ct, kLanes, nullptr);
+    launch_interp(ia, n_ct, kLanes, c->rom_lds, nullptr);
     RenderArgs ra{};
     ra.logs = d_clog;
     ra.n_slots = 2;
@@ -773,8 +837,8 @@ int vcs_set_state(vcs_ctx* c, uint32_t env, const uint8_t* in) {
     if (from_record(in, &e)) return fail(VCS_E_INVAL, "bad timer fields in state record");
     if (e.rom_id >= c->n_roms) return fail(VCS_E_INVAL, "state names an unknown ROM");
     if (e.rom_id != c->h_env_rom[env]) return fail(VCS_E_INVAL, "state's ROM differs from the env's ROM");
-    if (c->h_schemes[e.rom_id] == VCS_BANK_4K && e.bank != 0) return fail(VCS_E_INVAL, "bank must be 0 for a 4K ROM");
-    if (e.bank > 1) return fail(VCS_E_INVAL, "bank must be 0 or 1");
+    const uint32_t bank = e.bank | ((uint32_t)e.bank_hi << 8);
+    if (bank >= c->h_rinfo[e.rom_id].n_vbanks) return fail(VCS_E_INVAL, "bank state out of range for the ROM's scheme");
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemcpy(c->d_envs + env, &e, sizeof(DevEnv), hipMemcpyHostToDevice));

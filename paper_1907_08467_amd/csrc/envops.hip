@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(64) k_reset(ResetArgs A) {
     __syncthreads();   // every thread has read the env's bookkeeping before it is overwritten
     const uint4* s4 = reinterpret_cast<const uint4*>(src);
     uint4* d4 = reinterpret_cast<uint4*>(dst);
-    if (threadIdx.x < 16) {
+    if (threadIdx.x < sizeof(DevEnv) / 16) {
         uint4 q = s4[threadIdx.x];
         if (threadIdx.x == 12) {          // bytes 192..207: rom_id, step_idx, episode_idx
             q.x = rom;

@@ -38,7 +38,9 @@ enum Mn : int {
     ADC, AND, ASL, BCC, BCS, BEQ, BIT, BMI, BNE, BPL, BRK, BVC, BVS, CLC, CLD, CLI, CLV, CMP,
     CPX, CPY, DEC, DEX, DEY, EOR, INC, INX, INY, JMP, JSR, LDA, LDX, LDY, LSR, NOP, ORA, PHA,
     PHP, PLA, PLP, ROL, ROR, RTI, RTS, SBC, SEC, SED, SEI, STA, STX, STY, TAX, TAY, TSX, TXA,
-    TXS, TYA, ILL
+    TXS, TYA,
+    SLO, RLA, SRE, RRA, SAX, LAX, DCP, ISC, ANC, ALR, ARR, SBX, LAS,   // undocumented, stable
+    ILL
 };
 enum Md : int { IMP, ACC, IMM, ZP, ZPX, ZPY, ABS, ABX, ABY, IZX, IZY, IND, REL };
 
@@ -47,8 +49,8 @@ struct OpInfo {
     bool pen;   // +1 cycle on an indexed page cross
 };
 
-// Decode from the opcode's aaabbbcc structure (documented opcodes only).
-constexpr OpInfo decode(int op) {
+// Decode of the documented opcodes from their aaabbbcc structure.
+constexpr OpInfo decode_doc(int op) {
     const int a = op >> 5, b = (op >> 2) & 7, cc = op & 3;
     OpInfo ill{ILL, IMP, 2, false};
     if (cc == 1) {
@@ -129,6 +131,61 @@ constexpr OpInfo decode(int op) {
     return ill;
 }
 
+// Decode of every opcode: the documented ones, then the stable undocumented
+// ones (NMOS unintended-opcode matrix); JAMs and the unstable ANE, LXA, SHA,
+// SHX, SHY, TAS stay ILL.
+constexpr OpInfo decode(int op) {
+    const OpInfo d = decode_doc(op);
+    if (d.mn != ILL) return d;
+    const int a = op >> 5, b = (op >> 2) & 7, cc = op & 3;
+    OpInfo ill{ILL, IMP, 2, false};
+    if (cc == 3) {
+        const int combo[8] = {SLO, RLA, SRE, RRA, SAX, LAX, DCP, ISC};
+        const int mn = combo[a];
+        if (b == 2) {                               // immediate column
+            const int imm[8] = {ANC, ANC, ALR, ARR, ILL, ILL, SBX, SBC};
+            return imm[a] == ILL ? ill : OpInfo{imm[a], IMM, 2, false};
+        }
+        if (mn == SAX) {
+            switch (b) {
+            case 0: return OpInfo{SAX, IZX, 6, false};
+            case 1: return OpInfo{SAX, ZP, 3, false};
+            case 3: return OpInfo{SAX, ABS, 4, false};
+            case 5: return OpInfo{SAX, ZPY, 4, false};
+            default: return ill;                    // SHA, TAS, SHA: unstable
+            }
+        }
+        if (mn == LAX) {
+            switch (b) {
+            case 0: return OpInfo{LAX, IZX, 6, false};
+            case 1: return OpInfo{LAX, ZP, 3, false};
+            case 3: return OpInfo{LAX, ABS, 4, false};
+            case 4: return OpInfo{LAX, IZY, 5, true};
+            case 5: return OpInfo{LAX, ZPY, 4, false};
+            case 6: return OpInfo{LAS, ABY, 4, true};
+            default: return OpInfo{LAX, ABY, 4, true};
+            }
+        }
+        const int mds[8] = {IZX, ZP, IMM, ABS, IZY, ZPX, ABY, ABX};
+        const int cyc[8] = {8, 5, 2, 6, 8, 6, 7, 7};
+        return OpInfo{mn, mds[b], cyc[b], false};
+    }
+    // NOPs of every width; the rest of the undocumented cc = 0, 1, 2 opcodes
+    // are JAMs or unstable
+    if (b == 0 && (op == 0x80 || op == 0x82 || op == 0xC2 || op == 0xE2)) return OpInfo{NOP, IMM, 2, false};
+    if (op == 0x89) return OpInfo{NOP, IMM, 2, false};
+    if (cc == 0 && b == 1 && (a == 0 || a == 2 || a == 3)) return OpInfo{NOP, ZP, 3, false};
+    if (op == 0x0C) return OpInfo{NOP, ABS, 4, false};
+    if (cc == 0 && b == 5 && a != 4 && a != 5) return OpInfo{NOP, ZPX, 4, false};
+    if (cc == 0 && b == 7 && a != 4 && a != 5) return OpInfo{NOP, ABX, 4, true};
+    if (cc == 2 && b == 6 && a != 4 && a != 5) return OpInfo{NOP, IMP, 2, false};
+    return ill;
+}
+
+constexpr bool combo_mn(int mn) {
+    return mn == SLO || mn == RLA || mn == SRE || mn == RRA || mn == DCP || mn == ISC;
+}
+
 constexpr int op_len(int md) {
     return (md == IMP || md == ACC) ? 1 : (md == ABS || md == ABX || md == ABY || md == IND) ? 3 : 2;
 }
@@ -153,8 +210,19 @@ struct Wave {                 // per-workgroup (uniform) data
     uint8_t* rom;             // LDS copy of the tile's cartridge
     uint8_t* ram;             // LDS, kRamStride bytes per lane
     uint8_t* tia;             // LDS, kTiaStride bytes per lane
-    uint32_t f8;              // 1 = F8 bank switching
+    const uint32_t* pre;      // the tile ROM's predecoded words
+    CartMap cm;               // its cartridge mapping
 };
+
+__device__ __forceinline__ uint32_t cm_kind(const Wave& W) { return W.cm.a & 3; }
+__device__ __forceinline__ uint32_t cm_sc(const Wave& W) { return (W.cm.a >> 2) & 1; }
+__device__ __forceinline__ uint32_t cm_tf_mask(const Wave& W) { return W.cm.b >> 16; }
+__device__ __forceinline__ uint32_t rom_off(const Wave& W, uint32_t bank, uint32_t a) {
+    return cart_rom_off(W.cm.a & 3, W.cm.b & 0xFFFF, bank, a);
+}
+__device__ __forceinline__ uint32_t hotspot(const Wave& W, uint32_t bank, uint32_t a) {
+    return cart_hotspot(W.cm.a & 3, W.cm.a >> 8, (W.cm.a >> 4) & 15, bank, a);
+}
 constexpr int kRamStride = 132;   // 33 dwords: bank-conflict free for equal offsets
 constexpr int kTiaStride = 20;    // 5 dwords
 
@@ -175,6 +243,7 @@ struct Cpu {
     uint32_t tqm;                  //   and the mask of used slots
     uint32_t ram_off, tia_off;
     uint8_t* log;             // current frame's row log, or nullptr
+    uint8_t* xram;            // the env's Superchip RAM (in its DevEnv)
     uint32_t slot, slots;     // its slot; slots completed so far
     int32_t open_row;
     uint32_t open_cnt;
@@ -206,30 +275,27 @@ __device__ __forceinline__ uint32_t riot_read(const Cpu& c, const Wave& W, uint3
     return (after & m) | (before & ~m);
 }
 
-__device__ __forceinline__ void cart_touch(Cpu& c, const Wave& W, uint32_t a) {
-    if (W.f8) {
-        const uint32_t lo = a & 0xFFF;
-        if (lo == 0xFF8) c.bank = 0;
-        else if (lo == 0xFF9) c.bank = 1;
-    }
-}
+// Superchip RAM window: cartridge offsets $000-$0FF (write port below $080)
+__device__ __forceinline__ bool sc_window(const Wave& W, uint32_t a) { return cm_sc(W) && !(a & 0xF00); }
 
-// data read at cycle t (side effects: F8 hotspots)
+// data read at cycle t (side effects: bank hotspots)
 __device__ __forceinline__ uint32_t rd(Cpu& c, const Wave& W, uint32_t addr, uint32_t t) {
     const uint32_t a = addr & 0x1FFF;
     if (a & 0x1000) {
-        cart_touch(c, W, a);
-        return W.rom[(c.bank << 12) | (a & 0xFFF)];
+        c.bank = hotspot(W, c.bank, a);
+        if (sc_window(W, a)) return (a & 0x80) ? (uint32_t)c.xram[a & 0x7F] : 0u;   // the write port reads 0
+        return W.rom[rom_off(W, c.bank, a)];
     }
     if (!(a & 0x80)) return tia_read(c, a);
     if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
     return riot_read(c, W, a, t);
 }
 
-// read without side effects (instruction fetch, zero-page pointers)
+// read without side effects (instruction fetch, zero-page pointers); the
+// cartridge area shows ROM even in the Superchip RAM window
 __device__ __forceinline__ uint32_t peek(const Cpu& c, const Wave& W, uint32_t addr, uint32_t t) {
     const uint32_t a = addr & 0x1FFF;
-    if (a & 0x1000) return W.rom[(c.bank << 12) | (a & 0xFFF)];
+    if (a & 0x1000) return W.rom[rom_off(W, c.bank, a)];
     if (!(a & 0x80)) return tia_read(c, a);
     if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
     return riot_read(c, W, a, t);
@@ -244,8 +310,10 @@ template <int K>
 __device__ __forceinline__ void wr(Cpu& c, const Wave& W, uint32_t addr, uint32_t v, uint32_t t) {
     const uint32_t a = addr & 0x1FFF;
     if (a & 0x1000) {
-        cart_touch(c, W, a);
+        c.bank = hotspot(W, c.bank, a);
+        if (sc_window(W, a) && !(a & 0x80)) c.xram[a & 0x7F] = (uint8_t)v;   // writes to the read port do nothing
     } else if (!(a & 0x80)) {
+        if (cm_kind(W) == CART_3F && a <= 0x3F) c.bank = v & cm_tf_mask(W);   // 3F: selects the lower slice
         if (K == 0) { c.tqr0 = a & 0x3F; c.tqv0 = v & 0xFF; }
         if (K == 1) { c.tqr1 = a & 0x3F; c.tqv1 = v & 0xFF; }
         if (K == 2) { c.tqr2 = a & 0x3F; c.tqv2 = v & 0xFF; }
@@ -315,18 +383,44 @@ __device__ __forceinline__ void do_cmp(Cpu& c, uint32_t r, uint32_t v) {
     c.p = nz(c.p, (r - v) & 0xFF);
 }
 
-// Decode word of an opcode: mode | mnemonic << 4 | base cycles << 10 |
-// page penalty << 13 | length << 14 | reads operand << 16 | writes to ea << 17.
+// ARR: (A AND operand) rotated right through C.  Binary: N, Z of the result,
+// C = bit 6, V = bit 6 ^ bit 5.  Decimal (NMOS): N = the old C, Z and V from
+// the rotate (V: bit 6 changed), then BCD fix-ups of each nibble decided on
+// the unrotated value, the high one also giving C.
+__device__ __forceinline__ void do_arr(Cpu& c, uint32_t v) {
+    const uint32_t t = c.a & v;
+    const uint32_t cin = c.p & FC;
+    uint32_t r = (t >> 1) | (cin << 7);
+    if (!(c.p & FD)) {
+        c.p = nz(c.p & ~(FC | FV), r) | ((r >> 6) & 1) | ((((r >> 6) ^ (r >> 5)) & 1) ? FV : 0);
+        c.a = r;
+        return;
+    }
+    uint32_t p = c.p & ~(FN | FZ | FV | FC);
+    p |= (cin ? FN : 0) | (r == 0 ? FZ : 0) | (((t ^ r) & 0x40) ? FV : 0);
+    if ((t & 0x0F) + (t & 0x01) > 5) r = (r & 0xF0) | ((r + 6) & 0x0F);
+    if ((t & 0xF0) + (t & 0x10) > 0x50) {
+        r = (r + 0x60) & 0xFF;
+        p |= FC;
+    }
+    c.p = p;
+    c.a = r;
+}
+
+// Decode word of an opcode: mode | mnemonic << 4 | base cycles << 11 |
+// page penalty << 15 | length << 16 | reads operand << 18 | writes to ea << 19.
+constexpr uint32_t DW_CYC = 11, DW_PEN = 15, DW_LEN = 16, DW_RD = 18, DW_WR = 19;
 constexpr uint32_t encode(int op) {
     const OpInfo I = decode(op);
-    const bool rmw = I.mn == ASL || I.mn == LSR || I.mn == ROL || I.mn == ROR || I.mn == INC || I.mn == DEC;
+    const bool rmw = I.mn == ASL || I.mn == LSR || I.mn == ROL || I.mn == ROR || I.mn == INC || I.mn == DEC ||
+                     combo_mn(I.mn);
     const bool mem = I.md != IMP && I.md != ACC && I.md != REL && I.md != IMM;
     const bool reads = (I.mn == LDA || I.mn == LDX || I.mn == LDY || I.mn == ADC || I.mn == SBC || I.mn == AND ||
                         I.mn == ORA || I.mn == EOR || I.mn == CMP || I.mn == CPX || I.mn == CPY || I.mn == BIT ||
-                        rmw) && mem;
-    const bool writes = (I.mn == STA || I.mn == STX || I.mn == STY || rmw) && mem;
-    return (uint32_t)I.md | ((uint32_t)I.mn << 4) | ((uint32_t)I.cyc << 10) | ((uint32_t)I.pen << 13) |
-           ((uint32_t)op_len(I.md) << 14) | ((uint32_t)reads << 16) | ((uint32_t)writes << 17);
+                        I.mn == LAX || I.mn == LAS || I.mn == NOP || rmw) && mem;
+    const bool writes = (I.mn == STA || I.mn == STX || I.mn == STY || I.mn == SAX || rmw) && mem;
+    return (uint32_t)I.md | ((uint32_t)I.mn << 4) | ((uint32_t)I.cyc << DW_CYC) | ((uint32_t)I.pen << DW_PEN) |
+           ((uint32_t)op_len(I.md) << DW_LEN) | ((uint32_t)reads << DW_RD) | ((uint32_t)writes << DW_WR);
 }
 struct DecodeTable {
     uint32_t w[256];
@@ -340,8 +434,8 @@ __constant__ DecodeTable kDecode = DecodeTable();
 // that fetched it.  Sets c.ac, c.pc, c.cyc (before a WSYNC stall) and queues
 // TIA writes.
 __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, uint32_t b1, uint32_t b2) {
-    const uint32_t md = d & 15, mn = (d >> 4) & 63;
-    uint32_t n = (d >> 10) & 7;
+    const uint32_t md = d & 15, mn = (d >> 4) & 127;
+    uint32_t n = (d >> DW_CYC) & 15;
     if (mn == ILL) {
         c.err |= ERR_ILLEGAL;
         return;
@@ -355,7 +449,7 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
     case ABX: case ABY: {
         const uint32_t base = b1 | (b2 << 8);
         ea = (base + (md == ABX ? c.x : c.y)) & 0xFFFF;
-        if ((d >> 13) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
+        if ((d >> DW_PEN) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
         break;
     }
     case IZX: {
@@ -366,12 +460,12 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
     case IZY: {
         const uint32_t base = zp_peek(c, W, b1) | (zp_peek(c, W, (b1 + 1) & 0xFF) << 8);
         ea = (base + c.y) & 0xFFFF;
-        if ((d >> 13) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
+        if ((d >> DW_PEN) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
         break;
     }
     default: break;
     }
-    const uint32_t next = (c.pc + ((d >> 14) & 3)) & 0xFFFF;
+    const uint32_t next = (c.pc + ((d >> DW_LEN) & 3)) & 0xFFFF;
     uint32_t npc = next;
     if (md == REL) {
         bool taken;
@@ -394,7 +488,7 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
     const uint32_t t = c.cyc + n - 1;     // access cycle
     c.ac = t;
     uint32_t v = b1;                      // operand (immediate, or read below)
-    if ((d >> 16) & 1) v = rd(c, W, ea, t);
+    if ((d >> DW_RD) & 1) v = rd(c, W, ea, t);
     uint32_t res = 0;                     // value written to ea when (d >> 17) & 1
     switch (mn) {
     case LDA: c.a = v; c.p = nz(c.p, v); break;
@@ -427,6 +521,33 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
         res = r;
         break;
     }
+    case SLO: case RLA: case SRE: case RRA: case DCP: case ISC: {
+        // the shift / rotate / count half; the ALU half follows the write
+        const uint32_t ci = c.p & FC;
+        uint32_t r, co = ci;
+        if (mn == SLO) { r = (v << 1) & 0xFF; co = v >> 7; }
+        else if (mn == RLA) { r = ((v << 1) | ci) & 0xFF; co = v >> 7; }
+        else if (mn == SRE) { r = v >> 1; co = v & 1; }
+        else if (mn == RRA) { r = (v >> 1) | (ci << 7); co = v & 1; }
+        else if (mn == DCP) { r = (v - 1) & 0xFF; }
+        else { r = (v + 1) & 0xFF; }
+        c.p = (c.p & ~FC) | co;
+        res = r;
+        break;
+    }
+    case SAX: res = c.a & c.x; break;
+    case LAX: c.a = c.x = v; c.p = nz(c.p, v); break;
+    case LAS: c.sp &= v; c.a = c.x = c.sp; c.p = nz(c.p, c.a); break;
+    case ANC: c.a &= v; c.p = nz(c.p, c.a); c.p = (c.p & ~FC) | (c.a >> 7); break;
+    case ALR: c.a &= v; c.p = (c.p & ~FC) | (c.a & 1); c.a >>= 1; c.p = nz(c.p, c.a); break;
+    case SBX: {
+        const uint32_t t0 = c.a & c.x;
+        c.p = (c.p & ~FC) | (t0 >= v ? FC : 0);
+        c.x = (t0 - v) & 0xFF;
+        c.p = nz(c.p, c.x);
+        break;
+    }
+    case ARR: do_arr(c, v); break;
     case INX: c.x = (c.x + 1) & 0xFF; c.p = nz(c.p, c.x); break;
     case INY: c.y = (c.y + 1) & 0xFF; c.p = nz(c.p, c.y); break;
     case DEX: c.x = (c.x - 1) & 0xFF; c.p = nz(c.p, c.x); break;
@@ -490,7 +611,13 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
     }
     default: break;                       // NOP, branches
     }
-    if ((d >> 17) & 1) wr<0>(c, W, ea, res, t);
+    if ((d >> DW_WR) & 1) wr<0>(c, W, ea, res, t);
+    if (mn == RRA) do_adc(c, res);        // the ALU half of the undocumented pairs,
+    else if (mn == ISC) do_sbc(c, res);   // after the write of their shifted /
+    else if (mn == DCP) do_cmp(c, c.a, res);   // counted operand
+    else if (mn == SLO) { c.a |= res; c.p = nz(c.p, c.a); }
+    else if (mn == RLA) { c.a &= res; c.p = nz(c.p, c.a); }
+    else if (mn == SRE) { c.a ^= res; c.p = nz(c.p, c.a); }
     c.pc = npc;
     c.cyc = t + 1;
 }
@@ -720,11 +847,8 @@ __device__ __forceinline__ uint32_t fast_tia(Cpu& c, const Wave& W, Fast& F, uin
 // Read of scalar address a (13 bits) at scalar cycle t.
 __device__ __forceinline__ uint32_t fast_rd(Cpu& c, const Wave& W, Fast& F, uint32_t a, uint32_t t) {
     if (a & 0x1000) {
-        if (W.f8) {
-            if ((a & 0xFFF) == 0xFF8) F.bank = 0;
-            else if ((a & 0xFFF) == 0xFF9) F.bank = 1;
-        }
-        return W.rom[(F.bank << 12) | (a & 0xFFF)];
+        F.bank = hotspot(W, F.bank, a);
+        return W.rom[rom_off(W, F.bank, a)];
     }
     if (!(a & 0x80)) {
         const uint32_t r = a & 0x0F;
@@ -739,10 +863,7 @@ __device__ __forceinline__ uint32_t fast_rd(Cpu& c, const Wave& W, Fast& F, uint
 __device__ __forceinline__ uint32_t fast_wr(Cpu& c, const Wave& W, Fast& F, uint32_t a, uint32_t v, uint32_t t,
                                             uint32_t& wsync) {
     if (a & 0x1000) {
-        if (W.f8) {
-            if ((a & 0xFFF) == 0xFF8) F.bank = 0;
-            else if ((a & 0xFFF) == 0xFF9) F.bank = 1;
-        }
+        F.bank = hotspot(W, F.bank, a);
         return 1;
     }
     if (!(a & 0x80)) return fast_tia(c, W, F, a & 0x3F, v & 0xFF, t, wsync);
@@ -868,8 +989,9 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
     constexpr int MD = I.md, MN = I.mn;
     constexpr uint32_t N = (uint32_t)I.cyc;
     const uint32_t next = (F.pc + (uint32_t)op_len(MD)) & 0xFFFF;
-    if constexpr (MN == ILL || MN == BRK || MN == RTI || MD == IZX || MD == IZY || MD == IND) {
-        return FS_EXIT;
+    if constexpr (MN == ILL || MN == BRK || MN == RTI || MD == IZX || MD == IZY || MD == IND || MN >= SLO ||
+                  (MN == NOP && MD != IMP)) {
+        return FS_EXIT;   // left to the per-lane path (undocumented opcodes included)
     } else if constexpr (MD == IMM) {
         uint32_t dm = 0;
         if constexpr (MN == ADC || MN == SBC) {
@@ -953,6 +1075,9 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             F.cyc += N;
             return FS_NEXT;
         } else if constexpr (read_mn(MN)) {
+            if constexpr (MD == ABS) {
+                if (aux == SC_EXIT) return FS_EXIT;   // the Superchip RAM window
+            }
             uint32_t dm = 0;
             if constexpr (MN == ADC || MN == SBC) {
                 dm = dec_mode(c);
@@ -974,10 +1099,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             } else if (aux == SC_EXIT) {
                 return FS_EXIT;
             } else if (aux == SC_CART) {
-                if (W.f8) {
-                    if ((a & 0xFFF) == 0xFF8) F.bank = 0;
-                    else if ((a & 0xFFF) == 0xFF9) F.bank = 1;
-                }
+                F.bank = hotspot(W, F.bank, a);
             }
             F.pc = next;
             F.cyc += N;
@@ -988,6 +1110,9 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             // left to the per-lane path, as are the stores fast_store_ok refuses
             if (!(a & 0x1000) && !(a & 0x80)) return FS_EXIT;
             if (!fast_store_ok(a)) return FS_EXIT;
+            if constexpr (MD == ABS) {
+                if (aux == SC_EXIT) return FS_EXIT;   // the Superchip RAM window
+            }
             const uint32_t v = fast_rd(c, W, F, a, t);
             const uint32_t r = fast_rmw(c, MN, v);
             uint32_t wsync = 0;
@@ -1008,7 +1133,8 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
         const uint32_t a = ea & 0x1FFF;
         const bool in_ram = (a & 0x1280) == 0x0080;
         if constexpr (read_mn(MN)) {
-            const bool in_cart = (a & 0x1000) && (!W.f8 || ((a & 0xFFF) != 0xFF8 && (a & 0xFFF) != 0xFF9));
+            // cartridge addresses that are plain ROM: no hotspot, no Superchip RAM
+            const bool in_cart = (a & 0x1000) && hotspot(W, F.bank, a) == F.bank && !sc_window(W, a);
             if (!all_lanes(in_ram || in_cart)) return FS_EXIT;
         } else {
             if (!all_lanes(in_ram)) return FS_EXIT;
@@ -1026,7 +1152,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
                 if (dm == 2) return FS_EXIT;
             }
             // one LDS read from RAM or cartridge, whichever each lane's address is in
-            const uint8_t* src = in_ram ? W.ram + c.ram_off + (a & 0x7F) : W.rom + ((F.bank << 12) | (a & 0xFFF));
+            const uint8_t* src = in_ram ? W.ram + c.ram_off + (a & 0x7F) : W.rom + rom_off(W, F.bank, a);
             fast_alu(c, MN, *src, dm);
         } else if constexpr (store_mn(MN)) {
             W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)store_value<MN>(c);
@@ -1202,9 +1328,11 @@ __device__ __forceinline__ uint32_t take_tile(uint32_t* queue) {
 // LL = envs a tile may hold (64 or 32): RAM and TIA registers get LL + 1
 // slots in LDS (lanes at LL and above, always idle, share the last one), so
 // narrow tiles take less LDS and more waves fit on a compute unit.
-template <int LL>
+// RC = bytes of cartridge staged in LDS (8 KB, or 32 KB when a loaded ROM is
+// larger than 8 KB).
+template <int LL, int RC>
 __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t* __restrict__ pre_all) {
-    __shared__ uint32_t s_rom[kRomSlot / 4 + 4];
+    __shared__ uint32_t s_rom[RC / 4 + 4];
     __shared__ uint32_t s_ram[(LL + 1) * kRamStride / 4];
     __shared__ uint32_t s_tia[(LL + 1) * kTiaStride / 4];
 
@@ -1217,14 +1345,15 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
 
         // stage the cartridge in LDS
         const uint4* rsrc = reinterpret_cast<const uint4*>(A.roms + (size_t)rom_id * kRomSlot);
-        for (int i = lane; i < kRomSlot / 16; i += kLanes) reinterpret_cast<uint4*>(s_rom)[i] = rsrc[i];
-        if (lane < 4) s_rom[kRomSlot / 4 + lane] = 0;
+        for (int i = lane; i < RC / 16; i += kLanes) reinterpret_cast<uint4*>(s_rom)[i] = rsrc[i];
+        if (lane < 4) s_rom[RC / 4 + lane] = 0;
 
         Wave W;
         W.rom = reinterpret_cast<uint8_t*>(s_rom);
         W.ram = reinterpret_cast<uint8_t*>(s_ram);
         W.tia = reinterpret_cast<uint8_t*>(s_tia);
-        W.f8 = A.schemes[rom_id];
+        W.cm = A.cmap[rom_id];
+        W.pre = pre_all + A.pre_off[rom_id];
 
         const int env = lane < T.count ? T.env[lane] : -1;
         const int out = lane < T.count ? T.out[lane] : 0;
@@ -1247,7 +1376,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             const uint4 qt = reinterpret_cast<const uint4*>(E->tia)[0];
             uint32_t* dt = s_tia + (c.tia_off >> 2);
             dt[0] = qt.x; dt[1] = qt.y; dt[2] = qt.z; dt[3] = qt.w; dt[4] = 0;
-            c.a = E->a; c.x = E->x; c.y = E->y; c.sp = E->sp; c.p = E->p; c.bank = E->bank;
+            c.a = E->a; c.x = E->x; c.y = E->y; c.sp = E->sp; c.p = E->p;
+            c.bank = E->bank | ((uint32_t)E->bank_hi << 8);
+            c.xram = E->xram;
             c.vsync = E->vsync; c.hmp0 = E->hmp0; c.hmp1 = E->hmp1;
             c.tv = E->tv; c.tshift = E->tshift; c.tbase = E->tbase;
             c.pc = E->pc;
@@ -1325,7 +1456,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == tmin && c.fl == fl0 &&
                                   c.open_row == or0 && c.open_cnt == oc0 && (c.log != nullptr ? 1u : 0u) == lg0;
                 const uint32_t partial = __builtin_amdgcn_ballot_w64(!same) != 0 ? 1u : 0u;
-                if (same) uni = run_fast(c, W, pre_all + (size_t)rom_id * kRomSlot, ended, end_t, partial);
+                if (same) uni = run_fast(c, W, W.pre, ended, end_t, partial);
             }
             const bool ran_uniform = __any(uni);
             const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;
@@ -1338,9 +1469,14 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                     const uint32_t pc = c.pc;
                     const uint32_t off = pc & 0xFFF;
                     if ((pc & 0x1000) && off <= 0xFFD) {
-                        const uint32_t boff = (c.bank << 12) | off;
-                        const uint32_t w0 = s_rom[boff >> 2], w1 = s_rom[(boff >> 2) + 1];
-                        const uint32_t v = __builtin_amdgcn_alignbyte(w1, w0, boff & 3);
+                        uint32_t v;
+                        if (cm_kind(W) == CART_LINEAR) {   // the 4 KB bank is contiguous in LDS
+                            const uint32_t boff = (c.bank << 12) | off;
+                            const uint32_t w0 = s_rom[boff >> 2], w1 = s_rom[(boff >> 2) + 1];
+                            v = __builtin_amdgcn_alignbyte(w1, w0, boff & 3);
+                        } else {                          // segments: the predecoded word
+                            v = W.pre[(c.bank << 12) | off];
+                        }
                         op = v & 0xFF;
                         b1 = (v >> 8) & 0xFF;
                         b2 = (v >> 16) & 0xFF;
@@ -1418,7 +1554,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             for (int i = 0; i < 8; ++i) dst[i] = make_uint4(sr[4 * i], sr[4 * i + 1], sr[4 * i + 2], sr[4 * i + 3]);
             const uint32_t* st = s_tia + (c.tia_off >> 2);
             reinterpret_cast<uint4*>(E->tia)[0] = make_uint4(st[0], st[1], st[2], st[3]);
-            E->a = c.a; E->x = c.x; E->y = c.y; E->sp = c.sp; E->p = c.p; E->bank = c.bank;
+            E->a = c.a; E->x = c.x; E->y = c.y; E->sp = c.sp; E->p = c.p;
+            E->bank = (uint8_t)c.bank;
+            E->bank_hi = (uint8_t)(c.bank >> 8);
             E->vsync = c.vsync; E->hmp0 = c.hmp0; E->hmp1 = c.hmp1;
             E->tv = c.tv; E->tshift = c.tshift; E->tbase = c.tbase;
             E->pc = c.pc;
@@ -1454,33 +1592,51 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
     }
 }
 
-// Predecoded ROM: for every bank offset, opcode | b1 << 8 | b2 << 16 |
-// aux << 24 for the instruction that starts there, aux being the store class
-// of the address of a zero-page or absolute STA/STX/STY (0 otherwise).
-// Entries past offset $FFD are never used.
-__global__ void k_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre) {
+// Predecoded ROM: for every virtual bank and offset, opcode | b1 << 8 |
+// b2 << 16 | aux << 24 for the instruction that starts there (each byte read
+// through the bank's mapping, so instructions that cross an E0 or 3F segment
+// boundary decode exactly).  aux is the store class of the address of a
+// zero-page or absolute STA/STX/STY; SC_EXIT also marks stores to $00-$3F on
+// 3F cartridges (they switch banks) and absolute accesses to a Superchip RAM
+// window, which the per-lane path takes.  Entries past offset $FFD are never
+// used.
+__global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_roms * (uint32_t)kRomSlot) return;
-    const uint32_t r = i / kRomSlot, o = i % kRomSlot, bank = o >> 12, off = o & 0xFFF;
-    const uint8_t* rom = roms + (size_t)r * kRomSlot + (bank << 12);
-    const uint32_t op = rom[off];
-    const uint32_t b1 = off + 1 < 4096 ? rom[off + 1] : 0, b2 = off + 2 < 4096 ? rom[off + 2] : 0;
+    if (i >= R.n_vbanks * 4096u) return;
+    const uint32_t bank = i >> 12, off = i & 0xFFF;
+    const uint32_t op = rom[cart_rom_off(R, bank, 0x1000 | off)];
+    const uint32_t b1 = off + 1 < 4096 ? rom[cart_rom_off(R, bank, 0x1000 | (off + 1))] : 0;
+    const uint32_t b2 = off + 2 < 4096 ? rom[cart_rom_off(R, bank, 0x1000 | (off + 2))] : 0;
+    const uint32_t d = kDecode.w[op];
+    const uint32_t md = d & 15, abs_addr = (b1 | (b2 << 8)) & 0x1FFF;
     uint32_t aux = 0;
-    if (op == 0x84 || op == 0x85 || op == 0x86) aux = store_class(b1);
-    else if (op == 0x8C || op == 0x8D || op == 0x8E) aux = store_class((b1 | (b2 << 8)) & 0x1FFF);
+    const bool st = op == 0x84 || op == 0x85 || op == 0x86 || op == 0x8C || op == 0x8D || op == 0x8E;
+    const uint32_t a = (op == 0x84 || op == 0x85 || op == 0x86) ? b1 : abs_addr;
+    if (st) {
+        aux = store_class(a);
+        if (R.kind == CART_3F && a <= 0x3F) aux = SC_EXIT;
+    }
+    if (R.sc && md == ABS && ((d >> DW_RD) & 1 || (d >> DW_WR) & 1) && (abs_addr & 0x1000) && !(abs_addr & 0xF00))
+        aux = SC_EXIT;
     pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24);
 }
 
-void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre, hipStream_t s) {
-    const uint32_t n = n_roms * (uint32_t)kRomSlot;
-    hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, roms, n_roms, pre);
+void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, hipStream_t s) {
+    const uint32_t n = info.n_vbanks * 4096u;
+    hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, rom, info, pre);
 }
 
-void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, hipStream_t s) {
-    if (tile_envs <= 32)
-        hipLaunchKernelGGL(k_interp<32>, dim3(grid), dim3(kLanes), 0, s, a, a.pre);
-    else
-        hipLaunchKernelGGL(k_interp<64>, dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s) {
+    if (rom_lds > 8192) {
+        if (tile_envs <= 32)
+            hipLaunchKernelGGL((k_interp<32, 32768>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+        else
+            hipLaunchKernelGGL((k_interp<64, 32768>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+    } else if (tile_envs <= 32) {
+        hipLaunchKernelGGL((k_interp<32, 8192>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+    } else {
+        hipLaunchKernelGGL((k_interp<64, 8192>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+    }
 }
 
 }  // namespace vcs

@@ -1,6 +1,6 @@
 // Device-side layouts shared by the vcs355 kernels and the host library.
 //
-// Env state lives in HBM as one 256-byte record per env (DevEnv).  A step
+// Env state lives in HBM as one 384-byte record per env (DevEnv).  A step
 // loads a tile of 64 envs into one wave: RAM into LDS, CPU registers into
 // VGPRs.  The interpreter writes, for each frame it renders, a row log: per
 // scanline row a 16-byte snapshot of the render registers at the row's first
@@ -25,7 +25,7 @@ constexpr int kFrameBytes = kRows * kCols;
 constexpr int kRowEntries = 24;        // max register writes inside one row's visible part
 constexpr int kRowBytes = 16 + 4 * kRowEntries;   // snapshot + entries = 112
 constexpr int kFrameLogBytes = kRows * kRowBytes; // 23,520
-constexpr int kRomSlot = 8192;         // bytes per ROM slot (4 KB ROMs use the first half)
+constexpr int kRomSlot = 32768;        // bytes per ROM slot (smaller ROMs use its start)
 
 // render register order inside a snapshot (TIA $06..$0F map to 0..9)
 enum : int {
@@ -42,9 +42,9 @@ struct alignas(16) DevEnv {
     uint8_t ram[128];        //   0  RAM $80..$FF
     uint8_t tia[16];         // 128  render registers (snapshot order); [15] = 0
     uint8_t a, x, y, sp;     // 144
-    uint8_t p, bank, vsync, hmp0;              // 148
+    uint8_t p, bank, vsync, hmp0;              // 148  bank: bank state bits 0-7
     uint8_t hmp1, tv, tshift, prev_action;     // 152  timer value / log2 interval
-    uint8_t err, pad0;                         // 156
+    uint8_t err, bank_hi;                      // 156  bank state bits 8-15
     uint16_t pc;                               // 158
     uint64_t cycle;          // 160  start cycle of the next instruction
     uint64_t frame_line0;    // 168  scanline of the write that began the frame
@@ -52,8 +52,65 @@ struct alignas(16) DevEnv {
     uint64_t instr;          // 184  instructions executed
     uint32_t rom_id, step_idx, episode_idx, pad1;   // 192
     uint8_t reserved[48];    // 208
+    uint8_t xram[128];       // 256  Superchip RAM
 };
-static_assert(sizeof(DevEnv) == 256, "DevEnv is 256 bytes");
+static_assert(sizeof(DevEnv) == 384, "DevEnv is 384 bytes");
+
+// Cartridge mapping of one ROM.  The bank state of an env (16 bits) is a
+// "virtual bank": the 4 KB bank of linear schemes (4K, F8, F6, F4 and their
+// Superchip forms), the three E0 segment slices s0 | s1 << 3 | s2 << 6, or the
+// 3F slice of the lower 2 KB.  The predecoded ROM holds 4096 words per
+// virtual bank, so the instruction at (bank, pc) is one load for every scheme.
+enum : uint32_t { CART_LINEAR = 0, CART_E0 = 1, CART_3F = 2 };
+struct RomInfo {
+    uint32_t kind;            // CART_*
+    uint32_t hs_first;        // linear: first hotspot offset ($FF8 / $FF6 / $FF4)
+    uint32_t hs_n;            // linear: number of banks when switched (0 = no hotspots)
+    uint32_t sc;              // 1: Superchip RAM at $1000-$10FF
+    uint32_t tf_last;         // 3F: ROM offset of the last 2 KB slice
+    uint32_t tf_mask;         // 3F: slices - 1 (a power of two minus one)
+    uint32_t n_vbanks;        // virtual banks (predecoded ROM = n_vbanks x 4096 words)
+    uint32_t pre_off;         // this ROM's first word in the predecoded table
+};
+
+// ROM offset shown at cartridge address a (A12 set) under bank state `bank`
+__host__ __device__ inline uint32_t cart_rom_off(uint32_t kind, uint32_t tf_last, uint32_t bank, uint32_t a) {
+    const uint32_t lo = a & 0xFFF;
+    if (kind == CART_LINEAR) return (bank << 12) | lo;
+    if (kind == CART_E0) {
+        const uint32_t seg = lo >> 10;
+        const uint32_t sl = seg == 3 ? 7u : (bank >> (3 * seg)) & 7u;
+        return (sl << 10) | (lo & 0x3FF);
+    }
+    return (lo < 0x800 ? (bank << 11) : tf_last) | (lo & 0x7FF);
+}
+__host__ __device__ inline uint32_t cart_rom_off(const RomInfo& R, uint32_t bank, uint32_t a) {
+    return cart_rom_off(R.kind, R.tf_last, bank, a);
+}
+
+// Bank state after a data access to cartridge address a (hotspots)
+__host__ __device__ inline uint32_t cart_hotspot(uint32_t kind, uint32_t hs_first, uint32_t hs_n, uint32_t bank,
+                                                 uint32_t a) {
+    const uint32_t lo = a & 0xFFF;
+    if (kind == CART_LINEAR) {
+        const uint32_t d = lo - hs_first;
+        return d < hs_n ? d : bank;
+    }
+    if (kind == CART_E0 && lo - 0xFE0u < 24u) {
+        const uint32_t sh = 3 * ((lo - 0xFE0) >> 3);
+        return (bank & ~(7u << sh)) | ((lo & 7u) << sh);
+    }
+    return bank;
+}
+
+// The mapping packed into two words for the interpreter's scalar registers:
+// a = kind | sc << 2 | hs_n << 4 | hs_first << 8, b = tf_last | tf_mask << 16
+struct CartMap {
+    uint32_t a, b;
+};
+__host__ __device__ inline CartMap pack_cart(const RomInfo& R) {
+    return CartMap{R.kind | (R.sc << 2) | (R.hs_n << 4) | (R.hs_first << 8), R.tf_last | (R.tf_mask << 16)};
+}
 
 struct Tile {                 // up to 64 envs of one ROM, one per lane
     int32_t rom;
@@ -74,8 +131,9 @@ struct InterpArgs {
     const uint32_t* n_tiles;  // device count of valid tiles (grid may be larger)
     DevEnv* envs;
     const uint8_t* roms;      // [n_roms][kRomSlot]
-    const uint32_t* schemes;  // [n_roms]
-    const uint32_t* pre;      // [n_roms][kRomSlot] predecoded ROM
+    const CartMap* cmap;      // [n_roms]
+    const uint32_t* pre_off;  // [n_roms]: each ROM's first predecoded word
+    const uint32_t* pre;      // predecoded ROMs (RomInfo::pre_off, n_vbanks)
     const uint8_t* actions;   // [n outputs]; NULL = NOOP
     const uint16_t* nframes_per_out;  // [n outputs] or NULL
     uint32_t nframes;         // frames per step when nframes_per_out is NULL
@@ -137,8 +195,9 @@ struct ResetArgs {
 };
 
 // host launchers (one per kernel)
-void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, hipStream_t s);  // tile_envs: widest tile
-void launch_predecode(const uint8_t* roms, uint32_t n_roms, uint32_t* pre, hipStream_t s);
+// tile_envs: widest tile; rom_lds: bytes of ROM staged in LDS (8192 or 32768)
+void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s);
+void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, hipStream_t s);
 void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s);
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s);
 void launch_reset(const ResetArgs& a, hipStream_t s);

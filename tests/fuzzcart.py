@@ -1,13 +1,28 @@
 """Random cartridges for differential testing of the GPU interpreter against
 the oracle.  Every documented opcode appears with every addressing mode, on
 RAM, TIA, RIOT (ports and timer) and cartridge operands, in decimal and
-binary mode, with forward branches, subroutines, BRK/RTI and page crossings.
-Control flow stays structured so that frames keep ending (VSYNC) and the
-cartridge never executes an undocumented opcode.
+binary mode, with forward branches, subroutines, BRK/RTI and page crossings;
+optionally the stable undocumented opcodes too.  Control flow stays
+structured so that frames keep ending (VSYNC) and the cartridge never
+executes a JAM or an unstable opcode.
+
+Cartridge schemes: linear ones (4K, F8, F6, F4 and their Superchip forms)
+carry the same code in every bank so a switch continues in place, with
+different data per bank, and the data accesses hit the hotspots and the
+Superchip RAM ports; E0 and 3F keep the code in the fixed segment and read
+data from the switched ones, switch them at random, and call a routine that
+straddles the last switched segment and the fixed one.
 """
 import numpy as np
 
-from paper_1907_08467_amd.inputs.asm6502 import OPCODES, assemble_with_symbols
+from paper_1907_08467_amd.inputs.asm6502 import OPCODES, UNDOC_OPCODES, assemble_with_symbols
+
+S_4K, S_F8, S_F6, S_F4, S_F8SC, S_F6SC, S_F4SC, S_E0, S_3F = range(9)
+LINEAR_BANKS = {S_4K: 1, S_F8: 2, S_F6: 4, S_F4: 8, S_F8SC: 2, S_F6SC: 4, S_F4SC: 8}
+HOTSPOTS = {S_F8: range(0x1FF8, 0x1FFA), S_F6: range(0x1FF6, 0x1FFA), S_F4: range(0x1FF4, 0x1FFC),
+            S_F8SC: range(0x1FF8, 0x1FFA), S_F6SC: range(0x1FF6, 0x1FFA), S_F4SC: range(0x1FF4, 0x1FFC),
+            S_E0: range(0x1FE0, 0x1FF8)}
+UNDOC_RMW = ["slo", "rla", "sre", "rra", "dcp", "isc"]
 
 RAM = [a for a in range(0x80, 0xF8) if a not in (0xD0, 0xD1, 0xD4, 0xD5, 0xE0, 0xE1)]   # $F8-$FF: stack
 TIA_W = [0x01, 0x06, 0x07, 0x08, 0x09, 0x0A, 0x0B, 0x0C, 0x0D, 0x0E, 0x0F, 0x10, 0x11, 0x1B, 0x1C,
@@ -26,11 +41,21 @@ BRANCHES = ["bpl", "bmi", "bvc", "bvs", "bcc", "bcs", "bne", "beq"]
 
 
 class Gen:
-    def __init__(self, seed, f8=False):
+    def __init__(self, seed, scheme=S_4K, undoc=False):
         self.r = np.random.default_rng(seed)
-        self.f8 = f8
+        self.scheme = scheme
+        self.undoc = undoc
         self.n = 0
         self.lines = []
+        self.hot = list(HOTSPOTS.get(scheme, []))
+        self.sc = scheme in (S_F8SC, S_F6SC, S_F4SC)
+        if scheme == S_E0:
+            self.cart_r = list(range(0x1000, 0x1C00, 7))     # the switched segments
+        elif scheme == S_3F:
+            self.cart_r = list(range(0x1000, 0x1800, 5))
+        else:
+            self.cart_r = CART_R
+        self.n_slices = 4
 
     def pick(self, seq):
         return seq[int(self.r.integers(0, len(seq)))]
@@ -50,21 +75,25 @@ class Gen:
                 return self.pick(RAM)
             if x < 0.7:
                 return self.pick(TIA_R)
-            if x < 0.85:
+            if x < 0.8:
                 return self.pick(RIOT_R)
-            if self.f8 and x < 0.88:
-                return self.pick([0x1FF8, 0x1FF9])
-            return self.pick(CART_R)
-        if x < 0.6:
+            if self.hot and x < 0.84:
+                return self.pick(self.hot)
+            if self.sc and x < 0.9:
+                return 0x1000 + int(self.r.integers(0, 256))    # both Superchip ports
+            return self.pick(self.cart_r)
+        if x < 0.55:
             return self.pick(RAM)
-        if x < 0.85:
+        if x < 0.8:
             return self.pick(TIA_W)
-        if self.f8 and x < 0.9:
-            return self.pick([0x1FF8, 0x1FF9])
+        if self.hot and x < 0.86:
+            return self.pick(self.hot)
+        if self.sc and x < 0.93:
+            return 0x1000 + int(self.r.integers(0, 256))
         return self.pick(RIOT_W)
 
     def mem_op(self, mn, kind):
-        modes = [m for m in OPCODES[mn] if m not in ("imp", "acc", "rel")]
+        modes = [m for m in {**UNDOC_OPCODES.get(mn, {}), **OPCODES.get(mn, {})} if m not in ("imp", "acc", "rel")]
         mode = self.pick(modes)
         if mode == "imm":
             self.emit(f"{mn} #${int(self.r.integers(0, 256)):02X}")
@@ -95,7 +124,7 @@ class Gen:
             self.emit("sta $E0")
             self.emit(f"lda #${t >> 8:02X}")
             self.emit("sta $E1")
-            if mn in ("sta",):
+            if mn in ("sta", "sax"):
                 self.emit(f"lda #${int(self.r.integers(0, 256)):02X}")
             self.emit(f"ldx #${k:02X}")
             self.emit(f"{mn} (${(0xE0 - k) & 0xFF:02X},x)")
@@ -106,12 +135,31 @@ class Gen:
             self.emit("sta $E0")
             self.emit(f"lda #${base >> 8:02X}")
             self.emit("sta $E1")
-            if mn in ("sta",):
+            if mn in ("sta", "sax"):
                 self.emit(f"lda #${int(self.r.integers(0, 256)):02X}")
             self.emit(f"ldy #${k:02X}")
             self.emit(f"{mn} ($E0),y")
 
     def instr(self):
+        x = self.r.random()
+        if self.undoc and x < 0.2:
+            self.undoc_op()
+            return
+        if self.scheme == S_E0 and x > 0.985:
+            # a data slice into segment 2, then a call that straddles it and the fixed segment
+            self.emit(f"lda $1FF{int(self.r.integers(0, 7)):X}")
+            self.emit("jsr $1BFE")
+            return
+        if self.scheme == S_3F and x > 0.985:
+            v = int(self.r.integers(0, 256 // self.n_slices)) * self.n_slices + int(self.r.integers(0, self.n_slices - 1))
+            self.emit(f"lda #${v:02X}")         # any slice but the fixed one
+            self.emit("sta $3F")
+            self.emit("jsr $17FE")
+            return
+        if self.scheme == S_3F and x > 0.96:
+            self.emit(f"lda #${int(self.r.integers(0, 256)):02X}")
+            self.emit("sta $3F")                  # selects slice v mod S
+            return
         x = self.r.random()
         if x < 0.35:
             self.mem_op(self.pick(READ_MN), "r")
@@ -141,6 +189,34 @@ class Gen:
         else:
             self.emit("brk")
             self.emit(".byte $EA")
+
+    def undoc_op(self):
+        """One stable undocumented opcode (every mode, every encoding kind)."""
+        x = self.r.random()
+        imm = int(self.r.integers(0, 256))
+        if x < 0.4:
+            self.mem_op(self.pick(UNDOC_RMW), "w")
+        elif x < 0.5:
+            self.mem_op("sax", "w")
+        elif x < 0.62:
+            self.mem_op("lax", "r")
+        elif x < 0.76:
+            self.emit(self.pick([f"anc #${imm:02X}", f"alr #${imm:02X}", f"arr #${imm:02X}", f"sbx #${imm:02X}",
+                                 f".byte $2B, ${imm:02X}", f".byte $EB, ${imm:02X}"]))
+        elif x < 0.8:
+            k = int(self.r.integers(0, 256))
+            t = self.pick(RAM)
+            self.emit(f"ldy #${k:02X}")
+            self.emit(f"las ${(t - k) & 0xFFFF | 0x2000:04X},y")
+            self.emit("ldx #$FB")                 # keep the stack where the code expects it
+            self.emit("txs")
+        elif x < 0.9:
+            self.mem_op("nop", "r")               # the NOPs read their operand
+        else:
+            self.emit(self.pick([".byte $1A", ".byte $3A", ".byte $5A", ".byte $7A", ".byte $DA", ".byte $FA",
+                                 f".byte $82, ${imm:02X}", f".byte $89, ${imm:02X}", f".byte $C2, ${imm:02X}",
+                                 f".byte $E2, ${imm:02X}", f".byte $44, ${self.pick(RAM):02X}",
+                                 f".byte $D4, ${self.pick(RAM):02X}", f".byte $FC, $00, $1E"]))
 
     def simple(self):
         x = self.r.random()
@@ -179,22 +255,54 @@ class Gen:
         data = ["    .org $1E00"] + ["    .byte " + ", ".join(f"${int(v):02X}" for v in self.r.integers(0, 256, 16))
                                      for _ in range(16)]
         tail = ["    jmp frame"]
-        return "\n".join(head + frame + body + tail + subs + handler + data)
+        return "\n".join(head + frame + body + tail + subs + handler), "\n".join(data)
 
 
-def fuzz_cart(seed, f8=False, lines_per_frame=60):
-    g = Gen(seed, f8)
-    src = g.source(lines_per_frame)
-    if not f8:
-        rom, _ = assemble_with_symbols("    .org $1000\n" + src + "\n    .org $1FFA\n    .word reset, reset, brkh\n")
-        return rom, 0
-    # F8: the same code in both banks (so a switch continues in place), different data
-    g2 = Gen(seed + 1, f8)
+VECTORS = "\n    .org $1FFA\n    .word reset, reset, brkh\n"
+
+
+def _segmented(seed, scheme, undoc, lines_per_frame, size):
+    """E0 (8 KB) or 3F (`size`): code in the fixed segment, data slices."""
+    g = Gen(seed, scheme, undoc)
+    if scheme == S_E0:
+        n_sl, sl, fixed_at = 8, 1024, 0x1C00
+    else:
+        n_sl, sl, fixed_at = size // 2048, 2048, 0x1800
+    g.n_slices = n_sl
+    code, _ = g.source(lines_per_frame)
+    r = np.random.default_rng(seed + 7)
+    # fixed segment: byte 0 = $1E (the high byte of the straddling LDA), RTS, the
+    # code, then (3F only) a data block at $1E00
+    data = "" if scheme == S_E0 else "\n    .org $1E00\n" + "\n".join(
+        "    .byte " + ", ".join(f"${int(v):02X}" for v in r.integers(0, 256, 16)) for _ in range(16))
+    src = f"    .org ${fixed_at:04X}\n    .byte $1E\n    rts\n" + code + "\ncode_end:" + data + VECTORS
+    img, syms = assemble_with_symbols(src)
+    assert syms["code_end"] <= (0x1FE0 if scheme == S_E0 else 0x1E00), hex(syms["code_end"])
+    fixed = img[fixed_at - 0x1000:]
+    out = bytearray()
+    for s_ in range(n_sl - 1):
+        part = bytearray(r.integers(0, 256, sl).astype(np.uint8).tobytes())
+        part[-2:] = bytes([0xAD, int(r.integers(0, 256))])    # LDA $1Exx across the boundary
+        out += part
+    out += fixed
+    assert len(out) == n_sl * sl
+    return bytes(out), scheme
+
+
+def fuzz_cart(seed, f8=False, lines_per_frame=60, scheme=None, undoc=False, size=8192):
+    scheme = (S_F8 if f8 else S_4K) if scheme is None else scheme
+    if scheme in (S_E0, S_3F):
+        return _segmented(seed, scheme, undoc, min(lines_per_frame, 14 if scheme == S_E0 else 40), size)
+    nb = LINEAR_BANKS[scheme]
+    org = "$1100" if scheme in (S_F8SC, S_F6SC, S_F4SC) else "$1000"
+    g = Gen(seed, scheme, undoc)
+    code, data = g.source(lines_per_frame)
+    # the same code in every bank (so a switch continues in place), different data
+    g2 = Gen(seed + 1, scheme, undoc)
     images = []
-    for b in range(2):
-        data_src = src if b == 0 else src[:src.index("    .org $1E00")] + "\n".join(
-            ["    .org $1E00"] + ["    .byte " + ", ".join(f"${int(v):02X}" for v in g2.r.integers(0, 256, 16))
-                                for _ in range(16)])
-        img, _ = assemble_with_symbols("    .org $1000\n" + data_src + "\n    .org $1FFA\n    .word reset, reset, brkh\n")
+    for b in range(nb):
+        d = data if b == 0 else "\n".join(["    .org $1E00"] + [
+            "    .byte " + ", ".join(f"${int(v):02X}" for v in g2.r.integers(0, 256, 16)) for _ in range(16)])
+        img, _ = assemble_with_symbols(f"    .org {org}\n" + code + "\n" + d + VECTORS)
         images.append(img)
-    return images[0] + images[1], 1
+    return b"".join(images), scheme

@@ -53,11 +53,12 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
-    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference"], default="plain",
+    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference", "schemes"], default="plain",
                    help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
                         "serve: 131072 resident envs behind the env server; divergent: 32768 envs over 8 "
                         "branchy ROMs with sticky actions, with the per-step rate over the run; stack: the frame "
-                        "stack of 16384 envs; inference: 4096 envs whose actions come from the policy CNN")
+                        "stack of 16384 envs; inference: 4096 envs whose actions come from the policy CNN; "
+                        "schemes: 36864 envs over one ROM of every cartridge scheme")
     p.add_argument("--serve-seconds", type=float, default=20.0)
     p.add_argument("--serve-pipelines", type=int, default=3)
     p.add_argument("--graph", type=int, default=4,
@@ -376,6 +377,76 @@ def bench_divergent(args):
     }
 
 
+def cpu_baseline_sample(w, roms, env_rom, per_rom, steps):
+    """The oracle on `per_rom` envs of every ROM of `w` for `steps` steps."""
+    import oracle
+    from paper_1907_08467_amd.inputs.palette import GRAY
+    ids = np.concatenate([np.nonzero(env_rom == r)[0][:per_rom] for r in range(len(roms))])
+    o = oracle.Oracle(ids.size, GRAY, frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode,
+                      sticky_threshold=w.sticky_threshold)
+    o.load_roms(roms)
+    o.assign(env_rom[ids])
+    acts = w.actions(steps=steps)[:, ids]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        o.step(acts[s])
+    dt = time.perf_counter() - t0
+    frames = ids.size * w.frameskip * steps
+    return {"value": frames / dt, "unit": "raw frames/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"{per_rom} envs of each of the {len(roms)} ROMs x {steps} steps x frameskip {w.frameskip}, "
+                      "same cartridges, sticky actions and render mode", "seconds": dt}
+
+
+def bench_schemes(args):
+    """36864 envs over one divergent ROM of every cartridge scheme (4K, F8,
+    F6, F4, F8SC, F6SC, F4SC, E0, 3F), sticky actions p = 0.25, last two
+    frames rendered: the interpreter with 32 KB of cartridge in LDS."""
+    import torch
+    from paper_1907_08467_amd.inputs.workloads import config
+    w = config(6)
+    n, K, W = w.n_envs, args.steps, args.warmup
+    env, roms, env_rom = gpu_env(w)
+    dev = torch.device("cuda", 0)
+    launch, launch_from = select_launch(env, args, n, False, True)
+    acts = torch.from_numpy(w.actions(steps=K + W)).to(dev)
+    obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
+    rew = torch.empty(n, dtype=torch.int32, device=dev)
+    done = torch.empty(n, dtype=torch.uint8, device=dev)
+    for s in range(W):
+        env.step(acts[s], out=(obs, rew, done, None))
+    torch.cuda.synchronize()
+    env.timing(True)
+    t0 = time.perf_counter()
+    for s in range(K):
+        env.step(acts[W + s], out=(obs, rew, done, None))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    env.timing(False)
+    instr_last, instr_uniform = env.last_step_stats()
+    kern = kernel_table(env)
+    value = n * w.frameskip * K / dt
+    bits = env.poll_errors()[1]
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("cpu baseline: oracle on a sample of every ROM", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_sample(w, roms, env_rom, per_rom=64, steps=48)
+    return {
+        "metric": "raw emulated frames/s on 1 MI355X (p50/p99 step latency in served mode)",
+        "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"mixed cartridge schemes: {n} envs over 9 synthetic divergent ROMs, one per scheme "
+                               "(4K, F8, F6, F4, F8SC, F6SC, F4SC, E0, 3F), sticky actions p = 0.25, frameskip 4, "
+                               "last two frames rendered + obs, eager steps", "num_envs": n,
+                   "launch": launch, "launch_from": launch_from},
+        "roofline": dict(interp_roofline(kern, instr_last, n, w.frameskip), traffic=None),
+        "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
+        "emulated_instr_per_step": instr_last,
+        "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
+        "errors": bits, "cpu_baseline": cpu,
+    }
+
+
 def bench_stack(args):
     """Frame stack of the last four observations for 16384 envs (the paper's
     memory-wall point), 8-bit and 4-bit storage: push throughput against HBM."""
@@ -589,7 +660,8 @@ def main():
               "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)
         sys.exit(2)
     fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
-          "divergent": bench_divergent, "stack": bench_stack, "inference": bench_inference}[args.workload]
+          "divergent": bench_divergent, "stack": bench_stack, "inference": bench_inference,
+          "schemes": bench_schemes}[args.workload]
     print(json.dumps(fn(args)))
 
 

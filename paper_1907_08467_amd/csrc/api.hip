@@ -72,7 +72,7 @@ struct vcs_ctx {
     std::vector<uint32_t> h_schemes;
     std::vector<RomInfo> h_rinfo;
     std::vector<uint8_t> h_roms;   // [n_roms][kRomSlot]
-    uint32_t rom_lds = 8192;       // cartridge bytes the interpreter stages in LDS
+    uint32_t rom_lds = 8192;       // cartridge bytes the interpreter stages in LDS (0: reads HBM)
 
     // envs
     DevEnv* d_envs = nullptr;
@@ -555,7 +555,7 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     }
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
-    dev_free(c, c->d_roms, (size_t)c->n_roms * kRomSlot);
+    dev_free(c, c->d_roms, (size_t)c->n_roms * kRomSlot + 16);
     dev_free(c, c->d_pre, c->pre_words * sizeof(uint32_t));
     dev_free(c, c->d_cmap, (size_t)c->n_roms * sizeof(CartMap));
     dev_free(c, c->d_pre_off, (size_t)c->n_roms * 4);
@@ -575,13 +575,15 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     c->h_roms.assign((size_t)n_roms * kRomSlot, 0);
     c->h_schemes.assign(scheme, scheme + n_roms);
     c->h_rinfo = info;
-    c->rom_lds = max_bytes > 8192 ? 32768u : 8192u;
+    c->rom_lds = max_bytes > 8192 ? 0u : 8192u;
     for (uint32_t r = 0; r < n_roms; ++r) {
         uint8_t* dst = c->h_roms.data() + (size_t)r * kRomSlot;
         std::memcpy(dst, rom_host[r], rom_bytes[r]);
         if (rom_bytes[r] == 2048) std::memcpy(dst + 2048, rom_host[r], 2048);   // a 2 KB ROM shows twice
     }
-    int rc = alloc_n(c, &c->d_roms, (size_t)n_roms * kRomSlot, "ROMs");
+    // 16 bytes past the last slot: the per-lane fetch reads the dword after a
+    // bank's last instruction word
+    int rc = alloc_n(c, &c->d_roms, (size_t)n_roms * kRomSlot + 16, "ROMs");
     if (!rc) rc = alloc_n(c, &c->d_pre, pre_words, "predecoded ROMs");
     if (!rc) c->pre_words = pre_words;
     if (!rc) rc = alloc_n(c, &c->d_cmap, n_roms, "ROM mappings");
@@ -599,6 +601,7 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     if (!rc) rc = ensure_tile_buffer(c);
     if (rc) return rc;
     for (auto& P : c->pipes) HIP_OK(hipMemset(P.d_stepw, 0, (size_t)c->stepw_words * 4));
+    HIP_OK(hipMemset(c->d_roms, 0, (size_t)n_roms * kRomSlot + 16));
     HIP_OK(hipMemcpy(c->d_roms, c->h_roms.data(), c->h_roms.size(), hipMemcpyHostToDevice));
     std::vector<CartMap> cmap(n_roms);
     std::vector<uint32_t> pre_off(n_roms);

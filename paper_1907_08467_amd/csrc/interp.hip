@@ -207,7 +207,7 @@ __device__ __forceinline__ uint32_t joy_pressed(uint32_t a) {
 __device__ __forceinline__ bool fire_pressed(uint32_t a) { return a == 1 || a >= 10; }
 
 struct Wave {                 // per-workgroup (uniform) data
-    uint8_t* rom;             // LDS copy of the tile's cartridge
+    const uint8_t* rom;       // the tile's cartridge: its LDS copy, or its HBM slot
     uint8_t* ram;             // LDS, kRamStride bytes per lane
     uint8_t* tia;             // LDS, kTiaStride bytes per lane
     const uint32_t* pre;      // the tile ROM's predecoded words
@@ -764,6 +764,9 @@ __device__ __forceinline__ uint32_t fast_store_ok(uint32_t a) {
 // Store classes of a static address, kept in the predecoded ROM word of a
 // store instruction (its byte 3) so the scalar path needs no address decode.
 constexpr uint32_t SC_RAM = 0, SC_WSYNC = 1, SC_IGNORE = 2, SC_EXIT = 3, SC_CART = 4, SC_TIA = 0x20;
+// predecoded classes that depend on the cartridge: an absolute access to the
+// Superchip RAM window, and a 3F slice-select store to an ignored TIA register
+constexpr uint32_t SC_XRAM = 5, SC_3F = 6;
 
 // Class of a store to a (13 bits): RAM, WSYNC, a rendered TIA register (SC_TIA
 // | register code), a write that changes nothing emulated, a cartridge access,
@@ -1075,15 +1078,17 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             F.cyc += N;
             return FS_NEXT;
         } else if constexpr (read_mn(MN)) {
-            if constexpr (MD == ABS) {
-                if (aux == SC_EXIT) return FS_EXIT;   // the Superchip RAM window
-            }
             uint32_t dm = 0;
             if constexpr (MN == ADC || MN == SBC) {
                 dm = dec_mode(c);
                 if (dm == 2) return FS_EXIT;
             }
-            fast_alu(c, MN, fast_rd(c, W, F, a, t), dm);
+            uint32_t v;
+            if (MD == ABS && aux == SC_XRAM)      // Superchip RAM: read port, or the write port (0)
+                v = (a & 0x80) ? (uint32_t)c.xram[a & 0x7F] : 0u;
+            else
+                v = fast_rd(c, W, F, a, t);
+            fast_alu(c, MN, v, dm);
             F.pc = next;
             F.cyc += N;
             return FS_NEXT;
@@ -1100,6 +1105,13 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
                 return FS_EXIT;
             } else if (aux == SC_CART) {
                 F.bank = hotspot(W, F.bank, a);
+            } else if (aux == SC_XRAM) {
+                if (!(a & 0x80)) c.xram[a & 0x7F] = (uint8_t)v;   // writes to the read port do nothing
+            } else if (aux == SC_3F) {
+                // the slice number must agree across the lanes to stay uniform
+                const uint32_t sl = v & cm_tf_mask(W), s0 = rfl(sl);
+                if (!all_lanes(sl == s0)) return FS_EXIT;
+                F.bank = s0;
             }
             F.pc = next;
             F.cyc += N;
@@ -1111,7 +1123,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             if (!(a & 0x1000) && !(a & 0x80)) return FS_EXIT;
             if (!fast_store_ok(a)) return FS_EXIT;
             if constexpr (MD == ABS) {
-                if (aux == SC_EXIT) return FS_EXIT;   // the Superchip RAM window
+                if (aux == SC_XRAM) return FS_EXIT;   // RMW on the Superchip RAM window
             }
             const uint32_t v = fast_rd(c, W, F, a, t);
             const uint32_t r = fast_rmw(c, MN, v);
@@ -1328,11 +1340,13 @@ __device__ __forceinline__ uint32_t take_tile(uint32_t* queue) {
 // LL = envs a tile may hold (64 or 32): RAM and TIA registers get LL + 1
 // slots in LDS (lanes at LL and above, always idle, share the last one), so
 // narrow tiles take less LDS and more waves fit on a compute unit.
-// RC = bytes of cartridge staged in LDS (8 KB, or 32 KB when a loaded ROM is
-// larger than 8 KB).
+// RC = bytes of cartridge staged in LDS (8 KB), or 0: the cartridge is read
+// from its HBM slot through the caches (launches with a ROM larger than 8 KB,
+// which would otherwise need 32 KB of LDS per wave and cut the waves per CU
+// by three).
 template <int LL, int RC>
 __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t* __restrict__ pre_all) {
-    __shared__ uint32_t s_rom[RC / 4 + 4];
+    __shared__ uint32_t s_rom[RC ? RC / 4 + 4 : 1];
     __shared__ uint32_t s_ram[(LL + 1) * kRamStride / 4];
     __shared__ uint32_t s_tia[(LL + 1) * kTiaStride / 4];
 
@@ -1343,13 +1357,15 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
         const int lane = threadIdx.x;
         const int rom_id = T.rom;
 
-        // stage the cartridge in LDS
-        const uint4* rsrc = reinterpret_cast<const uint4*>(A.roms + (size_t)rom_id * kRomSlot);
-        for (int i = lane; i < RC / 16; i += kLanes) reinterpret_cast<uint4*>(s_rom)[i] = rsrc[i];
-        if (lane < 4) s_rom[RC / 4 + lane] = 0;
-
         Wave W;
-        W.rom = reinterpret_cast<uint8_t*>(s_rom);
+        if constexpr (RC > 0) {   // stage the cartridge in LDS
+            const uint4* rsrc = reinterpret_cast<const uint4*>(A.roms + (size_t)rom_id * kRomSlot);
+            for (int i = lane; i < RC / 16; i += kLanes) reinterpret_cast<uint4*>(s_rom)[i] = rsrc[i];
+            if (lane < 4) s_rom[RC / 4 + lane] = 0;
+            W.rom = reinterpret_cast<const uint8_t*>(s_rom);
+        } else {
+            W.rom = A.roms + (size_t)rom_id * kRomSlot;
+        }
         W.ram = reinterpret_cast<uint8_t*>(s_ram);
         W.tia = reinterpret_cast<uint8_t*>(s_tia);
         W.cm = A.cmap[rom_id];
@@ -1472,7 +1488,8 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                         uint32_t v;
                         if (cm_kind(W) == CART_LINEAR) {   // the 4 KB bank is contiguous in LDS
                             const uint32_t boff = (c.bank << 12) | off;
-                            const uint32_t w0 = s_rom[boff >> 2], w1 = s_rom[(boff >> 2) + 1];
+                            const uint32_t* rw = reinterpret_cast<const uint32_t*>(W.rom);
+                            const uint32_t w0 = rw[boff >> 2], w1 = rw[(boff >> 2) + 1];
                             v = __builtin_amdgcn_alignbyte(w1, w0, boff & 3);
                         } else {                          // segments: the predecoded word
                             v = W.pre[(c.bank << 12) | off];
@@ -1596,10 +1613,11 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
 // b2 << 16 | aux << 24 for the instruction that starts there (each byte read
 // through the bank's mapping, so instructions that cross an E0 or 3F segment
 // boundary decode exactly).  aux is the store class of the address of a
-// zero-page or absolute STA/STX/STY; SC_EXIT also marks stores to $00-$3F on
-// 3F cartridges (they switch banks) and absolute accesses to a Superchip RAM
-// window, which the per-lane path takes.  Entries past offset $FFD are never
-// used.
+// zero-page or absolute STA/STX/STY; on 3F cartridges a store to $00-$3F
+// (which also selects a slice) is SC_3F when the TIA register it reaches is
+// not emulated, else SC_EXIT (left to the per-lane path); on Superchip
+// cartridges an absolute access to the RAM window is SC_XRAM.  Entries past
+// offset $FFD are never used.
 __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R.n_vbanks * 4096u) return;
@@ -1614,10 +1632,10 @@ __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre) {
     const uint32_t a = (op == 0x84 || op == 0x85 || op == 0x86) ? b1 : abs_addr;
     if (st) {
         aux = store_class(a);
-        if (R.kind == CART_3F && a <= 0x3F) aux = SC_EXIT;
+        if (R.kind == CART_3F && a <= 0x3F) aux = aux == SC_IGNORE ? SC_3F : SC_EXIT;
     }
     if (R.sc && md == ABS && ((d >> DW_RD) & 1 || (d >> DW_WR) & 1) && (abs_addr & 0x1000) && !(abs_addr & 0xF00))
-        aux = SC_EXIT;
+        aux = SC_XRAM;
     pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24);
 }
 
@@ -1627,11 +1645,11 @@ void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, hi
 }
 
 void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s) {
-    if (rom_lds > 8192) {
+    if (rom_lds == 0) {
         if (tile_envs <= 32)
-            hipLaunchKernelGGL((k_interp<32, 32768>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+            hipLaunchKernelGGL((k_interp<32, 0>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
         else
-            hipLaunchKernelGGL((k_interp<64, 32768>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+            hipLaunchKernelGGL((k_interp<64, 0>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
     } else if (tile_envs <= 32) {
         hipLaunchKernelGGL((k_interp<32, 8192>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
     } else {

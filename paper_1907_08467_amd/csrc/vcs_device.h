@@ -195,7 +195,8 @@ struct ResetArgs {
 };
 
 // host launchers (one per kernel)
-// tile_envs: widest tile; rom_lds: bytes of ROM staged in LDS (8192 or 32768)
+// tile_envs: widest tile; rom_lds: bytes of ROM staged in LDS (8192), or 0 to
+// read the cartridges from HBM
 void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s);
 void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, hipStream_t s);
 void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s);

@@ -1,4 +1,4 @@
-"""The five workload configurations, as seeded synthetic inputs.
+"""The workload configurations, as seeded synthetic inputs.
 
 Each configuration stands in for the paper's emulation-only measurements on
 its game suite (Section 4, Fig. 2a and Fig. 3) with synthetic cartridges from
@@ -83,6 +83,12 @@ def config(c: int) -> Workload:
         return Workload("batching: 65536 envs, 16 ROMs Zipf 1.2, render last 2", 65536, _mixed16(4),
                         2000, action_seed=3, render_mode=RENDER_LAST2, rng_seed=4,
                         counts=zipf_counts(65536, 16, 1.2), assign_seed=104)
+    if c == 6:
+        kinds = ["4k", "f8", "f6", "f4", "f8sc", "f6sc", "f4sc", "e0", "3f"]
+        specs = [RomSpec(6000 + r, k, True) for r, k in enumerate(kinds)]
+        return Workload("mixed schemes: 36864 envs, 9 ROMs (every cartridge scheme), sticky 0.25, render last 2",
+                        36864, specs, 2000, action_seed=6, sticky_threshold=0x40000000,
+                        render_mode=RENDER_LAST2, rng_seed=6, assign_seed=106)
     if c == 5:
         return Workload("serving: 131072 resident envs, 16 ROMs Zipf 1.2", 131072, _mixed16(4),
                         0, action_seed=5, render_mode=RENDER_LAST2, rng_seed=5,

@@ -124,3 +124,9 @@ def test_plain_batch_4096_all_envs_states():
         a_, b_ = g.get_state(e), o.get_state(e)
         assert np.array_equal(a_, b_), f"state of env {e}: {diff_records(a_, b_)}"
     say(f"all {w.n_envs} env states agree after {steps} steps")
+
+
+def test_mixed_schemes_36864_sampled():
+    """36864 envs over one ROM of every cartridge scheme (E0 and 3F included),
+    sticky actions, last two frames rendered."""
+    run_sampled(6, steps=30, per_rom=10, check_every=15)

@@ -189,6 +189,7 @@ static void build_cache_entry(oracle_ctx* c, uint32_t r, uint32_t k) {
     ORom* rom = &c->roms[r];
     OMachine m;
     m_power_on(&m, rom->data, rom->size, rom->scheme);
+    m.track_cx = c->cfg.collisions ? 1 : 0;
     m_set_action(&m, 0);
     uint32_t noops = (uint32_t)((oracle_rng(c->cfg.seed, r, NOOPS, k) >> 32) % (c->cfg.noop_max + 1));
     uint32_t total = 1 + c->cfg.startup_frames + noops;   /* frame 0 + start-up + no-ops */
@@ -385,6 +386,7 @@ int oracle_set_state(oracle_ctx* c, uint32_t env, const uint8_t* in) {
     if (r >= c->n_roms) return ORC_E_INVAL;
     OMachine* m = &c->envs[env];
     m_from_record(m, in);
+    m->track_cx = c->cfg.collisions ? 1 : 0;
     m->rom = c->roms[r].data;
     m->rom_size = c->roms[r].size;
     m->scheme = c->roms[r].scheme;

@@ -37,6 +37,19 @@
  *    segment k of 0-2 set to slice n by an access to $FE0 + 8k + n); 3F
  *    (2 KB slices: the upper half fixed to the last one, the lower half set
  *    to slice v mod S by a write of v to $00-$3F, which also reaches the TIA).
+ *  - TIA objects: players with NUSIZ copies (offsets 0/16/32/64 by mode) and
+ *    double/quad width, missiles (ENAM, 1-8 pixels, the player's copies,
+ *    hidden while RESMP is set and placed at the player's position + 3/6/10
+ *    when it is released), the ball (ENABL, CTRLPF size), vertical delay (a
+ *    GRP0 write copies GRP1 to its old register, a GRP1 write copies GRP0 and
+ *    ENABL), RESM/RESBL at h < 68 ? 2 : h - 68 + 4, HMOVE moving all five by
+ *    their HM nibbles and, when written before colour clock 68, blanking
+ *    pixels 0-7 of its line; priority P0/M0 > P1/M1 > PF/BL > BK (PF/BL
+ *    first with CTRLPF D2), the ball in COLUPF.
+ *  - Collisions (when tracked): the 15 latches set at every drawn pixel of
+ *    the 210 frame rows (VBLANK clear, outside an HMOVE blank) where two
+ *    objects meet; a read at access cycle t sees pixels up to colour clock
+ *    3t+2; CXCLR clears them; untracked, they read 0.
  *  - Undocumented opcodes: the stable ones (SLO, RLA, SRE, RRA, SAX, LAX,
  *    DCP, ISC, ANC, ALR, ARR, SBX, LAS, SBC #, and the NOPs of every width,
  *    which perform their read) run with the operations, cycle counts and
@@ -274,6 +287,8 @@ static void cart_write(OMachine* m, uint16_t a, uint8_t v) {
 }
 
 static uint8_t tia_read(const OMachine* m, uint16_t reg) {
+    if ((reg & 0x0F) < 8)              /* CXM0P .. CXPPMM: latches in D7, D6 */
+        return m->track_cx ? (uint8_t)(((m->cx >> (2 * (reg & 7))) & 3) << 6) : 0;
     switch (reg & 0x0F) {
     case 0x0C: return m->inpt4;        /* INPT4: fire button of player 0 */
     case 0x0D: return 0x80;            /* INPT5: player 1 button never pressed */
@@ -334,20 +349,49 @@ static void tia_write(OMachine* m, uint16_t reg, uint8_t v) {
     case 0x0F: m->pf2 = v; break;
     case 0x10: m->p0x = (uint8_t)(h_eff < 68 ? 3 : (h_eff - 68 + 5) % 160); break;
     case 0x11: m->p1x = (uint8_t)(h_eff < 68 ? 3 : (h_eff - 68 + 5) % 160); break;
-    case 0x1B: m->grp0 = v; break;
-    case 0x1C: m->grp1 = v; break;
+    case 0x12: m->m0x = (uint8_t)(h_eff < 68 ? 2 : (h_eff - 68 + 4) % 160); break;
+    case 0x13: m->m1x = (uint8_t)(h_eff < 68 ? 2 : (h_eff - 68 + 4) % 160); break;
+    case 0x14: m->blx = (uint8_t)(h_eff < 68 ? 2 : (h_eff - 68 + 4) % 160); break;
+    case 0x04: m->nusiz0 = v; break;
+    case 0x05: m->nusiz1 = v; break;
+    case 0x1B: m->grp0 = v; m->grp1_old = m->grp1; break;
+    case 0x1C: m->grp1 = v; m->grp0_old = m->grp0; m->enabl_old = m->enabl; break;
+    case 0x1D: m->enam0 = v; break;
+    case 0x1E: m->enam1 = v; break;
+    case 0x1F: m->enabl = v; break;
     case 0x20: m->hmp0 = v; break;
     case 0x21: m->hmp1 = v; break;
-    case 0x2A: {                       /* HMOVE: move by the signed high nibble, now */
-        int d0 = (m->hmp0 >> 4) & 0xF, d1 = (m->hmp1 >> 4) & 0xF;
-        if (d0 >= 8) d0 -= 16;
-        if (d1 >= 8) d1 -= 16;
-        m->p0x = (uint8_t)(((int)m->p0x - d0 + 160) % 160);
-        m->p1x = (uint8_t)(((int)m->p1x - d1 + 160) % 160);
+    case 0x22: m->hmm0 = v; break;
+    case 0x23: m->hmm1 = v; break;
+    case 0x24: m->hmbl = v; break;
+    case 0x25: m->vdelp0 = v; break;
+    case 0x26: m->vdelp1 = v; break;
+    case 0x27: m->vdelbl = v; break;
+    case 0x28: case 0x29: {            /* RESMP: release puts the missile at the player's centre */
+        static const uint8_t CENTRE[8] = {3, 3, 3, 3, 3, 6, 3, 10};
+        if (reg == 0x28) {
+            if (!(v & 2) && (m->resmp0 & 2)) m->m0x = (uint8_t)((m->p0x + CENTRE[m->nusiz0 & 7]) % 160);
+            m->resmp0 = v;
+        } else {
+            if (!(v & 2) && (m->resmp1 & 2)) m->m1x = (uint8_t)((m->p1x + CENTRE[m->nusiz1 & 7]) % 160);
+            m->resmp1 = v;
+        }
         break;
     }
-    case 0x2B: m->hmp0 = 0; m->hmp1 = 0; break;
-    default: break;                    /* audio, missiles, ball, NUSIZ, ... ignored */
+    case 0x2A: {                       /* HMOVE: every object by its signed high nibble, now */
+        const uint8_t hm[5] = {m->hmp0, m->hmp1, m->hmm0, m->hmm1, m->hmbl};
+        uint8_t* pos[5] = {&m->p0x, &m->p1x, &m->m0x, &m->m1x, &m->blx};
+        for (int i = 0; i < 5; i++) {
+            int d = (hm[i] >> 4) & 0xF;
+            if (d >= 8) d -= 16;
+            *pos[i] = (uint8_t)(((int)*pos[i] - d + 160) % 160);
+        }
+        if (h_eff < 68) m->hmove_blank_line = (int64_t)((m->access_cycle + 1) / 76);
+        break;
+    }
+    case 0x2B: m->hmp0 = m->hmp1 = m->hmm0 = m->hmm1 = m->hmbl = 0; break;
+    case 0x2C: m->cx = 0; break;
+    default: break;                    /* audio and the rest: no emulated effect */
     }
 }
 
@@ -391,48 +435,111 @@ static int playfield_bit(const OMachine* m, int p) {
     return (m->pf2 >> (p - 12)) & 1;                    /* PF2 D0..D7 */
 }
 
-static int player_on(uint8_t pos, uint8_t grp, uint8_t refp, int x) {
+/* copies of a player / missile for NUSIZ mode 0-7: offsets, count */
+static const uint8_t COPY_OFF[8][3] = {{0}, {0, 16}, {0, 32}, {0, 16, 32}, {0, 64}, {0}, {0, 32, 64}, {0}};
+static const uint8_t COPY_N[8] = {1, 2, 2, 3, 2, 1, 3, 1};
+
+static int player_on(uint8_t pos, uint8_t grp, uint8_t refp, uint8_t nusiz, int x) {
+    int mode = nusiz & 7;
+    int w = mode == 5 ? 2 : (mode == 7 ? 4 : 1);
     int d = (x - (int)pos + 160) % 160;
-    if (d >= 8) return 0;
-    int bit = (refp & 8) ? d : 7 - d;
-    return (grp >> bit) & 1;
+    for (int k = 0; k < COPY_N[mode]; k++) {
+        int dd = d - COPY_OFF[mode][k];
+        if (dd < 0 || dd >= 8 * w) continue;
+        int b = dd / w;
+        int bit = (refp & 8) ? b : 7 - b;
+        return (grp >> bit) & 1;
+    }
+    return 0;
 }
 
-/* colour of visible pixel x (0..159) from the registers in effect now */
-static uint8_t pixel_colour(const OMachine* m, int x) {
-    if (m->vblank & 2) return 0;
+static int missile_on(uint8_t pos, uint8_t enam, uint8_t resmp, uint8_t nusiz, int x) {
+    if (!(enam & 2) || (resmp & 2)) return 0;
+    int mode = nusiz & 7;
+    int size = 1 << ((nusiz >> 4) & 3);
+    int n = (mode == 5 || mode == 7) ? 1 : COPY_N[mode];
+    int d = (x - (int)pos + 160) % 160;
+    for (int k = 0; k < n; k++) {
+        int dd = d - COPY_OFF[mode][k];
+        if (dd >= 0 && dd < size) return 1;
+    }
+    return 0;
+}
+
+static int ball_on(const OMachine* m, int x) {
+    uint8_t en = (m->vdelbl & 1) ? m->enabl_old : m->enabl;
+    if (!(en & 2)) return 0;
+    int d = (x - (int)m->blx + 160) % 160;
+    return d < (1 << ((m->ctrlpf >> 4) & 3));
+}
+
+/* the objects at visible pixel x: bit 0 PF, 1 BL, 2 P0, 3 P1, 4 M0, 5 M1 */
+static int objects_at(const OMachine* m, int x) {
     int p;
     if (x < 80) p = x / 4;
     else if (m->ctrlpf & 1) p = 19 - (x - 80) / 4;
     else p = (x - 80) / 4;
-    int pf = playfield_bit(m, p);
-    int p0 = player_on(m->p0x, m->grp0, m->refp0, x);
-    int p1 = player_on(m->p1x, m->grp1, m->refp1, x);
+    int o = playfield_bit(m, p);
+    o |= ball_on(m, x) << 1;
+    o |= player_on(m->p0x, (m->vdelp0 & 1) ? m->grp0_old : m->grp0, m->refp0, m->nusiz0, x) << 2;
+    o |= player_on(m->p1x, (m->vdelp1 & 1) ? m->grp1_old : m->grp1, m->refp1, m->nusiz1, x) << 3;
+    o |= missile_on(m->m0x, m->enam0, m->resmp0, m->nusiz0, x) << 4;
+    o |= missile_on(m->m1x, m->enam1, m->resmp1, m->nusiz1, x) << 5;
+    return o;
+}
+
+/* colour of pixel x (0..159) drawn with objects o */
+static uint8_t pixel_colour(const OMachine* m, int x, int o) {
+    int pf = o & 1, bl = (o >> 1) & 1, p0 = ((o >> 2) | (o >> 4)) & 1, p1 = ((o >> 3) | (o >> 5)) & 1;
     uint8_t pfc = (m->ctrlpf & 2) ? (x < 80 ? m->colup0 : m->colup1) : m->colupf;
+    uint8_t fc = pf ? pfc : m->colupf;          /* the playfield/ball level */
     uint8_t c;
     if (m->ctrlpf & 4) {
-        if (pf) c = pfc;
+        if (pf || bl) c = fc;
         else if (p0) c = m->colup0;
         else if (p1) c = m->colup1;
         else c = m->colubk;
     } else {
         if (p0) c = m->colup0;
         else if (p1) c = m->colup1;
-        else if (pf) c = pfc;
+        else if (pf || bl) c = fc;
         else c = m->colubk;
     }
     return (uint8_t)(c & 0xFE);
 }
 
+/* collision latches for objects o: (object a, object b, latch bit) */
+static void collide(OMachine* m, int o) {
+    static const uint8_t PAIRS[15][3] = {
+        {4, 3, 1}, {4, 2, 0},     /* CXM0P:  M0-P1, M0-P0 */
+        {5, 2, 3}, {5, 3, 2},     /* CXM1P:  M1-P0, M1-P1 */
+        {2, 0, 5}, {2, 1, 4},     /* CXP0FB: P0-PF, P0-BL */
+        {3, 0, 7}, {3, 1, 6},     /* CXP1FB: P1-PF, P1-BL */
+        {4, 0, 9}, {4, 1, 8},     /* CXM0FB: M0-PF, M0-BL */
+        {5, 0, 11}, {5, 1, 10},   /* CXM1FB: M1-PF, M1-BL */
+        {1, 0, 13},               /* CXBLPF: BL-PF */
+        {2, 3, 15}, {4, 5, 14}};  /* CXPPMM: P0-P1, M0-M1 */
+    for (int i = 0; i < 15; i++)
+        if (((o >> PAIRS[i][0]) & 1) && ((o >> PAIRS[i][1]) & 1)) m->cx |= (uint16_t)(1u << PAIRS[i][2]);
+}
+
 /* the beam during cycle c: colour clocks 3c .. 3c+2 */
 static void beam_cycle(OMachine* m, uint64_t c) {
-    if (!m->fb) return;
+    if (!m->fb && !m->track_cx) return;
     for (int i = 0; i < 3; i++) {
         uint64_t g = 3 * c + (uint64_t)i;
         int64_t line = (int64_t)(g / 228);
         int h = (int)(g % 228);
         int64_t row = line - (int64_t)m->frame_line0 - 34;
-        if (h >= 68 && row >= 0 && row < 210) m->fb[row * 160 + (h - 68)] = pixel_colour(m, h - 68);
+        if (h < 68 || row < 0 || row >= 210) continue;
+        int x = h - 68;
+        uint8_t px = 0;
+        if (!(m->vblank & 2) && !(x < 8 && line == m->hmove_blank_line)) {
+            int o = objects_at(m, x);
+            px = pixel_colour(m, x, o);
+            if (m->track_cx) collide(m, o);
+        }
+        if (m->fb) m->fb[row * 160 + x] = px;
     }
 }
 
@@ -807,6 +914,7 @@ void m_power_on(OMachine* m, const uint8_t* rom, uint32_t size, uint32_t scheme)
     m->sp = 0xFD;
     m->p = 0x24;
     m->tim_interval = 1024;            /* INTIM reads 0 from cycle 0, interval 1024 */
+    m->hmove_blank_line = -1;
     m->pc = (uint16_t)(rom_byte(m, 0x1FFC) | (rom_byte(m, 0x1FFD) << 8));
     m_set_action(m, 0);
 }
@@ -845,6 +953,13 @@ void m_to_record(const OMachine* src, uint8_t* out) {
     out[192] = m.prev_action;
     out[194] = m.err;
     put64(out + 200, m.instr_count);
+    const uint8_t objs[19] = {m.nusiz0, m.nusiz1, m.enam0, m.enam1, m.enabl, m.enabl_old, m.grp0_old, m.grp1_old,
+                              m.vdelp0, m.vdelp1, m.vdelbl, m.resmp0, m.resmp1, m.m0x, m.m1x, m.blx,
+                              m.hmm0, m.hmm1, m.hmbl};
+    memcpy(out + 208, objs, 19);
+    out[227] = m.hmove_blank_line == (int64_t)(m.cycle / 76);
+    put16(out + 228, m.cx);
+    out[230] = m.track_cx;
     memcpy(out + 256, m.xram, 128);
 }
 
@@ -871,5 +986,13 @@ void m_from_record(OMachine* m, const uint8_t* in) {
     m->prev_action = in[192];
     m->err = in[194];
     m->instr_count = get64(in + 200);
+    const uint8_t* o = in + 208;
+    m->nusiz0 = o[0]; m->nusiz1 = o[1]; m->enam0 = o[2]; m->enam1 = o[3]; m->enabl = o[4]; m->enabl_old = o[5];
+    m->grp0_old = o[6]; m->grp1_old = o[7]; m->vdelp0 = o[8]; m->vdelp1 = o[9]; m->vdelbl = o[10];
+    m->resmp0 = o[11]; m->resmp1 = o[12]; m->m0x = o[13]; m->m1x = o[14]; m->blx = o[15];
+    m->hmm0 = o[16]; m->hmm1 = o[17]; m->hmbl = o[18];
+    m->hmove_blank_line = in[227] ? (int64_t)(m->cycle / 76) : -1;
+    m->cx = get16(in + 228);
+    m->track_cx = in[230];
     memcpy(m->xram, in + 256, 128);
 }

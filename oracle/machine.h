@@ -35,10 +35,17 @@ typedef struct {
     uint8_t tim_expired;
     uint16_t tim_sub;
     uint16_t tim_interval;
-    /* TIA write registers (last byte written) and player positions */
+    /* TIA write registers (last byte written) and object positions */
     uint8_t vsync, vblank, colup0, colup1, colupf, colubk, ctrlpf, refp0, refp1;
     uint8_t pf0, pf1, pf2, grp0, grp1, hmp0, hmp1;
     uint8_t p0x, p1x;
+    uint8_t nusiz0, nusiz1, enam0, enam1, enabl, resmp0, resmp1;
+    uint8_t vdelp0, vdelp1, vdelbl, hmm0, hmm1, hmbl;
+    uint8_t grp0_old, grp1_old, enabl_old;     /* the vertical-delay copies */
+    uint8_t m0x, m1x, blx;
+    int64_t hmove_blank_line;   /* line whose pixels 0-7 an early HMOVE blanked, or -1 */
+    uint16_t cx;                /* collision latches: bit 2r+1 = D7, bit 2r = D6 of CX register r */
+    uint8_t track_cx;           /* collision latches tracked (else they read 0) */
     /* the frame being emulated */
     uint64_t frame_line0;
     uint8_t* fb;                /* 210 x 160 frame buffer, or NULL */

@@ -31,6 +31,13 @@
  *  173 GRP1 174 HMP0 175 HMP1 176 P0 position 177 P1 position
  *  180..183 rom_id   184..187 step_idx   188..191 episode_idx
  *  192 prev_action   193 (0)   194 err bits   200..207 instructions executed
+ *  208 NUSIZ0 209 NUSIZ1 210 ENAM0 211 ENAM1 212 ENABL 213 ENABL (delayed copy)
+ *  214 GRP0 (delayed copy) 215 GRP1 (delayed copy) 216 VDELP0 217 VDELP1
+ *  218 VDELBL 219 RESMP0 220 RESMP1 221 M0 position 222 M1 position
+ *  223 ball position 224 HMM0 225 HMM1 226 HMBL
+ *  227 1 when an early HMOVE blanked pixels 0-7 of the line of `cycle`
+ *  228..229 collision latches (bit 2r+1 / 2r = D7 / D6 of CX register r)
+ *  230 collision latches tracked (0/1)
  *  256..383 Superchip RAM (0 for other cartridges)
  *  all other bytes 0.
  *
@@ -69,6 +76,7 @@ typedef struct {
     uint32_t startup_frames;     /* start-up frames (paper: 64)               */
     uint64_t seed;
     uint32_t render_mode;        /* ORC_RENDER_ALL or ORC_RENDER_LAST2        */
+    uint32_t collisions;         /* 1: track the TIA collision latches        */
     uint8_t gray_lut[128];       /* gray value of colour index (c >> 1)       */
 } oracle_config;
 

@@ -110,7 +110,8 @@ VCS_SYMBOLS = {
     "HMP0": 0x20, "HMP1": 0x21, "HMM0": 0x22, "HMM1": 0x23, "HMBL": 0x24,
     "VDELP0": 0x25, "VDELP1": 0x26, "VDELBL": 0x27, "RESMP0": 0x28, "RESMP1": 0x29,
     "HMOVE": 0x2A, "HMCLR": 0x2B, "CXCLR": 0x2C,
-    "INPT4": 0x0C, "INPT5": 0x0D,
+    "CXM0P": 0x00, "CXM1P": 0x01, "CXP0FB": 0x02, "CXP1FB": 0x03, "CXM0FB": 0x04, "CXM1FB": 0x05,
+    "CXBLPF": 0x06, "CXPPMM": 0x07, "INPT4": 0x0C, "INPT5": 0x0D,
     "SWCHA": 0x280, "SWACNT": 0x281, "SWCHB": 0x282, "SWBCNT": 0x283,
     "INTIM": 0x284, "TIMINT": 0x285,
     "TIM1T": 0x294, "TIM8T": 0x295, "TIM64T": 0x296, "T1024T": 0x297,

@@ -1,0 +1,253 @@
+"""Pins of the oracle's fuller TIA: NUSIZ copies and widths, missiles, the
+ball, vertical delay, RESMP, HMOVE of every object and its blank, priority
+with missiles and ball, and the collision latches.  Every expected pixel and
+latch is derived by hand from the register definitions and the timing
+conventions: a write at access cycle c takes effect at colour clock
+3(c+1); a player reset at clock h >= 68 lands at h - 68 + 5, a missile or
+ball reset at h - 68 + 4; frame row r is scanline 34 + r.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import cart, decode
+
+ROW = 60                                   # a visible row every test looks at
+
+
+def rom_with(setup, per_frame_end=""):
+    """`setup` runs once on a line of its own (after a WSYNC, so its first
+    instruction starts at cycle 0); frames are 1 + 255 WSYNC lines, then
+    `per_frame_end` runs in the VSYNC line."""
+    src = f"""
+reset:
+    sta WSYNC
+{setup}
+frame:
+    sta WSYNC
+    lda #2
+    sta VSYNC
+    lda #0
+    sta VSYNC
+{per_frame_end}
+    ldx #0
+lines:
+    sta WSYNC
+    dex
+    bne lines
+    jmp frame
+"""
+    rom, _ = cart(src)
+    return rom
+
+
+def run(rom, n=3, track=False):
+    st = oracle.power_on(rom)
+    st[230] = 1 if track else 0
+    st, frames, ends, got = oracle.run_frames(st, rom, n, actions=np.zeros(n, np.uint8))
+    assert got == n and decode(st)["err"] == 0
+    return frames[-1], decode(st)
+
+
+def lit(row):
+    return set(np.nonzero(row)[0].tolist())
+
+
+# 20 NOPs after the WSYNC: the next store's access cycle is 40 + 2 = 42 ->
+# clock 129 -> player position 66, missile / ball position 65
+AT42 = "    nop\n" * 20
+
+
+@pytest.mark.parametrize("mode,want", [(0, {66}), (1, {66, 82}), (2, {66, 98}), (3, {66, 82, 98}),
+                                       (4, {66, 130}), (5, {66, 67}), (6, {66, 98, 130}),
+                                       (7, {66, 67, 68, 69})])
+def test_player_copies_and_widths(mode, want):
+    f, _ = run(rom_with(f"    lda #${mode:02X}\n    sta NUSIZ0\n    lda #$80\n    sta GRP0\n"
+                        f"    lda #$36\n    sta COLUP0\n    sta WSYNC\n" + AT42 + "    sta RESP0"))
+    assert lit(f[ROW]) == want and f[ROW][66] == 0x36
+
+
+@pytest.mark.parametrize("nusiz,want", [(0x00, {65}), (0x10, {65, 66}), (0x20, set(range(65, 69))),
+                                        (0x30, set(range(65, 73))), (0x11, {65, 66, 81, 82}),
+                                        (0x05, {65}), (0x16, {65, 66, 97, 98, 129, 130})])
+def test_missile_sizes_and_copies(nusiz, want):
+    f, _ = run(rom_with(f"    lda #${nusiz:02X}\n    sta NUSIZ0\n    lda #2\n    sta ENAM0\n"
+                        f"    lda #$36\n    sta COLUP0\n    sta WSYNC\n" + AT42 + "    sta RESM0"))
+    assert lit(f[ROW]) == want and f[ROW][65] == 0x36
+
+
+@pytest.mark.parametrize("ctrlpf,want", [(0x00, {65}), (0x10, {65, 66}), (0x20, set(range(65, 69))),
+                                         (0x30, set(range(65, 73)))])
+def test_ball_sizes_in_playfield_colour(ctrlpf, want):
+    f, _ = run(rom_with(f"    lda #${ctrlpf | 2:02X}\n    sta CTRLPF\n    lda #2\n    sta ENABL\n"
+                        f"    lda #$44\n    sta COLUPF\n    lda #$36\n    sta COLUP0\n    sta WSYNC\n" + AT42 +
+                        "    sta RESBL"))
+    # score mode (CTRLPF D1) colours the playfield, not the ball
+    assert lit(f[ROW]) == want and f[ROW][65] == 0x44
+
+
+def test_vertical_delay():
+    base = "    lda #1\n    sta VDELP0\n    lda #$FF\n    sta GRP0\n    lda #$36\n    sta COLUP0\n" \
+           "    sta WSYNC\n" + AT42 + "    sta RESP0\n"
+    f, _ = run(rom_with(base))
+    assert lit(f[ROW]) == set()                       # the delayed copy is still 0
+    f, _ = run(rom_with(base + "    sta GRP1\n    lda #0\n    sta GRP0"))
+    assert lit(f[ROW]) == set(range(66, 74))          # GRP1 copied GRP0 ($FF); a new GRP0 waits
+    f, _ = run(rom_with("    lda #2\n    sta ENABL\n    lda #1\n    sta VDELBL\n    sta WSYNC\n" + AT42 +
+                        "    sta RESBL\n    lda #$44\n    sta COLUPF"))
+    assert lit(f[ROW]) == set()
+    f, _ = run(rom_with("    lda #2\n    sta ENABL\n    lda #1\n    sta VDELBL\n    sta GRP1\n"
+                        "    lda #0\n    sta ENABL\n    sta WSYNC\n" + AT42 + "    sta RESBL\n    lda #$44\n    sta COLUPF"))
+    assert lit(f[ROW]) == {65}                        # GRP1 copied ENABL (2) before it was cleared
+
+
+@pytest.mark.parametrize("nusiz,pos", [(0, 69), (5, 72), (7, 76)])
+def test_resmp_release_centres_missile(nusiz, pos):
+    setup = f"    lda #${nusiz:02X}\n    sta NUSIZ0\n    lda #2\n    sta ENAM0\n    sta RESMP0\n" \
+            "    lda #$36\n    sta COLUP0\n    sta WSYNC\n" + AT42 + "    sta RESP0\n"
+    f, _ = run(rom_with(setup))
+    assert lit(f[ROW]) == set()                       # hidden while RESMP0 D1 is set
+    f, _ = run(rom_with(setup + "    lda #0\n    sta RESMP0"))
+    assert lit(f[ROW]) == {pos}
+
+
+def test_hmove_moves_missiles_and_ball():
+    setup = "    lda #2\n    sta ENAM0\n    sta ENABL\n    lda #$36\n    sta COLUP0\n    lda #$44\n    sta COLUPF\n" \
+            "    sta WSYNC\n" + AT42 + "    sta RESM0\n" + "    sta WSYNC\n" + "    nop\n" * 24 + "    sta RESBL\n" \
+            "    lda #$F0\n    sta HMM0\n    lda #$20\n    sta HMBL\n    sta HMOVE\n"
+    # RESBL: 24 NOPs -> access cycle 50 -> clock 153 -> position 89; HMM0 $F0 moves +1, HMBL $20 moves -2
+    f, _ = run(rom_with(setup))
+    assert lit(f[ROW]) == {66, 87} and f[ROW][66] == 0x36 and f[ROW][87] == 0x44
+    f, _ = run(rom_with(setup + "    sta HMCLR\n    sta HMOVE"))
+    assert lit(f[ROW]) == {66, 87}                    # HMCLR: a second HMOVE moves nothing
+
+
+def test_hmove_blank():
+    # per line: STA HMOVE right after the WSYNC (access cycle 2, clock 9 < 68)
+    # blanks pixels 0-7 of the line; one at access cycle 42 does not
+    early = f"""
+reset:
+    lda #$1E
+    sta COLUBK
+frame:
+    sta WSYNC
+    lda #2
+    sta VSYNC
+    lda #0
+    sta VSYNC
+    ldx #0
+lines:
+    sta WSYNC
+    sta HMOVE
+    dex
+    bne lines
+    jmp frame
+"""
+    rom, _ = cart(early)
+    f, _ = run(rom)
+    assert (f[ROW][:8] == 0).all() and (f[ROW][8:] == 0x1E).all()
+    late = early.replace("    sta HMOVE\n", "    nop\n" * 20 + "    sta HMOVE\n")
+    rom, _ = cart(late)
+    f, _ = run(rom)
+    assert (f[ROW] == 0x1E).all()
+
+
+def test_priority_with_missiles_and_ball():
+    # M0 at 65 over P1 (66-73, $FF), ball at 65 under both; PF (PF2 bit 0 -> pixels 32-35) far away
+    setup = "    lda #2\n    sta ENAM0\n    sta ENABL\n    lda #$FF\n    sta GRP1\n    lda #$36\n    sta COLUP0\n" \
+            "    lda #$58\n    sta COLUP1\n    lda #$44\n    sta COLUPF\n    lda #$10\n    sta NUSIZ0\n" \
+            "    sta WSYNC\n" + AT42 + "    sta RESM0\n    sta WSYNC\n" + AT42 + "    sta RESP1\n" + \
+            "    sta WSYNC\n" + AT42 + "    sta RESBL\n"
+    f, _ = run(rom_with(setup))
+    row = f[ROW]
+    assert row[65] == 0x36 and row[66] == 0x36 and row[67] == 0x58 and row[73] == 0x58 and row[74] == 0
+    f, _ = run(rom_with(setup + "    lda #4\n    sta CTRLPF"))     # PF/BL first: the ball shows at 65
+    row = f[ROW]
+    assert row[65] == 0x44 and row[66] == 0x36 and row[67] == 0x58
+
+
+CX_READ = "\n".join(f"    lda ${r:02X}\n    sta ${0x90 + r:02X}" for r in range(8)) + "\n    sta CXCLR"
+
+
+def cx_regs(d):
+    return [int(d["ram"][0x10 + r]) for r in range(8)]
+
+
+def test_all_collisions_at_one_pixel():
+    # every object on pixel 66: players 66-73, missiles and ball 2 wide from 65,
+    # playfield block 16 (PF2 D4) = pixels 64-67
+    setup = "    lda #$10\n    sta PF2\n    lda #2\n    sta ENAM0\n    sta ENAM1\n    sta ENABL\n" \
+            "    lda #$FF\n    sta GRP0\n    sta GRP1\n    lda #$10\n    sta NUSIZ0\n    sta NUSIZ1\n" \
+            "    lda #$10\n    sta CTRLPF\n" + \
+            "".join("    sta WSYNC\n" + AT42 + f"    sta {r}\n" for r in ("RESP0", "RESP1", "RESM0", "RESM1", "RESBL"))
+    _, d = run(rom_with(setup, per_frame_end=CX_READ), track=True)
+    assert cx_regs(d) == [0xC0, 0xC0, 0xC0, 0xC0, 0xC0, 0xC0, 0x80, 0xC0]
+    _, d = run(rom_with(setup, per_frame_end=CX_READ), track=False)
+    assert cx_regs(d) == [0] * 8                        # untracked latches read 0
+
+
+@pytest.mark.parametrize("pair,reg,bit", [(("RESP0", "RESP1"), 7, 0x80), (("RESM0", "RESP1"), 0, 0x80),
+                                          (("RESM0", "RESP0"), 0, 0x40), (("RESM1", "RESP0"), 1, 0x80),
+                                          (("RESM1", "RESP1"), 1, 0x40), (("RESM0", "RESM1"), 7, 0x40),
+                                          (("RESP0", "RESBL"), 2, 0x40), (("RESP1", "RESBL"), 3, 0x40),
+                                          (("RESM0", "RESBL"), 4, 0x40), (("RESM1", "RESBL"), 5, 0x40)])
+def test_single_collision_pairs(pair, reg, bit):
+    """Only two objects are enabled and placed together: exactly one latch."""
+    enable = {"RESP0": "    lda #$FF\n    sta GRP0\n", "RESP1": "    lda #$FF\n    sta GRP1\n",
+              "RESM0": "    lda #$32\n    sta ENAM0\n    lda #$30\n    sta NUSIZ0\n",
+              "RESM1": "    lda #$32\n    sta ENAM1\n    lda #$30\n    sta NUSIZ1\n",
+              "RESBL": "    lda #2\n    sta ENABL\n    lda #$30\n    sta CTRLPF\n"}
+    setup = enable[pair[0]] + enable[pair[1]] + "".join("    sta WSYNC\n" + AT42 + f"    sta {r}\n" for r in pair)
+    _, d = run(rom_with(setup, per_frame_end=CX_READ), track=True)
+    want = [0] * 8
+    want[reg] = bit
+    assert cx_regs(d) == want
+
+
+def test_collision_read_timing_and_vblank():
+    # P0 (66-73) and P1 (66-73) meet at clocks 134-141 of every line; on the
+    # read line CXCLR (access cycle 2) clears the earlier rows' latches, then
+    # after n NOPs LDA CXPPMM (zero page, 3 cycles) reads at access cycle
+    # 2n + 5, seeing clocks up to 3(2n + 5) + 2: n = 19 -> clock 131 (none
+    # yet), n = 20 -> clock 137
+    def prog(nops, vblank=False):
+        return f"""
+reset:
+    lda #$FF
+    sta GRP0
+    sta GRP1
+    sta WSYNC
+{AT42}    sta RESP0
+    sta WSYNC
+{AT42}    sta RESP1
+frame:
+    sta WSYNC
+    lda #2
+    sta VSYNC
+    lda #0
+    sta VSYNC
+    lda #{2 if vblank else 0}
+    sta VBLANK
+    ldx #59
+lines:
+    sta WSYNC
+    dex
+    bne lines
+    sta WSYNC
+    sta CXCLR
+""" + "    nop\n" * nops + """    lda CXPPMM
+    sta $A0
+    ldx #0
+rest:
+    sta WSYNC
+    dex
+    bne rest
+    jmp frame
+"""
+    for nops, want in [(19, 0), (20, 0x80)]:
+        rom, _ = cart(prog(nops))
+        _, d = run(rom, track=True)
+        assert d["ram"][0x20] == want, nops
+    rom, _ = cart(prog(20, vblank=True))
+    _, d = run(rom, track=True)
+    assert d["ram"][0x20] == 0                     # nothing is drawn, so nothing collides, in VBLANK

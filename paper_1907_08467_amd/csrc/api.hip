@@ -200,6 +200,15 @@ void to_record(const DevEnv& e, uint8_t* out) {
     out[192] = e.prev_action;
     out[194] = e.err;
     std::memcpy(out + 200, &e.instr, 8);
+    const uint8_t* t2 = e.tia2;   // R[16..47]
+    auto R = [&](int i) { return t2[i - 16]; };
+    const uint8_t objs[19] = {R(R_NUSIZ0), R(R_NUSIZ1), R(R_ENAM0), R(R_ENAM1), R(R_ENABL), R(R_ENABL_OLD),
+                              R(R_GRP0_OLD), R(R_GRP1_OLD), R(R_VDELP0), R(R_VDELP1), R(R_VDELBL), R(R_RESMP0),
+                              R(R_RESMP1), R(R_M0X), R(R_M1X), R(R_BLX), R(R_HMM0), R(R_HMM1), R(R_HMBL)};
+    std::memcpy(out + 208, objs, 19);
+    out[227] = e.hmb_now;
+    std::memcpy(out + 228, &e.cx, 2);
+    out[230] = e.track_cx;
     std::memcpy(out + 256, e.xram, 128);
 }
 
@@ -240,6 +249,26 @@ int from_record(const uint8_t* in, DevEnv* e) {
     e->prev_action = in[192];
     e->err = in[194];
     std::memcpy(&e->instr, in + 200, 8);
+    const uint8_t* o = in + 208;
+    uint8_t* t2 = e->tia2;
+    auto W = [&](int i, uint8_t v) { t2[i - 16] = v; };
+    W(R_NUSIZ0, o[0]); W(R_NUSIZ1, o[1]); W(R_ENAM0, o[2]); W(R_ENAM1, o[3]); W(R_ENABL, o[4]);
+    W(R_ENABL_OLD, o[5]); W(R_GRP0_OLD, o[6]); W(R_GRP1_OLD, o[7]); W(R_VDELP0, o[8]); W(R_VDELP1, o[9]);
+    W(R_VDELBL, o[10]); W(R_RESMP0, o[11]); W(R_RESMP1, o[12]); W(R_M0X, o[13]); W(R_M1X, o[14]);
+    W(R_BLX, o[15]); W(R_HMM0, o[16]); W(R_HMM1, o[17]); W(R_HMBL, o[18]);
+    // the renderer's flag bits: ENAM0, ENAM1, ENABL, ENABL (delayed), RESMP0 D1; VDELP0, VDELP1, VDELBL D0
+    const uint8_t flags = (uint8_t)(((o[2] >> 1) & 1) | (((o[3] >> 1) & 1) << 1) | (((o[4] >> 1) & 1) << 2) |
+                                    (((o[5] >> 1) & 1) << 3) | ((o[8] & 1) << 4) | ((o[9] & 1) << 5) |
+                                    ((o[10] & 1) << 6) | (((o[11] >> 1) & 1) << 7));
+    W(R_FLAGS, flags);
+    W(R_FLAGS2, (uint8_t)((o[12] >> 1) & 1));
+    e->hmb_now = in[227] ? 1 : 0;
+    if (e->hmb_now) {   // the blanked line may be a row of the current frame
+        const int64_t row = (int64_t)(e->cycle / 76) - (int64_t)e->frame_line0 - kFirstRow;
+        if (row >= 0 && row < kRows) W(R_HMB, (uint8_t)(row + 1));
+    }
+    std::memcpy(&e->cx, in + 228, 2);
+    e->track_cx = in[230] ? 1 : 0;
     std::memcpy(e->xram, in + 256, 128);
     return 0;
 }

@@ -224,7 +224,7 @@ __device__ __forceinline__ uint32_t hotspot(const Wave& W, uint32_t bank, uint32
     return cart_hotspot(W.cm.a & 3, W.cm.a >> 8, (W.cm.a >> 4) & 15, bank, a);
 }
 constexpr int kRamStride = 132;   // 33 dwords: bank-conflict free for equal offsets
-constexpr int kTiaStride = 20;    // 5 dwords
+constexpr int kTiaStride = 52;    // 13 dwords (R[0..47] + 1): bank-conflict free
 
 struct Cpu {
     uint32_t a, x, y, sp, p, pc, bank;
@@ -249,6 +249,7 @@ struct Cpu {
     uint32_t open_cnt;
     uint32_t icount;
     uint32_t ucount;          // instructions executed in wave-uniform mode
+    int32_t hmb_line;         // line (relative to the base line) an early HMOVE blanked, or -1
 };
 
 __device__ __forceinline__ uint32_t nz(uint32_t p, uint32_t v) {
@@ -637,8 +638,9 @@ __device__ __forceinline__ void log_advance(Cpu& c, const Wave& W, int32_t targe
         c.open_row++;
         c.open_cnt = 0;
         const uint32_t* s = reinterpret_cast<const uint32_t*>(W.tia + c.tia_off);
-        uint4 q = make_uint4(s[0], s[1], s[2], s[3] & 0x00FFFFFFu);
-        *reinterpret_cast<uint4*>(c.log + c.open_row * kRowBytes) = q;
+        uint4* d = reinterpret_cast<uint4*>(c.log + c.open_row * kRowBytes);
+        d[0] = make_uint4(s[0], s[1], s[2], s[3] & 0x00FFFFFFu);
+        d[1] = make_uint4(s[4], s[5], s[6], s[7]);
     }
 }
 
@@ -648,7 +650,8 @@ __device__ __forceinline__ void log_entry(Cpu& c, int32_t row, uint32_t x, uint3
         c.err |= ERR_LOG;
         return;
     }
-    *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * c.open_cnt) = x | (code << 8) | (v0 << 16) | (v1 << 24);
+    *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + kSnapBytes + 4 * c.open_cnt) =
+        x | (code << 8) | (v0 << 16) | (v1 << 24);
     c.open_cnt++;
 }
 
@@ -667,15 +670,40 @@ __device__ __forceinline__ void log_event(Cpu& c, const Wave& W, uint32_t t, uin
 __device__ __forceinline__ void log_close(Cpu& c, const Wave& W, uint32_t t) {
     log_event(c, W, t, R_END, 0, 0);
     log_finalize(c);
-    for (int32_t r = c.open_row + 1; r < kRows; ++r)
-        *reinterpret_cast<uint4*>(c.log + r * kRowBytes) = make_uint4(0, 0, 0, kRowOutside << 24);
+    for (int32_t r = c.open_row + 1; r < kRows; ++r) {
+        uint4* d = reinterpret_cast<uint4*>(c.log + r * kRowBytes);
+        d[0] = make_uint4(0, 0, 0, kRowOutside << 24);
+        d[1] = make_uint4(0, 0, 0, 0);
+    }
     c.log = nullptr;
     c.slots |= 1u << c.slot;
 }
 
-// Apply one queued TIA write of `v` to register `reg` made at cycle t.
+// Position a RESPx (players, +5) or RESMx / RESBL (+4) write at cycle t sets.
+__device__ __forceinline__ uint32_t reset_pos(uint32_t t, uint32_t delay) {
+    const uint32_t h = 3 * ((t + 1) % 76);
+    return h < 68 ? delay - 2 : (h - 68 + delay) % 160;
+}
+
+// Full-byte register k (R[32 + k]) shows in R_FLAGS bit k (R_FLAGS2 bit 0
+// for k = 8): ENAM0, ENAM1, ENABL, ENABL (delayed), RESMP0, RESMP1 by D1,
+// VDELP0, VDELP1, VDELBL by D0.  The flags byte a write of v makes:
+__device__ __forceinline__ uint32_t flags_after(const uint8_t* R, uint32_t k, uint32_t v) {
+    const uint32_t bit = (k >= 4 && k <= 6) ? (v & 1) : ((v >> 1) & 1);
+    return k == 8 ? bit : (R[R_FLAGS] & ~(1u << k)) | (bit << k);
+}
+__device__ __forceinline__ void set_flag_reg(uint8_t* R, uint32_t k, uint32_t v, uint32_t flags) {
+    R[R_ENAM0 + k] = (uint8_t)v;
+    R[k == 8 ? R_FLAGS2 : R_FLAGS] = (uint8_t)flags;
+}
+
+__device__ __forceinline__ int32_t hm_delta(uint32_t hm) { return sext8(hm & 0xF0) >> 4; }
+
+// Apply one queued TIA write of `v` to register `reg` made at cycle t: the
+// row-log entries of what it changes for the renderer, then the registers.
 __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, uint32_t v, uint32_t t) {
     uint8_t* R = W.tia + c.tia_off;
+    const bool lg = c.log != nullptr;
     switch (reg) {
     case 0x00:
         if ((v & 2) && !(c.vsync & 2)) c.ev |= EV_VSYNC;
@@ -684,33 +712,83 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, u
     case 0x02: c.ev |= EV_WSYNC; return;
     case 0x20: c.hmp0 = v; return;
     case 0x21: c.hmp1 = v; return;
-    case 0x2B: c.hmp0 = 0; c.hmp1 = 0; return;
+    case 0x22: case 0x23: case 0x24: R[R_HMM0 + reg - 0x22] = (uint8_t)v; return;
+    case 0x2B: c.hmp0 = 0; c.hmp1 = 0; R[R_HMM0] = R[R_HMM1] = R[R_HMBL] = 0; return;
+    case 0x1B:                                  // GRP0; GRP1 to its delayed copy
+        if (lg) log_event(c, W, t, R_GRP0, v, 0);
+        R[R_GRP1_OLD] = R[R_GRP1];
+        R[R_GRP0] = (uint8_t)v;
+        return;
+    case 0x1C:                                  // GRP1; GRP0 and ENABL to their delayed copies
+        if (lg) log_event(c, W, t, R_GRP1, v, 0);
+        R[R_GRP0_OLD] = R[R_GRP0];
+        R[R_GRP1] = (uint8_t)v;
+        R[R_ENABL_OLD] = R[R_ENABL];
+        R[R_FLAGS] = (uint8_t)((R[R_FLAGS] & ~8u) | ((R[R_FLAGS] & 4u) << 1));
+        return;
+    case 0x1D: case 0x1E: case 0x1F: case 0x25: case 0x26: case 0x27: {
+        // (every entry is logged before the registers change: logging first
+        // takes the snapshots of the rows before the write)
+        const uint32_t k = reg <= 0x1F ? reg - 0x1D : reg - 0x25 + 4;
+        const uint32_t fl = flags_after(R, k, v);
+        if (lg) log_event(c, W, t, R_FLAGS, fl, 0);
+        set_flag_reg(R, k, v, fl);
+        return;
+    }
+    case 0x28: case 0x29: {                     // RESMP: the release puts the missile at the player's centre
+        const uint32_t i = reg - 0x28;
+        const uint32_t was = (R[R_RESMP0 + i] >> 1) & 1;
+        const uint32_t fl = flags_after(R, 7 + i, v);
+        const bool release = !(v & 2) && was;
+        const uint32_t mode = R[R_NUSIZ0 + i] & 7;
+        const uint32_t pos = (R[R_P0X + i] + (mode == 5 ? 6u : mode == 7 ? 10u : 3u)) % 160;
+        if (lg) {
+            if (release) log_event(c, W, t, R_M0X + i, pos, 0);
+            log_event(c, W, t, i ? R_FLAGS2 : R_FLAGS, fl, 0);
+        }
+        if (release) R[R_M0X + i] = (uint8_t)pos;
+        set_flag_reg(R, 7 + i, v, fl);
+        return;
+    }
+    case 0x2A: {                                // HMOVE: every object by its motion nibble, now
+        const uint32_t p0 = (uint32_t)(((int32_t)R[R_P0X] - hm_delta(c.hmp0) + 160) % 160);
+        const uint32_t p1 = (uint32_t)(((int32_t)R[R_P1X] - hm_delta(c.hmp1) + 160) % 160);
+        const uint32_t m0 = (uint32_t)(((int32_t)R[R_M0X] - hm_delta(R[R_HMM0]) + 160) % 160);
+        const uint32_t m1 = (uint32_t)(((int32_t)R[R_M1X] - hm_delta(R[R_HMM1]) + 160) % 160);
+        const uint32_t bl = (uint32_t)(((int32_t)R[R_BLX] - hm_delta(R[R_HMBL]) + 160) % 160);
+        const uint32_t ln = (t + 1) / 76, h = 3 * (t + 1 - 76 * ln);
+        if (lg) {
+            log_event(c, W, t, R_HMOVE, p0, p1);
+            log_event(c, W, t, R_M0X, m0, 0);
+            log_event(c, W, t, R_M1X, m1, 0);
+            log_event(c, W, t, R_BLX, bl, 0);
+        }
+        R[R_P0X] = (uint8_t)p0; R[R_P1X] = (uint8_t)p1;
+        R[R_M0X] = (uint8_t)m0; R[R_M1X] = (uint8_t)m1; R[R_BLX] = (uint8_t)bl;
+        if (h < 68) {                           // written in the horizontal blank: pixels 0-7 of the line blank
+            c.hmb_line = (int32_t)ln;
+            const int32_t row = (int32_t)ln - c.fl - kFirstRow;
+            if (row >= 0 && row < kRows) R[R_HMB] = (uint8_t)(row + 1);
+        }
+        return;
+    }
     default: break;
     }
-    uint32_t code, v0 = v, v1 = 0;
+    uint32_t code, v0 = v;
     if (reg >= 0x06 && reg <= 0x0F) code = reg - 0x06;
     else if (reg == 0x01) code = R_VBLANK;
-    else if (reg == 0x1B) code = R_GRP0;
-    else if (reg == 0x1C) code = R_GRP1;
+    else if (reg == 0x04 || reg == 0x05) code = R_NUSIZ0 + (reg - 0x04);
     else if (reg == 0x10 || reg == 0x11) {
-        const uint32_t h = 3 * ((t + 1) % 76);
-        code = reg == 0x10 ? R_P0X : R_P1X;
-        v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
-    } else if (reg == 0x2A) {
-        code = R_HMOVE;
-        const int32_t d0 = sext8(c.hmp0 & 0xF0) >> 4, d1 = sext8(c.hmp1 & 0xF0) >> 4;
-        v0 = (uint32_t)(((int32_t)R[R_P0X] - d0 + 160) % 160);
-        v1 = (uint32_t)(((int32_t)R[R_P1X] - d1 + 160) % 160);
+        code = R_P0X + (reg - 0x10);
+        v0 = reset_pos(t, 5);
+    } else if (reg >= 0x12 && reg <= 0x14) {
+        code = R_M0X + (reg - 0x12);
+        v0 = reset_pos(t, 4);
     } else {
-        return;   // audio, missiles, ball, NUSIZ, VDEL, ... are not rendered
+        return;   // audio and the rest: no emulated effect
     }
-    if (c.log) log_event(c, W, t, code, v0, v1);
-    if (code == R_HMOVE) {
-        R[R_P0X] = (uint8_t)v0;
-        R[R_P1X] = (uint8_t)v1;
-    } else {
-        R[code] = (uint8_t)v0;
-    }
+    if (lg) log_event(c, W, t, code, v0, 0);
+    R[code] = (uint8_t)v0;
 }
 
 __device__ __forceinline__ void apply_queue(Cpu& c, const Wave& W, uint32_t t) {
@@ -748,15 +826,18 @@ struct Fast {
 __device__ __forceinline__ bool all_lanes(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
 
 // Stores the scalar path leaves to the per-lane path: VSYNC (it may end the
-// frame), the horizontal-motion registers, HMOVE, and timer writes.  They
-// are rare, and keeping them out leaves the per-lane VSYNC, motion and timer
-// state untouched inside the scalar loop.
+// frame), the motion registers, HMOVE, HMCLR, RESMP, CXCLR, the missile and
+// ball registers, NUSIZ, VDEL, and timer writes.  Keeping them out leaves
+// the per-lane VSYNC, motion, collision and timer state untouched inside the
+// scalar loop and its store code short.
+__device__ __forceinline__ bool tia_exit_reg(uint32_t reg) {
+    return reg == 0x00 || (reg >= 0x20 && reg <= 0x24) || reg == 0x28 || reg == 0x29 || reg == 0x2A || reg == 0x2B ||
+           reg == 0x2C || reg == 0x04 || reg == 0x05 || (reg >= 0x12 && reg <= 0x14) || (reg >= 0x1D && reg <= 0x1F) ||
+           (reg >= 0x25 && reg <= 0x27);
+}
 __device__ __forceinline__ uint32_t fast_store_ok(uint32_t a) {
     if (a & 0x1000) return 1;                             // cartridge: bank hotspots only
-    if (!(a & 0x80)) {                                    // TIA
-        const uint32_t reg = a & 0x3F;
-        return (reg != 0x00 && reg != 0x20 && reg != 0x21 && reg != 0x2A && reg != 0x2B) ? 1u : 0u;
-    }
+    if (!(a & 0x80)) return tia_exit_reg(a & 0x3F) ? 0u : 1u;   // TIA
     if (!(a & 0x200)) return 1;                           // RAM
     return (a & 0x14) != 0x14 ? 1u : 0u;                  // RIOT: everything but the timer
 }
@@ -768,38 +849,47 @@ constexpr uint32_t SC_RAM = 0, SC_WSYNC = 1, SC_IGNORE = 2, SC_EXIT = 3, SC_CART
 // Superchip RAM window, and a 3F slice-select store to an ignored TIA register
 constexpr uint32_t SC_XRAM = 5, SC_3F = 6;
 
-// Class of a store to a (13 bits): RAM, WSYNC, a rendered TIA register (SC_TIA
-// | register code), a write that changes nothing emulated, a cartridge access,
-// or one the scalar path leaves to the per-lane path (fast_store_ok).
+// Class of a store to a (13 bits): RAM, WSYNC, a TIA register the scalar path
+// writes (SC_TIA | its R index), a write that changes nothing emulated, a
+// cartridge access, or one the scalar path leaves to the per-lane path
+// (fast_store_ok).
 __device__ __forceinline__ uint32_t store_class(uint32_t a) {
     if (a & 0x1000) return SC_CART;
     if (!(a & 0x80)) {
         const uint32_t reg = a & 0x3F;
         if (reg == 0x02) return SC_WSYNC;
-        if (reg == 0x00 || reg == 0x20 || reg == 0x21 || reg == 0x2A || reg == 0x2B) return SC_EXIT;
+        if (tia_exit_reg(reg)) return SC_EXIT;
         if (reg >= 0x06 && reg <= 0x0F) return SC_TIA | (reg - 0x06);
         if (reg == 0x01) return SC_TIA | R_VBLANK;
         if (reg == 0x1B) return SC_TIA | R_GRP0;
         if (reg == 0x1C) return SC_TIA | R_GRP1;
-        if (reg == 0x10) return SC_TIA | R_P0X;
-        if (reg == 0x11) return SC_TIA | R_P1X;
-        return SC_IGNORE;   // audio, missiles, ball, NUSIZ, VDEL, ... are not rendered
+        if (reg == 0x10 || reg == 0x11) return SC_TIA | (R_P0X + reg - 0x10);
+        if (reg == 0x04 || reg == 0x05 || (reg >= 0x12 && reg <= 0x14) || (reg >= 0x1D && reg <= 0x1F) ||
+            (reg >= 0x25 && reg <= 0x27))
+            return SC_EXIT;   // NUSIZ, RESM, RESBL, ENAM, ENABL, VDEL: the per-lane path
+        return SC_IGNORE;   // audio and the rest
     }
     if (!(a & 0x200)) return SC_RAM;
     return (a & 0x14) == 0x14 ? SC_EXIT : SC_IGNORE;
 }
 
-// Write of per-lane value v to the rendered TIA register `code` at scalar
-// cycle t, with its row-log entry.  Returns 0, before changing anything,
-// when the row-log entry would not fit (the per-lane path then records the
-// error).
-__device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F, uint32_t code, uint32_t v,
+// Write of per-lane value v to TIA register class `sc` (SC_TIA | code) at
+// scalar cycle t, with its row-log entry.  The scalar path takes the colour,
+// playfield, control, reflection and VBLANK registers, RESP0/1 and the
+// players' graphics; the other object registers (ENAM, ENABL, VDEL, NUSIZ, RESM,
+// RESBL) go to the per-lane path, which keeps this, inlined at every store,
+// short.  A GRP0 / GRP1 entry also stands for the copy to the delayed
+// registers (the other player's graphics; with GRP1, ENABL), which the
+// renderer repeats from its own state.  Returns 0, before changing anything,
+// when the row's entries are full (the per-lane path then records the error).
+__device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F, uint32_t sc, uint32_t v,
                                                   uint32_t t) {
     const uint32_t ln = (t + 1) / 76;
     const uint32_t h = 3 * (t + 1 - 76 * ln);
+    uint8_t* R = W.tia + c.tia_off;
+    const uint32_t code = sc & 0x1F;
     uint32_t v0 = v;
     if (code == R_P0X || code == R_P1X) v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
-    uint8_t* R = W.tia + c.tia_off;
     if (F.logon) {
         // rows before the one the write lands in (its own row too when the
         // write lands in the visible part) get their snapshots first
@@ -812,9 +902,12 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
                 if (F.ocnt) c.log[(F.orow - 1) * kRowBytes + 15] = (uint8_t)F.ocnt;
             }
             const uint32_t* src = reinterpret_cast<const uint32_t*>(R);
-            const uint4 snap = make_uint4(src[0], src[1], src[2], src[3] & 0x00FFFFFFu);
+            const uint4 snap0 = make_uint4(src[0], src[1], src[2], src[3] & 0x00FFFFFFu);
+            const uint4 snap1 = make_uint4(src[4], src[5], src[6], src[7]);
             do {    // F.orow holds the open row + 1 (0 = none)
-                *reinterpret_cast<uint4*>(c.log + F.orow * kRowBytes) = snap;
+                uint4* d = reinterpret_cast<uint4*>(c.log + F.orow * kRowBytes);
+                d[0] = snap0;
+                d[1] = snap1;
                 F.orow++;
             } while ((int32_t)F.orow <= target);
             F.ocnt = 0;
@@ -823,11 +916,18 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
             if ((uint32_t)row < (uint32_t)kRows) {
                 // the row is the open one here; a full row is left to the per-lane path
                 if (F.ocnt >= (uint32_t)kRowEntries) return 0;
-                *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + 16 + 4 * F.ocnt) =
+                *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + kSnapBytes + 4 * F.ocnt) =
                     (h - 68) | (code << 8) | (v0 << 16);
                 F.ocnt++;
             }
         }
+    }
+    if (code == R_GRP0) {
+        R[R_GRP1_OLD] = R[R_GRP1];
+    } else if (code == R_GRP1) {
+        R[R_GRP0_OLD] = R[R_GRP0];
+        R[R_ENABL_OLD] = R[R_ENABL];
+        R[R_FLAGS] = (uint8_t)((R[R_FLAGS] & ~8u) | ((R[R_FLAGS] & 4u) << 1));
     }
     R[code] = (uint8_t)v0;
     return 1;
@@ -844,7 +944,7 @@ __device__ __forceinline__ uint32_t fast_tia(Cpu& c, const Wave& W, Fast& F, uin
         return 1;
     }
     if (sc < SC_TIA) return 1;
-    return fast_tia_code(c, W, F, sc & 0x1F, v, t);
+    return fast_tia_code(c, W, F, sc, v, t);
 }
 
 // Read of scalar address a (13 bits) at scalar cycle t.
@@ -1098,7 +1198,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             if (aux == SC_RAM) {
                 W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
             } else if (aux >= SC_TIA) {
-                if (!fast_tia_code(c, W, F, aux & 0x1F, v & 0xFF, t)) return FS_EXIT;
+                if (!fast_tia_code(c, W, F, aux, v & 0xFF, t)) return FS_EXIT;
             } else if (aux == SC_WSYNC) {
                 return fast_finish(F, next, t, 1);
             } else if (aux == SC_EXIT) {
@@ -1390,8 +1490,14 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
             }
             const uint4 qt = reinterpret_cast<const uint4*>(E->tia)[0];
+            const uint4* q2 = reinterpret_cast<const uint4*>(E->tia2);
             uint32_t* dt = s_tia + (c.tia_off >> 2);
-            dt[0] = qt.x; dt[1] = qt.y; dt[2] = qt.z; dt[3] = qt.w; dt[4] = 0;
+            dt[0] = qt.x; dt[1] = qt.y; dt[2] = qt.z; dt[3] = qt.w;
+            for (int i = 0; i < 2; ++i) {
+                const uint4 q = q2[i];
+                dt[4 + 4 * i] = q.x; dt[5 + 4 * i] = q.y; dt[6 + 4 * i] = q.z; dt[7 + 4 * i] = q.w;
+            }
+            dt[12] = 0;
             c.a = E->a; c.x = E->x; c.y = E->y; c.sp = E->sp; c.p = E->p;
             c.bank = E->bank | ((uint32_t)E->bank_hi << 8);
             c.xram = E->xram;
@@ -1402,6 +1508,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             base_line = cyc / 76;
             c.cyc = (uint32_t)(cyc - base_line * 76);
             c.fl = (int32_t)((int64_t)E->frame_line0 - (int64_t)base_line);
+            c.hmb_line = E->hmb_now ? 0 : -1;     // the line of `cycle` is the base line
             prev_action = E->prev_action;
             step_idx = E->step_idx;
             c.err = E->err;
@@ -1441,6 +1548,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             c.slot = (uint32_t)slot;
             c.open_row = -1;
             c.open_cnt = 0;
+            W.tia[c.tia_off + R_HMB] = 0;          // an earlier frame's blanked row is not this frame's
         };
 
         if (active) {
@@ -1571,6 +1679,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             for (int i = 0; i < 8; ++i) dst[i] = make_uint4(sr[4 * i], sr[4 * i + 1], sr[4 * i + 2], sr[4 * i + 3]);
             const uint32_t* st = s_tia + (c.tia_off >> 2);
             reinterpret_cast<uint4*>(E->tia)[0] = make_uint4(st[0], st[1], st[2], st[3]);
+            reinterpret_cast<uint4*>(E->tia2)[0] = make_uint4(st[4], st[5], st[6], st[7]);
+            reinterpret_cast<uint4*>(E->tia2)[1] = make_uint4(st[8], st[9], st[10], st[11]);
+            E->hmb_now = c.hmb_line >= 0 && (uint32_t)c.hmb_line == c.cyc / 76 ? 1 : 0;
             E->a = c.a; E->x = c.x; E->y = c.y; E->sp = c.sp; E->p = c.p;
             E->bank = (uint8_t)c.bank;
             E->bank_hi = (uint8_t)(c.bank >> 8);

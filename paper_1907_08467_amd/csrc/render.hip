@@ -8,65 +8,20 @@
 // thread draws a 16-pixel segment of one row from the row's snapshot and the
 // writes logged inside it.
 //
-// Pixel rule (TIA register semantics): VBLANK bit 1 or a pixel outside the
-// frame -> 0; playfield bit p of the 20-bit sequence PF0 D4..D7, PF1 D7..D0,
-// PF2 D0..D7 with p = x/4 on the left half and, on the right half,
-// (x-80)/4 or (reflect) 19-(x-80)/4; player i covers x = pos..pos+7 (mod 160)
-// with bit 7-d of GRPi (bit d when REFPi D3 is set); the playfield colour is
-// COLUPF, or in score mode COLUP0/COLUP1 by half; priority P0 > P1 > PF > BK,
-// or PF > P0 > P1 > BK with CTRLPF D2; the stored value is the colour & $FE.
+// Pixel rule (TIA register semantics; the objects as in tia_draw.h): VBLANK
+// D1, an early HMOVE's blank (pixels 0-7) or a pixel outside the frame -> 0;
+// priority P0/M0 > P1/M1 > PF/BL > BK, or PF/BL > P0/M0 > P1/M1 > BK with
+// CTRLPF D2; P0 and M0 in COLUP0, P1 and M1 in COLUP1, the ball in COLUPF,
+// the playfield in COLUPF or, in score mode, COLUP0 / COLUP1 by half; the
+// stored value is the colour & $FE.
 //
 // Observation: gray = lut[colour >> 1]; m = max over the two frames;
 // obs[i][j] = floor((sum_r sum_c wr*wc*m[r][c] + 100) / 200), the exact-area
 // average of 210x160 -> 84x84 with row weights in half rows (2,2,1 / 1,2,2)
 // and column weights |[40j, 40j+40) & [21c, 21c+21)|, rounded half up.
-#include "vcs_device.h"
+#include "tia_draw.h"
 
 namespace vcs {
-
-
-
-struct Regs {
-    uint32_t colup0, colup1, colupf, colubk, ctrlpf, refp0, refp1, pf0, pf1, pf2, grp0, grp1, p0x, p1x, vblank;
-    uint32_t pfm;             // playfield bits 0..19
-    bool outside;
-};
-
-__device__ __forceinline__ uint32_t pf_mask(uint32_t pf0, uint32_t pf1, uint32_t pf2) {
-    return ((pf0 >> 4) & 0xF) | ((__builtin_bitreverse32(pf1) >> 24) << 4) | ((pf2 & 0xFF) << 12);
-}
-
-__device__ __forceinline__ void unpack(Regs& r, uint4 s) {
-    r.colup0 = s.x & 0xFF; r.colup1 = (s.x >> 8) & 0xFF; r.colupf = (s.x >> 16) & 0xFF; r.colubk = s.x >> 24;
-    r.ctrlpf = s.y & 0xFF; r.refp0 = (s.y >> 8) & 0xFF; r.refp1 = (s.y >> 16) & 0xFF; r.pf0 = s.y >> 24;
-    r.pf1 = s.z & 0xFF; r.pf2 = (s.z >> 8) & 0xFF; r.grp0 = (s.z >> 16) & 0xFF; r.grp1 = s.z >> 24;
-    r.p0x = s.w & 0xFF; r.p1x = (s.w >> 8) & 0xFF; r.vblank = (s.w >> 16) & 0xFF;
-    r.outside = ((s.w >> 24) & kRowOutside) != 0;
-    r.pfm = pf_mask(r.pf0, r.pf1, r.pf2);
-}
-
-__device__ __forceinline__ void apply(Regs& r, uint32_t e) {
-    const uint32_t code = (e >> 8) & 0xFF, v0 = (e >> 16) & 0xFF, v1 = e >> 24;
-    switch (code) {
-    case R_COLUP0: r.colup0 = v0; break;
-    case R_COLUP1: r.colup1 = v0; break;
-    case R_COLUPF: r.colupf = v0; break;
-    case R_COLUBK: r.colubk = v0; break;
-    case R_CTRLPF: r.ctrlpf = v0; break;
-    case R_REFP0: r.refp0 = v0; break;
-    case R_REFP1: r.refp1 = v0; break;
-    case R_PF0: r.pf0 = v0; r.pfm = pf_mask(r.pf0, r.pf1, r.pf2); break;
-    case R_PF1: r.pf1 = v0; r.pfm = pf_mask(r.pf0, r.pf1, r.pf2); break;
-    case R_PF2: r.pf2 = v0; r.pfm = pf_mask(r.pf0, r.pf1, r.pf2); break;
-    case R_GRP0: r.grp0 = v0; break;
-    case R_GRP1: r.grp1 = v0; break;
-    case R_P0X: r.p0x = v0; break;
-    case R_P1X: r.p1x = v0; break;
-    case R_VBLANK: r.vblank = v0; break;
-    case R_HMOVE: r.p0x = v0; r.p1x = v1; break;
-    default: r.outside = true; break;   // R_END
-    }
-}
 
 // Segments are drawn 16 pixels at a time with bit masks: a 16-bit mask per
 // object (bit i = pixel x0 + i), widened to byte masks and combined with one
@@ -76,42 +31,28 @@ __device__ __forceinline__ void apply(Regs& r, uint32_t e) {
 // four mask bits -> four byte masks (bit j -> 0xFF in byte j)
 __device__ __forceinline__ uint32_t byte_masks(uint32_t n) { return ((n * 0x00204081u) & 0x01010101u) * 0xFFu; }
 
-__device__ __forceinline__ uint32_t rev4(uint32_t n) {
-    return ((n & 1) << 3) | ((n & 2) << 1) | ((n & 4) >> 1) | ((n & 8) >> 3);
-}
-
 // (m & a) | (~m & b)
 __device__ __forceinline__ uint32_t pick(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
 
-// pixels of player (pos, grp, refp) among x0 .. x0+15: the sprite's pixel d
-// (0..7) sits at x = pos + d (mod 160) and shows bit d of GRP when reflected,
-// bit 7-d otherwise
-__device__ __forceinline__ uint32_t player_mask16(uint32_t pos, uint32_t grp, uint32_t refp, uint32_t x0) {
-    const uint32_t spr = (refp & 8) ? grp : (__builtin_bitreverse32(grp) >> 24);
-    uint32_t r = pos + 160 - x0;          // (pos - x0) mod 160
-    if (r >= 160) r -= 160;
-    uint32_t m = 0;
-    if (r < 16) m = spr << r;
-    if (r > 152) m |= spr >> (160 - r);
-    return m & 0xFFFF;
-}
-
-// the 16 pixels x0 .. x0+15 drawn with registers r (x0 a multiple of 16, so
-// the segment lies in one half of the line)
-__device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0) {
-    if (r.outside || (r.vblank & 2)) return make_uint4(0, 0, 0, 0);
+// the 16 pixels of the common case: one copy of each player at normal width,
+// no missile, no ball, no vertical delay, no HMOVE blank
+__device__ __forceinline__ uint4 draw16_plain(const Regs& r, uint32_t x0) {
+    if (r.outside || (rb<R_VBLANK>(r) & 2)) return make_uint4(0, 0, 0, 0);
     const bool right = x0 >= 80;
+    const uint32_t ctrlpf = rb<R_CTRLPF>(r);
     uint32_t n;
     if (!right) n = (r.pfm >> (x0 >> 2)) & 0xF;
-    else if (!(r.ctrlpf & 1)) n = (r.pfm >> ((x0 - 80) >> 2)) & 0xF;
+    else if (!(ctrlpf & 1)) n = (r.pfm >> ((x0 - 80) >> 2)) & 0xF;
     else n = rev4((r.pfm >> (16 - ((x0 - 80) >> 2))) & 0xF);
     const uint32_t mpf = ((n & 1) | ((n & 2) << 3) | ((n & 4) << 6) | ((n & 8) << 9)) * 0xF;
-    const uint32_t m0 = player_mask16(r.p0x, r.grp0, r.refp0, x0);
-    const uint32_t m1 = player_mask16(r.p1x, r.grp1, r.refp1, x0);
-    const uint32_t pfc = (r.ctrlpf & 2) ? (right ? r.colup1 : r.colup0) : r.colupf;
-    const uint32_t c0 = (r.colup0 & 0xFE) * 0x01010101u, c1 = (r.colup1 & 0xFE) * 0x01010101u;
-    const uint32_t cp = (pfc & 0xFE) * 0x01010101u, cb = (r.colubk & 0xFE) * 0x01010101u;
-    const bool pf_first = (r.ctrlpf & 4) != 0;
+    const uint32_t g0 = rb<R_GRP0>(r), g1 = rb<R_GRP1>(r);
+    const uint32_t s0 = (rb<R_REFP0>(r) & 8) ? g0 : (__builtin_bitreverse32(g0) >> 24);
+    const uint32_t s1 = (rb<R_REFP1>(r) & 8) ? g1 : (__builtin_bitreverse32(g1) >> 24);
+    const uint32_t m0 = window16s(s0, 8, rb<R_P0X>(r), x0), m1 = window16s(s1, 8, rb<R_P1X>(r), x0);
+    const uint32_t pfc = (ctrlpf & 2) ? (right ? rb<R_COLUP1>(r) : rb<R_COLUP0>(r)) : rb<R_COLUPF>(r);
+    const uint32_t c0 = (rb<R_COLUP0>(r) & 0xFE) * 0x01010101u, c1 = (rb<R_COLUP1>(r) & 0xFE) * 0x01010101u;
+    const uint32_t cp = (pfc & 0xFE) * 0x01010101u, cb = (rb<R_COLUBK>(r) & 0xFE) * 0x01010101u;
+    const bool pf_first = (ctrlpf & 4) != 0;
     uint32_t w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -122,15 +63,45 @@ __device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0) {
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// the 16 pixels x0 .. x0+15 of row `row` drawn with registers r
+__device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0, uint32_t row) {
+    // ENAM0/1, ENABL and its copy, the VDEL bits clear, both NUSIZ modes 0, no blank
+    if (!(rb<R_FLAGS>(r) & 0x7F) && !((rb<R_NUSIZ0>(r) | rb<R_NUSIZ1>(r)) & 7) && rb<R_HMB>(r) == 0)
+        return draw16_plain(r, x0);
+    uint32_t o[6], shown;
+    objects16(r, x0, row, o, shown);
+    if (!shown) return make_uint4(0, 0, 0, 0);
+    const bool right = x0 >= 80;
+    const uint32_t ctrlpf = rb<R_CTRLPF>(r);
+    const uint32_t pfc = (ctrlpf & 2) ? (right ? rb<R_COLUP1>(r) : rb<R_COLUP0>(r)) : rb<R_COLUPF>(r);
+    const uint32_t c0 = (rb<R_COLUP0>(r) & 0xFE) * 0x01010101u, c1 = (rb<R_COLUP1>(r) & 0xFE) * 0x01010101u;
+    const uint32_t cp = (pfc & 0xFE) * 0x01010101u, cf = (rb<R_COLUPF>(r) & 0xFE) * 0x01010101u;
+    const uint32_t cb = (rb<R_COLUBK>(r) & 0xFE) * 0x01010101u;
+    const uint32_t m0 = o[2] | o[4], m1 = o[3] | o[5], mf = o[0] | o[1];   // P0/M0, P1/M1, PF/BL
+    const bool pf_first = (ctrlpf & 4) != 0;
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t b0 = byte_masks((m0 >> (4 * k)) & 0xF), b1 = byte_masks((m1 >> (4 * k)) & 0xF);
+        const uint32_t bf = byte_masks((mf >> (4 * k)) & 0xF), bp = byte_masks((o[0] >> (4 * k)) & 0xF);
+        const uint32_t cfl = pick(bp, cp, cf);   // the playfield's colour where it is set, else the ball's
+        const uint32_t v = pf_first ? pick(bf, cfl, pick(b0, c0, pick(b1, c1, cb)))
+                                    : pick(b0, c0, pick(b1, c1, pick(bf, cfl, cb)));
+        w[k] = v & byte_masks((shown >> (4 * k)) & 0xF);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // 16 pixels of row `row` starting at x0, packed little-endian into a uint4:
 // the row snapshot, then each logged write from its x position on
 __device__ __forceinline__ uint4 render_segment(const uint8_t* frame_log, int row, uint32_t x0) {
     const uint8_t* rec = frame_log + row * kRowBytes;
     const uint4 s = *reinterpret_cast<const uint4*>(rec);
+    const uint4 s2 = *reinterpret_cast<const uint4*>(rec + 16);
     Regs r;
-    unpack(r, s);
+    unpack(r, s, s2);
     const uint32_t cnt = (s.w >> 24) & 0x1F;
-    const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + 16);
+    const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + kSnapBytes);
     if (r.outside && cnt == 0) return make_uint4(0, 0, 0, 0);
     uint32_t ei = 0;
     uint32_t e = cnt ? ents[0] : 0;
@@ -144,7 +115,7 @@ __device__ __forceinline__ uint4 render_segment(const uint8_t* frame_log, int ro
     for (;;) {
         const bool more = ei < cnt && (e & 0xFF) < x0 + 16;
         const uint32_t end = more ? (e & 0xFF) - x0 : 16;
-        const uint4 px = draw16(r, x0);
+        const uint4 px = draw16(r, x0, (uint32_t)row);
         const uint32_t run = ((1u << end) - 1) & ~((1u << start) - 1);
         out.x = pick(byte_masks(run & 0xF), px.x, out.x);
         out.y = pick(byte_masks((run >> 4) & 0xF), px.y, out.y);

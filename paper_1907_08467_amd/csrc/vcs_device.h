@@ -23,14 +23,30 @@ constexpr int kObs = 84;
 constexpr int kObsBytes = kObs * kObs;
 constexpr int kFrameBytes = kRows * kCols;
 constexpr int kRowEntries = 24;        // max register writes inside one row's visible part
-constexpr int kRowBytes = 16 + 4 * kRowEntries;   // snapshot + entries = 112
-constexpr int kFrameLogBytes = kRows * kRowBytes; // 23,520
+constexpr int kSnapBytes = 32;         // row snapshot: the render registers R[0..31]
+constexpr int kRowBytes = kSnapBytes + 4 * kRowEntries;   // snapshot + entries = 128
+constexpr int kFrameLogBytes = kRows * kRowBytes;         // 26,880
+constexpr int kTiaRegs = 48;           // render registers + full-byte copies (R[0..47])
 constexpr int kRomSlot = 32768;        // bytes per ROM slot (smaller ROMs use its start)
 
-// render register order inside a snapshot (TIA $06..$0F map to 0..9)
+// TIA register file R[0..47] of an env, in snapshot order (TIA $06..$0F map
+// to 0..9).  Bytes 0..31 are what a row snapshot records and a log entry's
+// code names; 32..47 hold the last byte written to the registers the
+// renderer sees only through the flag bits of R_FLAGS / R_FLAGS2.
 enum : int {
     R_COLUP0 = 0, R_COLUP1, R_COLUPF, R_COLUBK, R_CTRLPF, R_REFP0, R_REFP1, R_PF0, R_PF1, R_PF2,
-    R_GRP0 = 10, R_GRP1 = 11, R_P0X = 12, R_P1X = 13, R_VBLANK = 14, R_HMOVE = 15, R_END = 16
+    R_GRP0 = 10, R_GRP1 = 11, R_P0X = 12, R_P1X = 13, R_VBLANK = 14,
+    R_COUNT = 15,            // snapshot only: entries in the row, kRowOutside
+    R_GRP0_OLD = 16, R_GRP1_OLD = 17, R_NUSIZ0 = 18, R_NUSIZ1 = 19, R_M0X = 20, R_M1X = 21, R_BLX = 22,
+    R_FLAGS = 23,            // ENAM0 D1, ENAM1 D1, ENABL D1, ENABL (delayed) D1, VDELP0 D0, VDELP1 D0, VDELBL D0, RESMP0 D1
+    R_FLAGS2 = 24,           // RESMP1 D1 in bit 0
+    R_HMB = 25,              // 1 + the frame row whose pixels 0-7 an early HMOVE blanked (0 = none)
+    // full bytes, in R_FLAGS bit order, then RESMP1 and the motion registers of missiles and ball
+    R_ENAM0 = 32, R_ENAM1, R_ENABL, R_ENABL_OLD, R_VDELP0, R_VDELP1, R_VDELBL, R_RESMP0, R_RESMP1,
+    R_HMM0 = 41, R_HMM1, R_HMBL,
+    // entry-only codes
+    R_HMOVE = 26,            // v0, v1: new P0 and P1 positions (M0, M1, BL follow as position entries)
+    R_END = 27
 };
 // snapshot byte 15: number of entries in the row, bit 7 = row outside the frame
 constexpr uint32_t kRowOutside = 0x80;
@@ -40,7 +56,7 @@ constexpr uint32_t ERR_ILLEGAL = 1, ERR_FRAME_CAP = 2, ERR_BAD_ACTION = 4, ERR_B
 
 struct alignas(16) DevEnv {
     uint8_t ram[128];        //   0  RAM $80..$FF
-    uint8_t tia[16];         // 128  render registers (snapshot order); [15] = 0
+    uint8_t tia[16];         // 128  render registers R[0..15]; [15] = 0
     uint8_t a, x, y, sp;     // 144
     uint8_t p, bank, vsync, hmp0;              // 148  bank: bank state bits 0-7
     uint8_t hmp1, tv, tshift, prev_action;     // 152  timer value / log2 interval
@@ -51,7 +67,11 @@ struct alignas(16) DevEnv {
     int64_t tbase;           // 176  first cycle at which the last timer write is visible
     uint64_t instr;          // 184  instructions executed
     uint32_t rom_id, step_idx, episode_idx, pad1;   // 192
-    uint8_t reserved[48];    // 208
+    uint8_t tia2[32];        // 208  R[16..47]
+    uint16_t cx;             // 240  collision latches (bit 2r+1 / 2r = D7 / D6 of CX register r)
+    uint8_t track_cx;        // 242  collision latches tracked
+    uint8_t hmb_now;         // 243  an early HMOVE blanked pixels 0-7 of the line of `cycle`
+    uint8_t reserved[12];    // 244
     uint8_t xram[128];       // 256  Superchip RAM
 };
 static_assert(sizeof(DevEnv) == 384, "DevEnv is 384 bytes");

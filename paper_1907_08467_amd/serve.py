@@ -32,7 +32,7 @@ import numpy as np
 
 # device bytes one in-flight env-step needs on a pipeline: row logs, obs,
 # reward, done, step info, id validity, its share of a tile
-LOG_BYTES = 210 * 112
+LOG_BYTES = 210 * 128
 OBS_BYTES = 84 * 84
 
 
@@ -41,7 +41,9 @@ def slot_bytes(n_slots):
 
 
 def resident_bytes(num_envs, n_roms, cache_k=30):
-    return num_envs * (256 + 2 + 4) + n_roms * cache_k * (256 + OBS_BYTES) + n_roms * 8192 * 9
+    # env records, ROM ids and tile entries; reset caches; 32 KB ROM slots and
+    # the predecoded words of up to 8 banks of 4 KB (E0 cartridges take 8 MB)
+    return num_envs * (384 + 2 + 4) + n_roms * cache_k * (384 + OBS_BYTES) + n_roms * (32768 + 8 * 4096 * 4)
 
 
 def slots_for_budget(budget_bytes, num_envs, n_roms, n_slots, pipelines):

@@ -26,7 +26,8 @@ UNDOC_RMW = ["slo", "rla", "sre", "rra", "dcp", "isc"]
 
 RAM = [a for a in range(0x80, 0xF8) if a not in (0xD0, 0xD1, 0xD4, 0xD5, 0xE0, 0xE1)]   # $F8-$FF: stack
 TIA_W = [0x01, 0x06, 0x07, 0x08, 0x09, 0x0A, 0x0B, 0x0C, 0x0D, 0x0E, 0x0F, 0x10, 0x11, 0x1B, 0x1C,
-         0x20, 0x21, 0x2A, 0x2B, 0x04, 0x05, 0x15, 0x19, 0x1D, 0x25, 0x2C]
+         0x20, 0x21, 0x2A, 0x2B, 0x04, 0x05, 0x15, 0x19, 0x1D, 0x25, 0x2C,
+         0x12, 0x13, 0x14, 0x1E, 0x1F, 0x22, 0x23, 0x24, 0x26, 0x27, 0x28, 0x29, 0x1B, 0x1C, 0x1D, 0x1F]
 TIA_R = list(range(0x00, 0x10))
 RIOT_R = [0x280, 0x281, 0x282, 0x283, 0x284, 0x285, 0x286, 0x287]
 RIOT_W = [0x294, 0x295, 0x296, 0x297, 0x280, 0x281]

@@ -101,6 +101,10 @@ typedef struct {
     uint32_t pipelines;         /* step pipelines (0 = 1, at most 8): each has its own
                                    scratch of max_batch envs, so calls on different
                                    pipelines may run concurrently (vcs_step_pipe) */
+    uint32_t collisions;        /* 1: track the TIA collision latches (CXM0P..CXPPMM
+                                   read what the frame's pixels so far set, CXCLR
+                                   clears them; every frame is then logged and scanned,
+                                   at some cost); 0: they read 0 */
     uint8_t gray_lut[128];      /* gray level of colour index (colour >> 1)      */
 } vcs_config;
 
@@ -165,8 +169,15 @@ int vcs_step_pipe(vcs_ctx* ctx, uint32_t pipe, const int32_t* env_ids_dev, const
    167 REFP0 168 REFP1 169 PF0 170 PF1 171 PF2 172 GRP0 173 GRP1 174 HMP0
    175 HMP1 176 P0 position 177 P1 position
    180..183 rom_id 184..187 step count 188..191 episode count 192 previous
-   action 194 error bits 200..207 instructions executed 256..383
-   Superchip RAM; other bytes 0.
+   action 194 error bits 200..207 instructions executed
+   208 NUSIZ0 209 NUSIZ1 210 ENAM0 211 ENAM1 212 ENABL 213 ENABL (delayed copy)
+   214 GRP0 (delayed copy) 215 GRP1 (delayed copy) 216 VDELP0 217 VDELP1
+   218 VDELBL 219 RESMP0 220 RESMP1 221 M0 position 222 M1 position
+   223 ball position 224 HMM0 225 HMM1 226 HMBL 227 1 when an early HMOVE
+   blanked pixels 0-7 of the line of `cycle` 228..229 collision latches (bit
+   2r+1 / 2r = D7 / D6 of CX register r) 230 latches tracked (vcs_config
+   .collisions; set_state takes the context's)
+   256..383 Superchip RAM; other bytes 0.
    get/set synchronise the device. */
 int vcs_get_state(vcs_ctx* ctx, uint32_t env_id, uint8_t* out_host);
 int vcs_set_state(vcs_ctx* ctx, uint32_t env_id, const uint8_t* in_host);

@@ -49,7 +49,8 @@
  *  - Collisions (when tracked): the 15 latches set at every drawn pixel of
  *    the 210 frame rows (VBLANK clear, outside an HMOVE blank) where two
  *    objects meet; a read at access cycle t sees pixels up to colour clock
- *    3t+2; CXCLR clears them; untracked, they read 0.
+ *    3t+2; CXCLR clears them; untracked, they read 0, and instruction fetches
+ *    and zero-page pointer fetches (no side effects) always read them as 0.
  *  - Undocumented opcodes: the stable ones (SLO, RLA, SRE, RRA, SAX, LAX,
  *    DCP, ISC, ANC, ALR, ARR, SBX, LAS, SBC #, and the NOPs of every width,
  *    which perform their read) run with the operations, cycle counts and
@@ -404,12 +405,13 @@ static uint8_t bus_read(OMachine* m, uint16_t addr) {
     return riot_read(m, a);
 }
 
-/* instruction-fetch bus: the same map without side effects; the cartridge
-   area always shows ROM (the Superchip RAM window is for data only) */
+/* instruction-fetch bus (also zero-page pointers): the same map without
+   side effects; the cartridge area always shows ROM (the Superchip RAM window
+   is for data only) and the collision latches read 0 */
 static uint8_t bus_peek(const OMachine* m, uint16_t addr) {
     uint16_t a = addr & 0x1FFF;
     if (a & 0x1000) return rom_byte(m, a);
-    if ((a & 0x80) == 0) return tia_read(m, a);
+    if ((a & 0x80) == 0) return (a & 0x0F) < 8 ? 0 : tia_read(m, a);
     if ((a & 0x200) == 0) return m->ram[a & 0x7F];
     return riot_read(m, a);
 }

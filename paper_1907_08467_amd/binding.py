@@ -39,6 +39,7 @@ class VcsConfig(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("device", ctypes.c_int32),
         ("pipelines", ctypes.c_uint32),
+        ("collisions", ctypes.c_uint32),
         ("gray_lut", ctypes.c_uint8 * 128),
     ]
 

@@ -44,6 +44,7 @@ struct TimedLaunch {
 // [counts R][offsets R][fill R] (pad) [instruction counters, 2 x u64][queue].
 struct Pipe {
     uint8_t* d_logs = nullptr;      // [max_batch][n_slots] row logs
+    uint8_t* d_cxlogs = nullptr;    // [max_batch] logs of unrendered frames (tracked collisions)
     StepInfo* d_info = nullptr;     // [max_batch]
     uint8_t* d_valid = nullptr;     // [max_batch]
     Tile* d_tiles = nullptr;        // [tiles_cap]
@@ -162,6 +163,7 @@ DevEnv power_on(const vcs_ctx* c, uint32_t r) {
     e.p = 0x24;
     e.bank = (uint8_t)bank;
     e.bank_hi = (uint8_t)(bank >> 8);
+    e.track_cx = c->cfg.collisions ? 1 : 0;
     e.pc = (uint16_t)(rom[cart_rom_off(R, bank, 0x1FFC)] | (rom[cart_rom_off(R, bank, 0x1FFD)] << 8));
     e.tv = 0;
     e.tshift = 10;
@@ -391,6 +393,8 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
     ia.err_word = c->d_err;
     ia.instr_total = P.d_instr;
     ia.queue = nullptr;
+    ia.track = c->cfg.collisions ? 1 : 0;
+    ia.cx_logs = P.d_cxlogs;
     if (c->launch.workers && c->launch.workers < grid) {
         ia.queue = P.d_queue;
         grid = c->launch.workers;
@@ -507,6 +511,7 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
     c->pipes.resize(cfg->pipelines ? cfg->pipelines : 1);
     for (auto& P : c->pipes) {
         if (!rc) rc = alloc_n(c, &P.d_logs, B * c->n_slots * kFrameLogBytes, "row logs");
+        if (!rc && cfg->collisions) rc = alloc_n(c, &P.d_cxlogs, B * kFrameLogBytes, "collision row logs");
         if (!rc) rc = alloc_n(c, &P.d_info, B, "step info");
         if (!rc) rc = alloc_n(c, &P.d_valid, B, "id validity");
         if (!rc) rc = alloc_n(c, &P.d_tag, 1, "claim tag");
@@ -641,7 +646,8 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     HIP_OK(hipMemcpy(c->d_cmap, cmap.data(), n_roms * sizeof(CartMap), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->d_pre_off, pre_off.data(), n_roms * 4, hipMemcpyHostToDevice));
     for (uint32_t r = 0; r < n_roms; ++r)
-        launch_predecode(c->d_roms + (size_t)r * kRomSlot, c->h_rinfo[r], c->d_pre + c->h_rinfo[r].pre_off, nullptr);
+        launch_predecode(c->d_roms + (size_t)r * kRomSlot, c->h_rinfo[r], c->d_pre + c->h_rinfo[r].pre_off,
+                         c->cfg.collisions ? 1u : 0u, nullptr);
     HIP_OK(hipGetLastError());
     HIP_OK(hipDeviceSynchronize());
     return VCS_OK;
@@ -697,13 +703,14 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     uint32_t* d_cnt = nullptr;
     rc = alloc_n(c, &d_ct, ctiles.size(), "cache tiles");
     if (!rc) rc = alloc_n(c, &d_nfr, M, "cache frame counts");
-    if (!rc) rc = alloc_n(c, &d_clog, (size_t)M * 2 * kFrameLogBytes, "cache row logs");
+    if (!rc) rc = alloc_n(c, &d_clog, (size_t)M * (2 + (c->cfg.collisions ? 1 : 0)) * kFrameLogBytes,
+                          "cache row logs");
     if (!rc) rc = alloc_n(c, &d_cinfo, M, "cache info");
     if (!rc) rc = alloc_n(c, &d_cnt, 1, "cache tile count");
     auto cleanup = [&]() {
         dev_free(c, d_ct, ctiles.size() * sizeof(Tile));
         dev_free(c, d_nfr, (size_t)M * 2);
-        dev_free(c, d_clog, (size_t)M * 2 * kFrameLogBytes);
+        dev_free(c, d_clog, (size_t)M * (2 + (c->cfg.collisions ? 1 : 0)) * kFrameLogBytes);
         dev_free(c, d_cinfo, (size_t)M * sizeof(StepInfo));
         dev_free(c, d_cnt, 4);
     };
@@ -743,6 +750,8 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     ia.done = nullptr;
     ia.err_word = c->d_err;
     ia.instr_total = nullptr;
+    ia.track = c->cfg.collisions ? 1 : 0;
+    ia.cx_logs = d_clog + (size_t)M * 2 * kFrameLogBytes;
     launch_interp(ia, n_ct, kLanes, c->rom_lds, nullptr);
     RenderArgs ra{};
     ra.logs = d_clog;
@@ -871,6 +880,7 @@ int vcs_set_state(vcs_ctx* c, uint32_t env, const uint8_t* in) {
     if (e.rom_id != c->h_env_rom[env]) return fail(VCS_E_INVAL, "state's ROM differs from the env's ROM");
     const uint32_t bank = e.bank | ((uint32_t)e.bank_hi << 8);
     if (bank >= c->h_rinfo[e.rom_id].n_vbanks) return fail(VCS_E_INVAL, "bank state out of range for the ROM's scheme");
+    e.track_cx = c->cfg.collisions ? 1 : 0;      // the context decides whether latches are tracked
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemcpy(c->d_envs + env, &e, sizeof(DevEnv), hipMemcpyHostToDevice));

@@ -30,7 +30,7 @@
 // scalar branches.  In lockstep (the common case for envs of one ROM) that is
 // a single pass.  TIA writes are queued during the pass and applied in one
 // shared block afterwards.
-#include "vcs_device.h"
+#include "tia_draw.h"
 
 namespace vcs {
 
@@ -212,6 +212,7 @@ struct Wave {                 // per-workgroup (uniform) data
     uint8_t* tia;             // LDS, kTiaStride bytes per lane
     const uint32_t* pre;      // the tile ROM's predecoded words
     CartMap cm;               // its cartridge mapping
+    uint32_t track;           // collision latches tracked
 };
 
 __device__ __forceinline__ uint32_t cm_kind(const Wave& W) { return W.cm.a & 3; }
@@ -250,13 +251,43 @@ struct Cpu {
     uint32_t icount;
     uint32_t ucount;          // instructions executed in wave-uniform mode
     int32_t hmb_line;         // line (relative to the base line) an early HMOVE blanked, or -1
+    uint32_t cx;              // collision latches (bit 2r+1 / 2r = D7 / D6 of CX register r)
+    int32_t cx_row, cx_x;     // the frame's pixels before (row, x) are in cx
+    int32_t cx_need;          // >= 0: a latch read needs the pixels through this clock scanned first
+    uint32_t log_scratch;     // the row log is the collision scratch copy, not a rendered frame
 };
 
 __device__ __forceinline__ uint32_t nz(uint32_t p, uint32_t v) {
     return (p & ~(FN | FZ)) | (v & FN) | (v == 0 ? FZ : 0);
 }
 
-__device__ __forceinline__ uint32_t tia_read(const Cpu& c, uint32_t a) {
+// Position of colour clock `clk` (relative to the base line) in the frame's
+// rows: (row, first pixel after it)
+__device__ __forceinline__ bool cx_scanned(const Cpu& c, int32_t clk) {
+    const int32_t line = clk / 228, h = clk % 228;
+    const int32_t row = line - c.fl - kFirstRow;
+    if (row < 0) return true;
+    if (row >= kRows) return c.cx_row >= kRows;
+    const int32_t x = h >= 68 ? h - 68 + 1 : 0;
+    return c.cx_row > row || (c.cx_row == row && c.cx_x >= x);
+}
+
+// TIA data read of address a by an access that sees the beam through clock
+// `through`.  A latch read (tracked) whose pixels are not all scanned yet
+// records that need and reads 0; the per-lane dispatch then scans the row
+// log and runs the instruction again.
+__device__ __forceinline__ uint32_t tia_read(Cpu& c, const Wave& W, uint32_t a, int32_t through) {
+    const uint32_t r = a & 0x0F;
+    if (r < 8) {
+        if (!W.track) return 0u;
+        if (!cx_scanned(c, through)) c.cx_need = through;
+        return ((c.cx >> (2 * r)) & 3) << 6;
+    }
+    return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);
+}
+// the same without side effects (instruction fetch, zero-page pointers): the
+// latches read 0 there
+__device__ __forceinline__ uint32_t tia_peek(const Cpu& c, uint32_t a) {
     const uint32_t r = a & 0x0F;
     return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);
 }
@@ -287,7 +318,7 @@ __device__ __forceinline__ uint32_t rd(Cpu& c, const Wave& W, uint32_t addr, uin
         if (sc_window(W, a)) return (a & 0x80) ? (uint32_t)c.xram[a & 0x7F] : 0u;   // the write port reads 0
         return W.rom[rom_off(W, c.bank, a)];
     }
-    if (!(a & 0x80)) return tia_read(c, a);
+    if (!(a & 0x80)) return tia_read(c, W, a, 3 * (int32_t)t + 2);   // the access cycle's own pixels too
     if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
     return riot_read(c, W, a, t);
 }
@@ -297,13 +328,13 @@ __device__ __forceinline__ uint32_t rd(Cpu& c, const Wave& W, uint32_t addr, uin
 __device__ __forceinline__ uint32_t peek(const Cpu& c, const Wave& W, uint32_t addr, uint32_t t) {
     const uint32_t a = addr & 0x1FFF;
     if (a & 0x1000) return W.rom[rom_off(W, c.bank, a)];
-    if (!(a & 0x80)) return tia_read(c, a);
+    if (!(a & 0x80)) return tia_peek(c, a);
     if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
     return riot_read(c, W, a, t);
 }
 
 __device__ __forceinline__ uint32_t zp_peek(const Cpu& c, const Wave& W, uint32_t z) {
-    return (z & 0x80) ? (uint32_t)W.ram[c.ram_off + (z & 0x7F)] : tia_read(c, z);
+    return (z & 0x80) ? (uint32_t)W.ram[c.ram_off + (z & 0x7F)] : tia_peek(c, z);
 }
 
 // data write at cycle t; TIA writes are queued in slot K of the instruction
@@ -676,7 +707,64 @@ __device__ __forceinline__ void log_close(Cpu& c, const Wave& W, uint32_t t) {
         d[1] = make_uint4(0, 0, 0, 0);
     }
     c.log = nullptr;
-    c.slots |= 1u << c.slot;
+    if (!c.log_scratch) c.slots |= 1u << c.slot;
+}
+
+// ------------------------------------------------------------ collisions
+
+// Latches of the pixels of the frame's rows from the scan position
+// (c.cx_row, c.cx_x) up to row_end (pixels of row_end before x_end), from
+// the row log: each row's snapshot and logged writes, 16 pixels at a time.
+__device__ __forceinline__ void cx_scan(Cpu& c, const Wave& W, int32_t row_end, int32_t x_end) {
+    if (row_end > kRows) {
+        row_end = kRows;
+        x_end = 0;
+    }
+    while (c.cx_row < row_end || (c.cx_row == row_end && c.cx_x < x_end && row_end < kRows)) {
+        const int32_t r = c.cx_row;
+        const uint32_t xe = r < row_end ? 160u : (uint32_t)x_end;
+        const uint8_t* rec = c.log + r * kRowBytes;
+        const uint4 sa = reinterpret_cast<const uint4*>(rec)[0], sb = reinterpret_cast<const uint4*>(rec)[1];
+        Regs R;
+        unpack(R, sa, sb);
+        const uint32_t cnt = r == c.open_row ? c.open_cnt : ((sa.w >> 24) & 0x1F);
+        const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + kSnapBytes);
+        uint32_t ei = 0, cur = (uint32_t)c.cx_x;
+        while (cur < xe) {
+            while (ei < cnt && (ents[ei] & 0xFF) <= cur) apply(R, ents[ei++]);
+            const uint32_t nx = ei < cnt ? min((uint32_t)(ents[ei] & 0xFF), xe) : xe;
+            for (uint32_t x0 = cur & ~15u; x0 < nx; x0 += 16) {
+                uint32_t o[6], shown;
+                objects16(R, x0, (uint32_t)r, o, shown);
+                const uint32_t lo = cur > x0 ? cur - x0 : 0u, hi = nx < x0 + 16 ? nx - x0 : 16u;
+                const uint32_t run = ((1u << hi) - 1) & ~((1u << lo) - 1);
+                c.cx |= collide16(o, shown & run);
+            }
+            cur = nx;
+        }
+        if (xe == 160) {
+            c.cx_row = r + 1;
+            c.cx_x = 0;
+        } else {
+            c.cx_x = (int32_t)xe;
+        }
+    }
+}
+
+// Scan the pixels through colour clock `through` (relative to the base line)
+// into the latches; the rows the beam has reached get their snapshots first
+// (as the next logged write would take them).  through < 0: the whole frame
+// (its log is complete).
+__device__ __forceinline__ void cx_catch_up(Cpu& c, const Wave& W, int32_t through) {
+    if (through < 0) {
+        cx_scan(c, W, kRows, 0);
+        return;
+    }
+    const int32_t line = through / 228, h = through % 228;
+    const int32_t row = line - c.fl - kFirstRow;
+    if (row < 0) return;
+    log_advance(c, W, h >= 68 ? row : row - 1);
+    cx_scan(c, W, row, h >= 68 ? h - 68 + 1 : 0);
 }
 
 // Position a RESPx (players, +5) or RESMx / RESBL (+4) write at cycle t sets.
@@ -714,6 +802,23 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, u
     case 0x21: c.hmp1 = v; return;
     case 0x22: case 0x23: case 0x24: R[R_HMM0 + reg - 0x22] = (uint8_t)v; return;
     case 0x2B: c.hmp0 = 0; c.hmp1 = 0; R[R_HMM0] = R[R_HMM1] = R[R_HMBL] = 0; return;
+    case 0x2C:                                  // CXCLR: the latches restart at clock 3(t+1)
+        if (W.track) {
+            const int32_t ln = (int32_t)((t + 1) / 76), h = 3 * ((int32_t)(t + 1) - 76 * ln);
+            const int32_t row = ln - c.fl - kFirstRow;
+            c.cx = 0;
+            if (row < 0) {
+                c.cx_row = 0;
+                c.cx_x = 0;
+            } else if (row >= kRows) {
+                c.cx_row = kRows;
+                c.cx_x = 0;
+            } else if (row > c.cx_row || (row == c.cx_row && h - 68 > c.cx_x)) {
+                c.cx_row = row;
+                c.cx_x = h >= 68 ? h - 68 : 0;
+            }
+        }
+        return;
     case 0x1B:                                  // GRP0; GRP1 to its delayed copy
         if (lg) log_event(c, W, t, R_GRP0, v, 0);
         R[R_GRP1_OLD] = R[R_GRP1];
@@ -1183,6 +1288,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
                 dm = dec_mode(c);
                 if (dm == 2) return FS_EXIT;
             }
+            if (aux == SC_EXIT) return FS_EXIT;   // a collision latch read: the per-lane path scans the log
             uint32_t v;
             if (MD == ABS && aux == SC_XRAM)      // Superchip RAM: read port, or the write port (0)
                 v = (a & 0x80) ? (uint32_t)c.xram[a & 0x7F] : 0u;
@@ -1444,7 +1550,9 @@ __device__ __forceinline__ uint32_t take_tile(uint32_t* queue) {
 // from its HBM slot through the caches (launches with a ROM larger than 8 KB,
 // which would otherwise need 32 KB of LDS per wave and cut the waves per CU
 // by three).
-template <int LL, int RC>
+// TRACK: collision latches tracked (the scan code exists only in that
+// instantiation, so the other keeps its registers).
+template <int LL, int RC, bool TRACK>
 __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t* __restrict__ pre_all) {
     __shared__ uint32_t s_rom[RC ? RC / 4 + 4 : 1];
     __shared__ uint32_t s_ram[(LL + 1) * kRamStride / 4];
@@ -1470,6 +1578,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
         W.tia = reinterpret_cast<uint8_t*>(s_tia);
         W.cm = A.cmap[rom_id];
         W.pre = pre_all + A.pre_off[rom_id];
+        W.track = TRACK ? 1u : 0u;
 
         const int env = lane < T.count ? T.env[lane] : -1;
         const int out = lane < T.count ? T.out[lane] : 0;
@@ -1509,6 +1618,8 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             c.cyc = (uint32_t)(cyc - base_line * 76);
             c.fl = (int32_t)((int64_t)E->frame_line0 - (int64_t)base_line);
             c.hmb_line = E->hmb_now ? 0 : -1;     // the line of `cycle` is the base line
+            c.cx = E->cx;
+            c.cx_need = -1;
             prev_action = E->prev_action;
             step_idx = E->step_idx;
             c.err = E->err;
@@ -1546,8 +1657,15 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                         ? A.logs + ((size_t)out * A.n_slots + slot) * kFrameLogBytes
                         : nullptr;
             c.slot = (uint32_t)slot;
+            c.log_scratch = 0;
+            if (TRACK && !c.log) {                 // tracked collisions read every frame's log
+                c.log = A.cx_logs + (size_t)out * kFrameLogBytes;
+                c.log_scratch = 1;
+            }
             c.open_row = -1;
             c.open_cnt = 0;
+            c.cx_row = 0;
+            c.cx_x = 0;
             W.tia[c.tia_off + R_HMB] = 0;          // an earlier frame's blanked row is not this frame's
         };
 
@@ -1627,8 +1745,23 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                     uint32_t d = kDecode.w[sw];
                     asm volatile("" : "+s"(d));
                     if (op == sop) {
+                        if constexpr (TRACK) {
+                            if (c.cx_need >= 0) {   // the second run of an instruction that read the latches
+                                cx_catch_up(c, W, c.cx_need);
+                                c.cx_need = -1;
+                            }
+                        }
+                        const uint32_t sa = c.a, sx = c.x, sy = c.y, ssp = c.sp, sp_ = c.p, spc = c.pc,
+                                       scy = c.cyc, sbk = c.bank;
                         exec_generic(d, c, W, b1, b2);
-                        todo = false;
+                        if (TRACK && c.cx_need >= 0) {   // undo; the latches are scanned before it runs again
+                            c.a = sa; c.x = sx; c.y = sy; c.sp = ssp; c.p = sp_; c.pc = spc; c.cyc = scy;
+                            c.bank = sbk;
+                            c.tqm = 0;
+                            c.ev = 0;
+                        } else {
+                            todo = false;
+                        }
                     }
                 }
             }
@@ -1656,7 +1789,15 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 end_t = c.cyc;
             }
             if (ended) {
-                if (c.log) log_close(c, W, end_t);
+                if (c.log) {
+                    uint8_t* lg = c.log;
+                    log_close(c, W, end_t);
+                    if constexpr (TRACK) {         // the latches take the frame's remaining rows
+                        c.log = lg;
+                        cx_catch_up(c, W, -1);
+                        c.log = nullptr;
+                    }
+                }
                 c.fl = (int32_t)(end_t / 76);
                 ++k;
                 ++f;
@@ -1682,6 +1823,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             reinterpret_cast<uint4*>(E->tia2)[0] = make_uint4(st[4], st[5], st[6], st[7]);
             reinterpret_cast<uint4*>(E->tia2)[1] = make_uint4(st[8], st[9], st[10], st[11]);
             E->hmb_now = c.hmb_line >= 0 && (uint32_t)c.hmb_line == c.cyc / 76 ? 1 : 0;
+            E->cx = (uint16_t)c.cx;
             E->a = c.a; E->x = c.x; E->y = c.y; E->sp = c.sp; E->p = c.p;
             E->bank = (uint8_t)c.bank;
             E->bank_hi = (uint8_t)(c.bank >> 8);
@@ -1727,9 +1869,10 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
 // zero-page or absolute STA/STX/STY; on 3F cartridges a store to $00-$3F
 // (which also selects a slice) is SC_3F when the TIA register it reaches is
 // not emulated, else SC_EXIT (left to the per-lane path); on Superchip
-// cartridges an absolute access to the RAM window is SC_XRAM.  Entries past
-// offset $FFD are never used.
-__global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre) {
+// cartridges an absolute access to the RAM window is SC_XRAM; with tracked
+// collisions a zero-page / absolute read of a latch register is SC_EXIT.
+// Entries past offset $FFD are never used.
+__global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre, uint32_t track) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R.n_vbanks * 4096u) return;
     const uint32_t bank = i >> 12, off = i & 0xFFF;
@@ -1747,25 +1890,37 @@ __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre) {
     }
     if (R.sc && md == ABS && ((d >> DW_RD) & 1 || (d >> DW_WR) & 1) && (abs_addr & 0x1000) && !(abs_addr & 0xF00))
         aux = SC_XRAM;
+    // tracked collision latches: zero-page / absolute reads of CXM0P..CXPPMM
+    const uint32_t ra = md == ZP ? b1 : abs_addr;
+    if (track && (md == ZP || md == ABS) && ((d >> DW_RD) & 1) && !((d >> DW_WR) & 1) && !(ra & 0x1080) && (ra & 0xF) < 8)
+        aux = SC_EXIT;
     pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24);
 }
 
-void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, hipStream_t s) {
+void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, uint32_t track, hipStream_t s) {
     const uint32_t n = info.n_vbanks * 4096u;
-    hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, rom, info, pre);
+    hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, rom, info, pre, track);
+}
+
+template <bool TRACK>
+static void launch_interp_t(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s) {
+    if (rom_lds == 0) {
+        if (tile_envs <= 32)
+            hipLaunchKernelGGL((k_interp<32, 0, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+        else
+            hipLaunchKernelGGL((k_interp<64, 0, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+    } else if (tile_envs <= 32) {
+        hipLaunchKernelGGL((k_interp<32, 8192, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+    } else {
+        hipLaunchKernelGGL((k_interp<64, 8192, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+    }
 }
 
 void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s) {
-    if (rom_lds == 0) {
-        if (tile_envs <= 32)
-            hipLaunchKernelGGL((k_interp<32, 0>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
-        else
-            hipLaunchKernelGGL((k_interp<64, 0>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
-    } else if (tile_envs <= 32) {
-        hipLaunchKernelGGL((k_interp<32, 8192>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
-    } else {
-        hipLaunchKernelGGL((k_interp<64, 8192>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
-    }
+    if (a.track)
+        launch_interp_t<true>(a, grid, tile_envs, rom_lds, s);
+    else
+        launch_interp_t<false>(a, grid, tile_envs, rom_lds, s);
 }
 
 }  // namespace vcs

@@ -172,6 +172,8 @@ struct InterpArgs {
     unsigned long long* instr_total;
     uint32_t* queue;          // NULL: workgroup b runs tile b; else workgroups take
                               // tiles from this counter until it passes *n_tiles
+    uint32_t track;           // collision latches tracked
+    uint8_t* cx_logs;         // [n outputs][kFrameLogBytes]: logs of frames not rendered (track)
 };
 
 // SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014)
@@ -218,7 +220,7 @@ struct ResetArgs {
 // tile_envs: widest tile; rom_lds: bytes of ROM staged in LDS (8192), or 0 to
 // read the cartridges from HBM
 void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s);
-void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, hipStream_t s);
+void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, uint32_t track, hipStream_t s);
 void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s);
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s);
 void launch_reset(const ResetArgs& a, hipStream_t s);

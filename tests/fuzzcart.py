@@ -28,7 +28,13 @@ RAM = [a for a in range(0x80, 0xF8) if a not in (0xD0, 0xD1, 0xD4, 0xD5, 0xE0, 0
 TIA_W = [0x01, 0x06, 0x07, 0x08, 0x09, 0x0A, 0x0B, 0x0C, 0x0D, 0x0E, 0x0F, 0x10, 0x11, 0x1B, 0x1C,
          0x20, 0x21, 0x2A, 0x2B, 0x04, 0x05, 0x15, 0x19, 0x1D, 0x25, 0x2C,
          0x12, 0x13, 0x14, 0x1E, 0x1F, 0x22, 0x23, 0x24, 0x26, 0x27, 0x28, 0x29, 0x1B, 0x1C, 0x1D, 0x1F]
+TIA_W_CX = [a for a in TIA_W if a != 0x01]       # no VBLANK: the objects stay drawn
 TIA_R = list(range(0x00, 0x10))
+# objects on at every frame start, then down to the visible rows (collision
+# cartridges)
+CX_FRAME = ["    lda #0", "    sta VBLANK", "    lda #$FF", "    sta GRP0", "    sta GRP1", "    lda #2",
+            "    sta ENAM0", "    sta ENAM1", "    sta ENABL", "    sta PF1",
+            "    ldx #36", "cxw:", "    sta WSYNC", "    dex", "    bne cxw"]
 RIOT_R = [0x280, 0x281, 0x282, 0x283, 0x284, 0x285, 0x286, 0x287]
 RIOT_W = [0x294, 0x295, 0x296, 0x297, 0x280, 0x281]
 CART_R = list(range(0x1E00, 0x1F00))
@@ -42,10 +48,11 @@ BRANCHES = ["bpl", "bmi", "bvc", "bvs", "bcc", "bcs", "bne", "beq"]
 
 
 class Gen:
-    def __init__(self, seed, scheme=S_4K, undoc=False):
+    def __init__(self, seed, scheme=S_4K, undoc=False, cx=False):
         self.r = np.random.default_rng(seed)
         self.scheme = scheme
         self.undoc = undoc
+        self.cx = cx
         self.n = 0
         self.lines = []
         self.hot = list(HOTSPOTS.get(scheme, []))
@@ -86,7 +93,7 @@ class Gen:
         if x < 0.55:
             return self.pick(RAM)
         if x < 0.8:
-            return self.pick(TIA_W)
+            return self.pick(TIA_W_CX if self.cx else TIA_W)
         if self.hot and x < 0.86:
             return self.pick(self.hot)
         if self.sc and x < 0.93:
@@ -236,6 +243,8 @@ class Gen:
                  "    bcc fc2", "    bne fc3", "    lda $D4", f"    cmp #${T & 0xFF:02X}", "    bcc fc2",
                  "fc3:", "    lda #1", "    sta $D1", "fc2:", "    lda INPT4", "    bmi fc4", "    sed", "    clc",
                  "    lda $D0", "    adc #1", "    sta $D0", "fc4:", "    cld", "    sta WSYNC"]
+        if self.cx:
+            frame += CX_FRAME
         self.lines = []
         for _ in range(lines_per_frame):
             for _ in range(int(self.r.integers(2, 7))):
@@ -262,9 +271,9 @@ class Gen:
 VECTORS = "\n    .org $1FFA\n    .word reset, reset, brkh\n"
 
 
-def _segmented(seed, scheme, undoc, lines_per_frame, size):
+def _segmented(seed, scheme, undoc, lines_per_frame, size, cx):
     """E0 (8 KB) or 3F (`size`): code in the fixed segment, data slices."""
-    g = Gen(seed, scheme, undoc)
+    g = Gen(seed, scheme, undoc, cx)
     if scheme == S_E0:
         n_sl, sl, fixed_at = 8, 1024, 0x1C00
     else:
@@ -290,13 +299,15 @@ def _segmented(seed, scheme, undoc, lines_per_frame, size):
     return bytes(out), scheme
 
 
-def fuzz_cart(seed, f8=False, lines_per_frame=60, scheme=None, undoc=False, size=8192):
+def fuzz_cart(seed, f8=False, lines_per_frame=60, scheme=None, undoc=False, size=8192, cx=False):
+    """cx: the objects are switched on at every frame start and VBLANK is
+    never written, so that they collide."""
     scheme = (S_F8 if f8 else S_4K) if scheme is None else scheme
     if scheme in (S_E0, S_3F):
-        return _segmented(seed, scheme, undoc, min(lines_per_frame, 14 if scheme == S_E0 else 40), size)
+        return _segmented(seed, scheme, undoc, min(lines_per_frame, (12 if cx else 14) if scheme == S_E0 else 40), size, cx)
     nb = LINEAR_BANKS[scheme]
     org = "$1100" if scheme in (S_F8SC, S_F6SC, S_F4SC) else "$1000"
-    g = Gen(seed, scheme, undoc)
+    g = Gen(seed, scheme, undoc, cx)
     code, data = g.source(lines_per_frame)
     # the same code in every bank (so a switch continues in place), different data
     g2 = Gen(seed + 1, scheme, undoc)

@@ -16,8 +16,9 @@ def test_every_declared_function_is_exported():
 
 
 def test_header_struct_matches_binding():
-    # vcs_config: 6 x u32, u64, 2 x u32, u64, i32, 128 B -> 184 bytes with alignment
-    assert ctypes.sizeof(B.VcsConfig) == 184
+    # vcs_config: 6 x u32, u64, 2 x u32, u64, i32, 2 x u32, 128 B -> 192 bytes with alignment
+    assert ctypes.sizeof(B.VcsConfig) == 192
+    assert B.VcsConfig.collisions.offset == 56 and B.VcsConfig.gray_lut.offset == 60
 
 
 @pytest.mark.parametrize("field,value", [("num_envs", 0), ("frameskip", 0), ("render_mode", 2),

@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
-    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference", "schemes"], default="plain",
+    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference", "schemes", "objects"], default="plain",
                    help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
                         "serve: 131072 resident envs behind the env server; divergent: 32768 envs over 8 "
                         "branchy ROMs with sticky actions, with the per-step rate over the run; stack: the frame "
@@ -85,7 +85,7 @@ def copy_calibration(mib):
 def cpu_baseline(w, roms, env_rom, steps):
     import oracle
     from paper_1907_08467_amd.inputs.palette import GRAY
-    o = oracle.Oracle(w.n_envs, GRAY, frameskip=w.frameskip, seed=w.rng_seed)
+    o = oracle.Oracle(w.n_envs, GRAY, frameskip=w.frameskip, seed=w.rng_seed, collisions=w.collisions)
     o.load_roms(roms)
     o.assign(env_rom)
     acts = w.actions(steps=steps)
@@ -152,14 +152,14 @@ def gpu_env(w, **kw):
     roms = [(r.data, r.scheme) for r in w.roms()]
     env_rom = w.env_rom()
     env = VcsEnv(roms, env_rom, GRAY, frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode,
-                 sticky_threshold=w.sticky_threshold, **kw)
+                 sticky_threshold=w.sticky_threshold, collisions=w.collisions, **kw)
     return env, roms, env_rom
 
 
-def bench_plain(args):
+def bench_plain(args, c=2):
     import torch
     from paper_1907_08467_amd.inputs.workloads import config
-    w = config(2)
+    w = config(c)
     if args.envs != w.n_envs:
         w.n_envs = args.envs
     G = args.graph
@@ -222,9 +222,13 @@ def bench_plain(args):
         "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": n * w.frameskip / value * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": f"plain batched step: {n} envs x 1 seeded 4 KB synthetic cartridge, frameskip "
-                               f"{w.frameskip}, every 210x160 frame rendered to HBM + 84x84 max-of-two gray obs, "
-                               "random actions (seed 1), no sticky actions",
+        "config": {"workload": (f"plain batched step: {n} envs x 1 seeded 4 KB synthetic cartridge, frameskip "
+                                f"{w.frameskip}, every 210x160 frame rendered to HBM + 84x84 max-of-two gray obs, "
+                                "random actions (seed 1), no sticky actions") if c == 2 else
+                               (f"objects step: {n} envs x 1 seeded 4 KB synthetic cartridge with missiles, ball, "
+                                f"NUSIZ copies, object motion and collision reads, collision latches tracked, "
+                                f"frameskip {w.frameskip}, every 210x160 frame rendered to HBM + 84x84 max-of-two "
+                                f"gray obs, random actions (seed {w.action_seed}), no sticky actions"),
                    "num_envs": n, "frameskip": w.frameskip, "render": "all frames",
                    "launch": launch, "launch_from": launch_from,
                    "steps_as": f"HIP graphs of {G} steps, render overlapping the next interpreter" if G
@@ -661,7 +665,7 @@ def main():
         sys.exit(2)
     fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
           "divergent": bench_divergent, "stack": bench_stack, "inference": bench_inference,
-          "schemes": bench_schemes}[args.workload]
+          "schemes": bench_schemes, "objects": lambda a: bench_plain(a, 7)}[args.workload]
     print(json.dumps(fn(args)))
 
 

@@ -239,7 +239,12 @@ int vcs_get_launch(vcs_ctx* ctx, vcs_launch* out);
    the tile count), then render_block.  Every candidate starts from the same
    env states; afterwards the states, the error bits and the counters are
    restored, so later steps give the results they would have given without
-   tuning.  Keeps the fastest shape and returns it with its ms per step.
+   tuning.  Keeps the fastest shape and returns it with its ms per step; an
+   interpreter shape (tile_envs, workers) replaces the current best only when
+   at least 3 % faster, so near ties keep the earlier shape (wider tiles, no
+   workers: fewer workgroups, which leave compute units to work that overlaps
+   the step, such as the previous step's render in captured graphs, and which
+   the isolated timing does not see).
    Temporary device buffers (a state snapshot, outputs: frames only if
    want_frames, obs only if want_obs) count against the budget.
    Synchronises. */

@@ -1064,12 +1064,14 @@ int vcs_autotune(vcs_ctx* c, uint32_t n, uint32_t steps, int want_frames, int wa
     vcs_launch best = start;
     best.workers = 0;
     double best_ms = 1e30;
-    auto consider = [&](const vcs_launch& l) -> int {
+    // interpreter shapes: a later candidate must be 3 % faster (near ties keep
+    // the wider, fewer-workgroup shape); render blocks: the fastest
+    auto consider = [&](const vcs_launch& l, double margin) -> int {
         double ms = 0;
         int r = measure(l, &ms);
         if (r == VCS_E_BUDGET) return VCS_OK;   // this shape's tile tables do not fit: skip it
         if (r) return r;
-        if (ms < best_ms) {
+        if (ms < best_ms * (1.0 - margin)) {
             best_ms = ms;
             best = l;
         }
@@ -1081,7 +1083,7 @@ int vcs_autotune(vcs_ctx* c, uint32_t n, uint32_t steps, int want_frames, int wa
         const uint64_t tiles = (n + w - 1) / w + c->n_roms;
         if (w != 64 && tiles > 12ull * c->n_cu) break;
         vcs_launch l{w, 0, start.render_block};
-        rc = consider(l);
+        rc = consider(l, 0.03);
     }
     // 2) persistent interpreter with 1, 2, 4 or 8 workgroups per CU
     const uint64_t tiles_best = (n + best.tile_envs - 1) / best.tile_envs + c->n_roms;
@@ -1089,7 +1091,7 @@ int vcs_autotune(vcs_ctx* c, uint32_t n, uint32_t steps, int want_frames, int wa
         if ((uint64_t)k * c->n_cu >= tiles_best) break;
         vcs_launch l = best;
         l.workers = k * c->n_cu;
-        rc = consider(l);
+        rc = consider(l, 0.03);
     }
     // 3) render workgroup size
     if (!rc && (want_frames || want_obs)) {
@@ -1098,7 +1100,7 @@ int vcs_autotune(vcs_ctx* c, uint32_t n, uint32_t steps, int want_frames, int wa
             if (blk == b.render_block || rc) continue;
             vcs_launch l = b;
             l.render_block = blk;
-            rc = consider(l);
+            rc = consider(l, 0.0);
         }
     }
     c->timing = timing;

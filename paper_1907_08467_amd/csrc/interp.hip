@@ -278,12 +278,11 @@ __device__ __forceinline__ bool cx_scanned(const Cpu& c, int32_t clk) {
 // log and runs the instruction again.
 __device__ __forceinline__ uint32_t tia_read(Cpu& c, const Wave& W, uint32_t a, int32_t through) {
     const uint32_t r = a & 0x0F;
-    if (r < 8) {
-        if (!W.track) return 0u;
+    if (W.track && r < 8) {
         if (!cx_scanned(c, through)) c.cx_need = through;
         return ((c.cx >> (2 * r)) & 3) << 6;
     }
-    return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);
+    return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);      // untracked latches read 0 here too
 }
 // the same without side effects (instruction fetch, zero-page pointers): the
 // latches read 0 there
@@ -792,6 +791,22 @@ __device__ __forceinline__ int32_t hm_delta(uint32_t hm) { return sext8(hm & 0xF
 __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, uint32_t v, uint32_t t) {
     uint8_t* R = W.tia + c.tia_off;
     const bool lg = c.log != nullptr;
+    if (W.track && reg == 0x2C) {               // CXCLR: the latches restart at clock 3(t+1)
+        const int32_t ln = (int32_t)((t + 1) / 76), h = 3 * ((int32_t)(t + 1) - 76 * ln);
+        const int32_t row = ln - c.fl - kFirstRow;
+        c.cx = 0;
+        if (row < 0) {
+            c.cx_row = 0;
+            c.cx_x = 0;
+        } else if (row >= kRows) {
+            c.cx_row = kRows;
+            c.cx_x = 0;
+        } else if (row > c.cx_row || (row == c.cx_row && h - 68 > c.cx_x)) {
+            c.cx_row = row;
+            c.cx_x = h >= 68 ? h - 68 : 0;
+        }
+        return;
+    }
     switch (reg) {
     case 0x00:
         if ((v & 2) && !(c.vsync & 2)) c.ev |= EV_VSYNC;
@@ -802,23 +817,6 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, u
     case 0x21: c.hmp1 = v; return;
     case 0x22: case 0x23: case 0x24: R[R_HMM0 + reg - 0x22] = (uint8_t)v; return;
     case 0x2B: c.hmp0 = 0; c.hmp1 = 0; R[R_HMM0] = R[R_HMM1] = R[R_HMBL] = 0; return;
-    case 0x2C:                                  // CXCLR: the latches restart at clock 3(t+1)
-        if (W.track) {
-            const int32_t ln = (int32_t)((t + 1) / 76), h = 3 * ((int32_t)(t + 1) - 76 * ln);
-            const int32_t row = ln - c.fl - kFirstRow;
-            c.cx = 0;
-            if (row < 0) {
-                c.cx_row = 0;
-                c.cx_x = 0;
-            } else if (row >= kRows) {
-                c.cx_row = kRows;
-                c.cx_x = 0;
-            } else if (row > c.cx_row || (row == c.cx_row && h - 68 > c.cx_x)) {
-                c.cx_row = row;
-                c.cx_x = h >= 68 ? h - 68 : 0;
-            }
-        }
-        return;
     case 0x1B:                                  // GRP0; GRP1 to its delayed copy
         if (lg) log_event(c, W, t, R_GRP0, v, 0);
         R[R_GRP1_OLD] = R[R_GRP1];
@@ -1190,8 +1188,9 @@ __device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t
 }
 
 // One instruction with opcode OP (a compile-time constant, so addressing
-// mode, operation and base cycles are folded) for every lane in exec.
-template <int OP>
+// mode, operation and base cycles are folded) for every lane in exec;
+// TRACK: collision latches tracked.
+template <int OP, bool TRACK>
 __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t b1, uint32_t b2, uint32_t aux) {
     constexpr OpInfo I = decode(OP);
     constexpr int MD = I.md, MN = I.mn;
@@ -1288,7 +1287,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
                 dm = dec_mode(c);
                 if (dm == 2) return FS_EXIT;
             }
-            if (aux == SC_EXIT) return FS_EXIT;   // a collision latch read: the per-lane path scans the log
+            if (TRACK && aux == SC_EXIT) return FS_EXIT;   // a latch read: the per-lane path scans the log
             uint32_t v;
             if (MD == ABS && aux == SC_XRAM)      // Superchip RAM: read port, or the write port (0)
                 v = (a & 0x80) ? (uint32_t)c.xram[a & 0x7F] : 0u;
@@ -1413,7 +1412,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
 }
 
 #define VCS_FAST_CASE(o) \
-    case (o): st = fop<(o)>(c, W, F, b1, b2, aux); break;
+    case (o): st = fop<(o), TRACK>(c, W, F, b1, b2, aux); break;
 #define VCS_FAST_4(o) VCS_FAST_CASE(o) VCS_FAST_CASE((o) + 1) VCS_FAST_CASE((o) + 2) VCS_FAST_CASE((o) + 3)
 #define VCS_FAST_16(o) VCS_FAST_4(o) VCS_FAST_4((o) + 4) VCS_FAST_4((o) + 8) VCS_FAST_4((o) + 12)
 #define VCS_FAST_64(o) VCS_FAST_16(o) VCS_FAST_16((o) + 16) VCS_FAST_16((o) + 32) VCS_FAST_16((o) + 48)
@@ -1426,6 +1425,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
 // return `c` holds every lane's state; `ended`/`end_t` mark lanes whose frame
 // ended.  Returns false when it made no progress (the per-lane path must then
 // execute the instruction in the same iteration).
+template <bool TRACK>
 __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* pre, bool& ended, uint32_t& end_t,
                                          uint32_t partial) {
     Fast F;
@@ -1465,7 +1465,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
             aux = q >> 24;
 #define VCS_HOT(o)                                            \
     if (op == (o)) {                                          \
-        if ((st = fop<(o)>(c, W, F, b1, b2, aux)) != FS_NEXT) break; \
+        if ((st = fop<(o), TRACK>(c, W, F, b1, b2, aux)) != FS_NEXT) break; \
     }
             VCS_HOT(0x85)                    // STA zp
             else VCS_HOT(0xA5)               // LDA zp
@@ -1698,7 +1698,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == tmin && c.fl == fl0 &&
                                   c.open_row == or0 && c.open_cnt == oc0 && (c.log != nullptr ? 1u : 0u) == lg0;
                 const uint32_t partial = __builtin_amdgcn_ballot_w64(!same) != 0 ? 1u : 0u;
-                if (same) uni = run_fast(c, W, W.pre, ended, end_t, partial);
+                if (same) uni = run_fast<TRACK>(c, W, W.pre, ended, end_t, partial);
             }
             const bool ran_uniform = __any(uni);
             const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;

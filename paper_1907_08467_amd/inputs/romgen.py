@@ -18,6 +18,13 @@ shape of a real game's frame loop:
   bytes interleaved with stores to COLUBK/COLUPF/PF0-2/GRP0/GRP1 and an
   optional store back to RAM.
 
+"Objects" cartridges also set NUSIZ modes and missile sizes, a ball size, turn
+both missiles and the ball on and strobe their positions once, give them
+motion (moved by every frame's HMOVE), let the visible stores also reach
+ENAM0/ENAM1/ENABL, and read the collision latches in the first overscan line:
+a frame in which the players met scores a point, a missile-1 hit on player 0
+changes the ball's motion, then CXCLR.
+
 "Divergent" cartridges also step the LFSR every visible line, branch on it with
 a per-branch taken probability p ~ U(0.1, 0.9), XOR it with SWCHA on the input
 line and add a random score event.  Bank-switched cartridges (F8, F6, F4: 2,
@@ -48,6 +55,8 @@ SCORE, TERM, LFSR, PPOS, CNT_LO, CNT_HI = 0xD0, 0xD1, 0xD2, 0xD3, 0xD4, 0xD5
 RAM_SRC_LO, RAM_SRC_HI = 0x80, 0xD5     # bytes the visible ops may read
 RAM_DST_LO, RAM_DST_HI = 0x80, 0xCF     # bytes the visible ops may write
 STORE_REGS = ["COLUBK", "COLUPF", "PF0", "PF1", "PF2", "GRP0", "GRP1"]
+OBJECT_STORE_REGS = STORE_REGS + ["ENAM0", "ENAM1", "ENABL"]
+HITS = 0xD6               # objects cartridges: frames in which the players met
 OPS = ["adc", "eor", "and", "lda"]
 
 # worst-case cycles of the instructions this generator emits (zp ops, stores,
@@ -68,6 +77,7 @@ class RomSpec:
     kind: str = "4k"            # a key of KINDS
     divergent: bool = False
     n_bands: int | None = None  # visible bands (192 lines split evenly)
+    objects: bool = False       # missiles, ball, NUSIZ, object motion, collision reads
 
 
 @dataclasses.dataclass
@@ -121,9 +131,10 @@ def _gen_shape(rng, divergent: bool, f8: bool, sc: bool = False, routine: bool =
     return shape
 
 
-def _fill_body(rng, shape, label: str, bank: int, n_banks: int = 2, tia_off: int = 0) -> _Body:
+def _fill_body(rng, shape, label: str, bank: int, n_banks: int = 2, tia_off: int = 0,
+               store_regs=STORE_REGS) -> _Body:
     b = _Body()
-    st_regs = list(STORE_REGS)
+    st_regs = list(store_regs)
     rng.shuffle(st_regs)
     n_st = sum(1 for it in shape["items"] if it == "st")
     st_regs = st_regs[:n_st]
@@ -233,6 +244,8 @@ def generate(spec: RomSpec) -> Rom:
             s += [f"    lda #${v:02X}", f"    sta ${a:02X}"]
         for i, d in enumerate(resp_delay):
             s += [f"    sta {T_('WSYNC')}"] + ["    nop"] * d + [f"    sta {T_(f'RESP{i}')}"]
+        if spec.objects:
+            s += objects_init()
         s += [f"    sta {T_('WSYNC')}", "    jmp frame"]
         # ---- frame loop ----
         s += ["frame:", "    lda #2", f"    sta {T_('VSYNC')}", f"    sta {T_('WSYNC')}", f"    sta {T_('WSYNC')}",
@@ -263,14 +276,49 @@ def generate(spec: RomSpec) -> Rom:
               "    lda #0", f"    sta {T_('VBLANK')}"]
         s += visible
         # overscan
-        s += ["    lda #2", f"    sta {T_('VBLANK')}", "    ldx #30", "ovs:", f"    sta {T_('WSYNC')}", "    dex",
+        s += ["    lda #2", f"    sta {T_('VBLANK')}"]
+        if spec.objects:
+            s += objects_overscan()
+        s += ["    ldx #30", "ovs:", f"    sta {T_('WSYNC')}", "    dex",
               "    bne ovs", "    jmp frame"]
         s += ["    .org $1FFA", "    .word reset, reset, reset"]
         return s
 
+    # objects cartridges: drawn from a generator of their own, so the other
+    # kinds stay byte-identical
+    orng = _rng(spec.seed + 0x0B1EC7)
+    o_nusiz = [int(x) for x in orng.integers(0, 8, 2) | (orng.integers(0, 4, 2) << 4)]
+    o_ball = int(orng.integers(0, 4)) << 4
+    o_delay = [int(x) for x in orng.integers(10, 34, 3)]
+    o_hm = [int(x) << 4 for x in orng.integers(0, 16, 3)]
+
+    def objects_init() -> list[str]:
+        """NUSIZ modes and missile sizes, ball size, missiles and ball on,
+        their positions strobed on lines of their own, their motion."""
+        s = [f"    lda #${o_nusiz[0]:02X}", f"    sta {T_('NUSIZ0')}", f"    lda #${o_nusiz[1]:02X}",
+             f"    sta {T_('NUSIZ1')}", f"    lda #${(ctrlpf | o_ball):02X}", f"    sta {T_('CTRLPF')}",
+             "    lda #2", f"    sta {T_('ENAM0')}", f"    sta {T_('ENAM1')}", f"    sta {T_('ENABL')}"]
+        for reg, d in zip(("RESM0", "RESM1", "RESBL"), o_delay):
+            s += [f"    sta {T_('WSYNC')}"] + ["    nop"] * d + [f"    sta {T_(reg)}"]
+        for reg, v in zip(("HMM0", "HMM1", "HMBL"), o_hm):
+            s += [f"    lda #${v:02X}", f"    sta {T_(reg)}"]
+        return s
+
+    def objects_overscan() -> list[str]:
+        """First overscan line: a frame in which the players met scores a
+        point (BCD) and counts at $D6; a missile hit on player 0 moves the
+        ball's motion; then CXCLR."""
+        s = ["    lda CXPPMM", "    bpl cx_np", "    sed", "    clc", f"    lda ${SCORE:02X}", "    adc #1",
+             f"    sta ${SCORE:02X}", "    cld", f"    inc ${HITS:02X}", "cx_np:", "    lda CXM1P", "    bpl cx_nm",
+             f"    lda ${HITS:02X}", f"    sta {T_('HMBL')}", "cx_nm:", f"    sta {T_('CXCLR')}"]
+        # lda 2, sta 3, then 3+2+2+2+3+2+3+2+5 + 3+2+3+3 + 3, ldx 2, sta WSYNC 3
+        assert 2 + 3 + 32 + 11 + 3 + 2 + 3 <= LINE_BUDGET + 3
+        return s
+
     def band_lines(bank: int, k: int, prefix: int) -> list[str]:
         brng = _rng(body_seeds[bank * n_bands + k])
-        body = _fill_body(brng, shapes[k], f"b{k}", bank, banks, tia)
+        body = _fill_body(brng, shapes[k], f"b{k}", bank, banks, tia,
+                          OBJECT_STORE_REGS if spec.objects else STORE_REGS)
         assert prefix + body.cycles <= LINE_BUDGET, (k, prefix + body.cycles)
         return [f"band{k}:"] + body.lines + [f"    sta {T_('WSYNC')}", "    dex", f"    bne band{k}"]
 
@@ -328,7 +376,7 @@ def generate(spec: RomSpec) -> Rom:
         fixed_part = fixed[4096 - sl_bytes:] if e0 else fixed[2048:]
         data = b"".join(bytes(x) for x in slices) + fixed_part
         frame_label = syms0["frame"]
-    manifest = dict(seed=spec.seed, kind=spec.kind, divergent=spec.divergent, n_bands=n_bands,
+    manifest = dict(seed=spec.seed, kind=spec.kind, divergent=spec.divergent, objects=spec.objects, n_bands=n_bands,
                     T=T, ctrlpf=ctrlpf, lfsr0=lfsr0, resp_delay=resp_delay,
                     thresholds=[sh.get("thr") for sh in shapes], frame_label=frame_label)
     return Rom(spec=spec, data=data, scheme=scheme, manifest=manifest)

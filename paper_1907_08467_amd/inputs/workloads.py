@@ -32,6 +32,7 @@ class Workload:
     rng_seed: int = 0
     counts: list | None = None      # envs per ROM (None = even split)
     assign_seed: int | None = None  # shuffle env ids across ROMs
+    collisions: bool = False        # collision latches tracked
 
     def roms(self):
         return [generate(s) for s in self.rom_specs]
@@ -89,6 +90,10 @@ def config(c: int) -> Workload:
         return Workload("mixed schemes: 36864 envs, 9 ROMs (every cartridge scheme), sticky 0.25, render last 2",
                         36864, specs, 2000, action_seed=6, sticky_threshold=0x40000000,
                         render_mode=RENDER_LAST2, rng_seed=6, assign_seed=106)
+    if c == 7:
+        return Workload("objects: 4096 envs, 1 objects ROM 4KB (missiles, ball, NUSIZ, object motion, "
+                        "collision reads), frameskip 4, render all, collisions tracked",
+                        4096, [RomSpec(7000, objects=True)], 10000, action_seed=7, rng_seed=7, collisions=True)
     if c == 5:
         return Workload("serving: 131072 resident envs, 16 ROMs Zipf 1.2", 131072, _mixed16(4),
                         0, action_seed=5, render_mode=RENDER_LAST2, rng_seed=5,

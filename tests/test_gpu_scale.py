@@ -43,7 +43,7 @@ def run_sampled(c, steps, per_rom, check_every):
     roms = [(r.data, r.scheme) for r in w.roms()]
     env_rom = w.env_rom()
     cfg = dict(frameskip=w.frameskip, sticky_threshold=w.sticky_threshold, seed=w.rng_seed,
-               render_mode=w.render_mode)
+               render_mode=w.render_mode, collisions=w.collisions)
     g = VcsEnv(roms, env_rom, GRAY, **cfg)
     o = oracle.Oracle(w.n_envs, GRAY, **cfg)
     o.load_roms(roms)
@@ -124,6 +124,12 @@ def test_plain_batch_4096_all_envs_states():
         a_, b_ = g.get_state(e), o.get_state(e)
         assert np.array_equal(a_, b_), f"state of env {e}: {diff_records(a_, b_)}"
     say(f"all {w.n_envs} env states agree after {steps} steps")
+
+
+def test_objects_4096_sampled():
+    """4096 envs of a cartridge with missiles, ball, NUSIZ copies, object
+    motion and collision reads that score, latches tracked, every frame."""
+    run_sampled(7, steps=40, per_rom=96, check_every=20)
 
 
 def test_mixed_schemes_36864_sampled():

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from fuzzcart import S_3F, S_E0, S_F8, S_F6SC, S_4K, fuzz_cart
-from helpers import cart, diff_records
+from helpers import cart, decode, diff_records
 from parity import make_pair, step_both
 
 pytestmark = pytest.mark.gpu
@@ -176,5 +176,32 @@ def test_untracked_latches_read_zero():
         step_both(o, g, np.zeros(n, np.uint8), want_frames=True, tag=f"untracked step {s}")
         compare_all(o, g, n, f"untracked step {s}")
     assert not o.get_state(0)[228:230].any()
+    g.close()
+    o.close()
+
+
+OBJ_CASES = [(7000, "4k", 0, True), (7001, "4k", 1, True), (7002, "f8", 0, True), (7003, "4k", 0, False)]
+
+
+@pytest.mark.parametrize("seed,kind,mode,track", OBJ_CASES, ids=[f"{c[0]}_{c[1]}_r{c[2]}_t{int(c[3])}" for c in OBJ_CASES])
+def test_objects_cartridges(seed, kind, mode, track):
+    """Generated objects cartridges (missiles, ball, NUSIZ copies, motion,
+    latch reads that score) with several ROMs per launch: rewards, frames and
+    states every step."""
+    from paper_1907_08467_amd.inputs.romgen import RomSpec, generate
+    roms = [generate(RomSpec(seed + 10 * k, kind, k == 1, objects=True)) for k in range(3)]
+    n = 3 * 32
+    env_rom = (np.arange(n) % 3).astype(np.uint16)
+    say(f"case: objects cartridges seed {seed} kind {kind} render_mode {mode} collisions {track}")
+    o, g = make_pair([(r.data, r.scheme) for r in roms], env_rom, seed=seed, frameskip=4, render_mode=mode,
+                     collisions=track)
+    rng = np.random.default_rng(seed)
+    for s in range(30):
+        step_both(o, g, rng.integers(0, 18, n), want_frames=True, tag=f"objects step {s}")
+        if s % 10 == 9:
+            compare_all(o, g, n, f"objects step {s}")
+    hits = sum(int(decode(o.get_state(e))["ram"][0x56]) for e in range(n))     # $D6: frames the players met
+    assert (hits > 0) == track
+    assert g.poll_errors() == o.poll_errors()
     g.close()
     o.close()

@@ -19,8 +19,9 @@ from paper_1907_08467_amd.inputs.romgen import RomSpec, generate
 
 
 @pytest.mark.parametrize("spec", [RomSpec(1000), RomSpec(2000), RomSpec(3000, "4k", True),
-                                  RomSpec(3004, "f8", True), RomSpec(4001, "f8", True)],
-                         ids=lambda s: f"{s.seed}-{s.kind}-{'div' if s.divergent else 'plain'}")
+                                  RomSpec(3004, "f8", True), RomSpec(4001, "f8", True), RomSpec(7000, objects=True),
+                                  RomSpec(7001, "f8", True, objects=True)],
+                         ids=lambda s: f"{s.seed}-{s.kind}-{'div' if s.divergent else 'plain'}{'-obj' if s.objects else ''}")
 def test_generated_rom_frame_invariants(spec):
     rom = generate(spec)
     rng = np.random.default_rng(spec.seed)
@@ -262,7 +263,7 @@ def test_all_workload_cartridges_keep_ntsc_frames():
     """Every cartridge of the workloads: 262-line frames, no faults."""
     from paper_1907_08467_amd.inputs.workloads import config
     seen = set()
-    for c in (1, 2, 3, 4, 6):
+    for c in (1, 2, 3, 4, 6, 7):
         for spec in config(c).rom_specs:
             if spec.seed in seen:
                 continue
@@ -273,3 +274,19 @@ def test_all_workload_cartridges_keep_ntsc_frames():
             st, _, ends, got = oracle.run_frames(st, rom.data, 12, rom.scheme, actions=acts, render=False)
             assert got == 12 and decode(st)["err"] == 0
             assert (np.diff(ends.astype(np.int64))[1:] == 19912).all(), spec
+
+
+def test_objects_cartridge_collides_and_scores():
+    """An objects cartridge with tracked latches: frames show missiles and
+    the ball, the players meet in some frames (counted at $D6, each such
+    frame scoring a point), and untracked the counter stays 0."""
+    rom = generate(RomSpec(7001, objects=True))
+    acts = np.random.default_rng(3).integers(0, 18, 40).astype(np.uint8)
+    for track in (True, False):
+        st = oracle.power_on(rom.data, rom.scheme)
+        st[230] = 1 if track else 0
+        st, frames, ends, got = oracle.run_frames(st, rom.data, 40, rom.scheme, actions=acts)
+        d = decode(st)
+        assert got == 40 and d["err"] == 0
+        hits = int(d["ram"][0x56])
+        assert (hits > 0) == track, hits

@@ -719,20 +719,43 @@ __device__ __forceinline__ void cx_scan(Cpu& c, const Wave& W, int32_t row_end, 
         row_end = kRows;
         x_end = 0;
     }
+    // the last whole row this call scanned: a whole row with the same snapshot
+    // and the same writes draws the same pixels (unless an HMOVE blank falls
+    // on one of the two), so its latch bits are already in c.cx
+    uint4 pa = make_uint4(0, 0, 0, 0), pb = make_uint4(0, 0, 0, 0);
+    uint32_t pcnt = ~0u;
+    const uint32_t* pents = nullptr;
     while (c.cx_row < row_end || (c.cx_row == row_end && c.cx_x < x_end && row_end < kRows)) {
         const int32_t r = c.cx_row;
         const uint32_t xe = r < row_end ? 160u : (uint32_t)x_end;
         const uint8_t* rec = c.log + r * kRowBytes;
         const uint4 sa = reinterpret_cast<const uint4*>(rec)[0], sb = reinterpret_cast<const uint4*>(rec)[1];
-        Regs R;
-        unpack(R, sa, sb);
         const uint32_t cnt = r == c.open_row ? c.open_cnt : ((sa.w >> 24) & 0x1F);
         const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + kSnapBytes);
+        const bool whole = c.cx_x == 0 && xe == 160;
+        if (whole && cnt == pcnt) {
+            const uint32_t hmb = (sb.z >> 8) & 0xFF;
+            bool same = sa.x == pa.x && sa.y == pa.y && sa.z == pa.z && ((sa.w ^ pa.w) & 0x80FFFFFFu) == 0 &&
+                        sb.x == pb.x && sb.y == pb.y && sb.z == pb.z && sb.w == pb.w &&
+                        hmb != (uint32_t)r && hmb != (uint32_t)r + 1;
+            for (uint32_t i = 0; same && i < cnt; ++i) same = ents[i] == pents[i];
+            if (same) {
+                c.cx_row = r + 1;
+                continue;
+            }
+        }
+        Regs R;
+        unpack(R, sa, sb);
         uint32_t ei = 0, cur = (uint32_t)c.cx_x;
         while (cur < xe) {
             while (ei < cnt && (ents[ei] & 0xFF) <= cur) apply(R, ents[ei++]);
             const uint32_t nx = ei < cnt ? min((uint32_t)(ents[ei] & 0xFF), xe) : xe;
-            for (uint32_t x0 = cur & ~15u; x0 < nx; x0 += 16) {
+            // only drawn runs, and in them only the segments where two objects can meet
+            uint32_t segs = (R.outside || (rb<R_VBLANK>(R) & 2)) ? 0u : collision_segs(R);
+            segs &= ((2u << ((nx - 1) >> 4)) - 1) & ~((1u << (cur >> 4)) - 1);
+            while (segs) {
+                const uint32_t x0 = 16u * (uint32_t)__builtin_ctz(segs);
+                segs &= segs - 1;
                 uint32_t o[6], shown;
                 objects16(R, x0, (uint32_t)r, o, shown);
                 const uint32_t lo = cur > x0 ? cur - x0 : 0u, hi = nx < x0 + 16 ? nx - x0 : 16u;
@@ -740,6 +763,14 @@ __device__ __forceinline__ void cx_scan(Cpu& c, const Wave& W, int32_t row_end, 
                 c.cx |= collide16(o, shown & run);
             }
             cur = nx;
+        }
+        if (whole) {
+            pa = sa;
+            pb = sb;
+            pcnt = cnt;
+            pents = ents;
+        } else {
+            pcnt = ~0u;
         }
         if (xe == 160) {
             c.cx_row = r + 1;
@@ -929,14 +960,12 @@ struct Fast {
 __device__ __forceinline__ bool all_lanes(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
 
 // Stores the scalar path leaves to the per-lane path: VSYNC (it may end the
-// frame), the motion registers, HMOVE, HMCLR, RESMP, CXCLR, the missile and
-// ball registers, NUSIZ, VDEL, and timer writes.  Keeping them out leaves
-// the per-lane VSYNC, motion, collision and timer state untouched inside the
-// scalar loop and its store code short.
+// frame), the motion registers, HMOVE, HMCLR, RESMP, CXCLR and timer writes.
+// Keeping them out leaves the per-lane VSYNC, motion, collision and timer
+// state untouched inside the scalar loop.
 __device__ __forceinline__ bool tia_exit_reg(uint32_t reg) {
     return reg == 0x00 || (reg >= 0x20 && reg <= 0x24) || reg == 0x28 || reg == 0x29 || reg == 0x2A || reg == 0x2B ||
-           reg == 0x2C || reg == 0x04 || reg == 0x05 || (reg >= 0x12 && reg <= 0x14) || (reg >= 0x1D && reg <= 0x1F) ||
-           (reg >= 0x25 && reg <= 0x27);
+           reg == 0x2C;
 }
 __device__ __forceinline__ uint32_t fast_store_ok(uint32_t a) {
     if (a & 0x1000) return 1;                             // cartridge: bank hotspots only
@@ -948,12 +977,19 @@ __device__ __forceinline__ uint32_t fast_store_ok(uint32_t a) {
 // Store classes of a static address, kept in the predecoded ROM word of a
 // store instruction (its byte 3) so the scalar path needs no address decode.
 constexpr uint32_t SC_RAM = 0, SC_WSYNC = 1, SC_IGNORE = 2, SC_EXIT = 3, SC_CART = 4, SC_TIA = 0x20;
+// SC_TIA | code: a register stored as is; SC_TIAS | code: a position from
+// the cycle or a flags byte; SC_TIAG | code: GRP0 / GRP1 (the delayed copies)
+constexpr uint32_t SC_TIAS = 0x40, SC_TIAG = 0x60;
 // predecoded classes that depend on the cartridge: an absolute access to the
 // Superchip RAM window, and a 3F slice-select store to an ignored TIA register
 constexpr uint32_t SC_XRAM = 5, SC_3F = 6;
+// TIA store codes past the snapshot registers: ENAM0, ENAM1, ENABL, VDELP0,
+// VDELP1, VDELBL (SC_TIAS | kScFlag0 + i), written as their full byte and a
+// new flags byte
+constexpr uint32_t kScFlag0 = 26;
 
 // Class of a store to a (13 bits): RAM, WSYNC, a TIA register the scalar path
-// writes (SC_TIA | its R index), a write that changes nothing emulated, a
+// writes (SC_TIA, SC_TIAS or SC_TIAG | its code), a write that changes nothing emulated, a
 // cartridge access, or one the scalar path leaves to the per-lane path
 // (fast_store_ok).
 __device__ __forceinline__ uint32_t store_class(uint32_t a) {
@@ -964,24 +1000,25 @@ __device__ __forceinline__ uint32_t store_class(uint32_t a) {
         if (tia_exit_reg(reg)) return SC_EXIT;
         if (reg >= 0x06 && reg <= 0x0F) return SC_TIA | (reg - 0x06);
         if (reg == 0x01) return SC_TIA | R_VBLANK;
-        if (reg == 0x1B) return SC_TIA | R_GRP0;
-        if (reg == 0x1C) return SC_TIA | R_GRP1;
-        if (reg == 0x10 || reg == 0x11) return SC_TIA | (R_P0X + reg - 0x10);
-        if (reg == 0x04 || reg == 0x05 || (reg >= 0x12 && reg <= 0x14) || (reg >= 0x1D && reg <= 0x1F) ||
-            (reg >= 0x25 && reg <= 0x27))
-            return SC_EXIT;   // NUSIZ, RESM, RESBL, ENAM, ENABL, VDEL: the per-lane path
+        if (reg == 0x04 || reg == 0x05) return SC_TIA | (R_NUSIZ0 + reg - 0x04);
+        if (reg == 0x1B) return SC_TIAG | R_GRP0;
+        if (reg == 0x1C) return SC_TIAG | R_GRP1;
+        if (reg == 0x10 || reg == 0x11) return SC_TIAS | (R_P0X + reg - 0x10);
+        if (reg >= 0x12 && reg <= 0x14) return SC_TIAS | (R_M0X + reg - 0x12);
+        if (reg >= 0x1D && reg <= 0x1F) return SC_TIAS | (kScFlag0 + reg - 0x1D);
+        if (reg >= 0x25 && reg <= 0x27) return SC_TIAS | (kScFlag0 + 3 + reg - 0x25);
         return SC_IGNORE;   // audio and the rest
     }
     if (!(a & 0x200)) return SC_RAM;
     return (a & 0x14) == 0x14 ? SC_EXIT : SC_IGNORE;
 }
 
-// Write of per-lane value v to TIA register class `sc` (SC_TIA | code) at
+// Write of per-lane value v to TIA register class `sc` (SC_TIA/S/G | code) at
 // scalar cycle t, with its row-log entry.  The scalar path takes the colour,
-// playfield, control, reflection and VBLANK registers, RESP0/1 and the
-// players' graphics; the other object registers (ENAM, ENABL, VDEL, NUSIZ, RESM,
-// RESBL) go to the per-lane path, which keeps this, inlined at every store,
-// short.  A GRP0 / GRP1 entry also stands for the copy to the delayed
+// playfield, control, reflection, VBLANK and NUSIZ registers, the object
+// resets, the players' graphics and the enable and vertical-delay bits
+// (logged as the new flags byte); motion, HMOVE, RESMP and CXCLR go to the
+// per-lane path.  A GRP0 / GRP1 entry also stands for the copy to the delayed
 // registers (the other player's graphics; with GRP1, ENABL), which the
 // renderer repeats from its own state.  Returns 0, before changing anything,
 // when the row's entries are full (the per-lane path then records the error).
@@ -990,9 +1027,22 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
     const uint32_t ln = (t + 1) / 76;
     const uint32_t h = 3 * (t + 1 - 76 * ln);
     uint8_t* R = W.tia + c.tia_off;
-    const uint32_t code = sc & 0x1F;
-    uint32_t v0 = v;
-    if (code == R_P0X || code == R_P1X) v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
+    uint32_t code = sc & 0x1F;
+    uint32_t v0 = v, full = 0;
+    if (sc >= SC_TIAS && sc < SC_TIAG) {
+        if (code == R_P0X || code == R_P1X) {
+            v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
+        } else if (code >= R_M0X && code <= R_BLX) {
+            v0 = h < 68 ? 2u : (h - 68 + 4) % 160;
+        } else if (code >= kScFlag0) {       // ENAM0/1, ENABL (D1), VDELP0/1, VDELBL (D0)
+            const uint32_t i = code - kScFlag0;
+            const uint32_t k = i < 3 ? i : i + 1;
+            const uint32_t bit = i < 3 ? (v >> 1) & 1 : v & 1;
+            v0 = (R[R_FLAGS] & ~(1u << k)) | (bit << k);
+            full = R_ENAM0 + k;
+            code = R_FLAGS;
+        }
+    }
     if (F.logon) {
         // rows before the one the write lands in (its own row too when the
         // write lands in the visible part) get their snapshots first
@@ -1025,12 +1075,16 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
             }
         }
     }
-    if (code == R_GRP0) {
-        R[R_GRP1_OLD] = R[R_GRP1];
-    } else if (code == R_GRP1) {
-        R[R_GRP0_OLD] = R[R_GRP0];
-        R[R_ENABL_OLD] = R[R_ENABL];
-        R[R_FLAGS] = (uint8_t)((R[R_FLAGS] & ~8u) | ((R[R_FLAGS] & 4u) << 1));
+    if (sc >= SC_TIAG) {
+        if (code == R_GRP0) {
+            R[R_GRP1_OLD] = R[R_GRP1];
+        } else {
+            R[R_GRP0_OLD] = R[R_GRP0];
+            R[R_ENABL_OLD] = R[R_ENABL];
+            R[R_FLAGS] = (uint8_t)((R[R_FLAGS] & ~8u) | ((R[R_FLAGS] & 4u) << 1));
+        }
+    } else if (full) {
+        R[full] = (uint8_t)v;
     }
     R[code] = (uint8_t)v0;
     return 1;

@@ -180,6 +180,65 @@ __device__ __forceinline__ void objects16(const Regs& r, uint32_t x0, uint32_t r
     o[5] = missile16(rb<R_M1X>(r), ((flags >> 1) & 1) && !(rb<R_FLAGS2>(r) & 1), rb<R_NUSIZ1>(r), x0);
 }
 
+// 10-bit mask of the 16-pixel segments that pixels [start, start + width)
+// (mod 160, width <= 32) touch
+__device__ __forceinline__ uint32_t span_segs(uint32_t start, uint32_t width) {
+    const uint32_t end = start + width - 1;
+    const uint32_t from = ~((1u << (start >> 4)) - 1);
+    if (end < 160) return ((2u << (end >> 4)) - 1) & from;
+    return (0x3FFu & from) | ((2u << ((end - 160) >> 4)) - 1);
+}
+
+__device__ __forceinline__ uint32_t copies_segs(uint32_t pos, uint32_t mode, uint32_t n, uint32_t width) {
+    const uint32_t offs = copy_offsets(mode);
+    uint32_t m = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        uint32_t st = pos + ((offs >> (8 * k)) & 0xFF);
+        st = st >= 160 ? st - 160 : st;
+        m |= span_segs(st, width);
+    }
+    return m;
+}
+
+// The segments of a row where two objects can meet under registers r: where
+// the extents of two of the players, missiles and ball overlap, or one of
+// them overlaps a playfield block that is set.  Every collision pair has a
+// player, missile or ball in it, so no latch can be set elsewhere.
+__device__ __forceinline__ uint32_t collision_segs(const Regs& r) {
+    const uint32_t ctrlpf = rb<R_CTRLPF>(r), flags = rb<R_FLAGS>(r);
+    uint32_t m[5];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const uint32_t nus = i ? rb<R_NUSIZ1>(r) : rb<R_NUSIZ0>(r), mode = nus & 7;
+        const uint32_t grp = ((flags >> (4 + i)) & 1) ? (i ? rb<R_GRP1_OLD>(r) : rb<R_GRP0_OLD>(r))
+                                                     : (i ? rb<R_GRP1>(r) : rb<R_GRP0>(r));
+        const uint32_t pw = mode == 5 ? 16u : (mode == 7 ? 32u : 8u);
+        m[i] = grp ? copies_segs(i ? rb<R_P1X>(r) : rb<R_P0X>(r), mode, copy_count(mode), pw) : 0u;
+        const bool mon = ((flags >> i) & 1) && !(i ? (rb<R_FLAGS2>(r) & 1) : ((flags >> 7) & 1));
+        m[2 + i] = mon ? copies_segs(i ? rb<R_M1X>(r) : rb<R_M0X>(r), mode,
+                                     (mode == 5 || mode == 7) ? 1u : copy_count(mode), 1u << ((nus >> 4) & 3))
+                       : 0u;
+    }
+    const bool bl_on = (((flags >> 6) & 1) ? (flags >> 3) : (flags >> 2)) & 1;
+    m[4] = bl_on ? span_segs(rb<R_BLX>(r), 1u << ((ctrlpf >> 4) & 3)) : 0u;
+    uint32_t one = 0, two = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        two |= one & m[i];
+        one |= m[i];
+    }
+    uint32_t pf = 0;                               // segments with a playfield block set
+#pragma unroll
+    for (int k = 0; k < 5; ++k) pf |= (((r.pfm >> (4 * k)) & 0xF) != 0 ? 1u : 0u) << k;
+    if (!(ctrlpf & 1)) {
+        pf |= pf << 5;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) pf |= ((pf >> (4 - j)) & 1) << (5 + j);
+    }
+    return two | (one & pf);
+}
+
 // collision latch bits for the pixels in `px` (a 16-bit mask)
 __device__ __forceinline__ uint32_t collide16(const uint32_t (&o)[6], uint32_t px) {
     const uint32_t pf = o[0] & px, bl = o[1] & px, p0 = o[2] & px, p1 = o[3] & px, m0 = o[4] & px, m1 = o[5] & px;

@@ -19,7 +19,7 @@ from parity import make_pair, step_both
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(S_4K, False, 0), (S_4K, True, 0), (S_F8, True, 1), (S_F6SC, False, 1), (S_E0, True, 0),
+CASES = [(S_4K, False, 0), (S_4K, True, 0), (S_4K, False, 1), (S_F8, True, 1), (S_F8, False, 0), (S_F6SC, False, 1), (S_E0, True, 0),
          (S_3F, True, 1)]
 
 

@@ -205,3 +205,78 @@ def test_objects_cartridges(seed, kind, mode, track):
     assert g.poll_errors() == o.poll_errors()
     g.close()
     o.close()
+
+
+def objects_roms():
+    from paper_1907_08467_amd.inputs.romgen import RomSpec, generate
+    return [(r.data, r.scheme) for r in (generate(RomSpec(7100 + k, "4k" if k % 2 == 0 else "f8", k >= 2, objects=True))
+                                         for k in range(4))]
+
+
+@pytest.mark.parametrize("pipes", [1, 2])
+def test_collisions_graph_replays(pipes):
+    """Captured steps with tracked latches and only the last two frames
+    rendered (the other frames log to the pipelines' scratch logs): every
+    replay equals the oracle's steps, with eager steps and other device work
+    between replays."""
+    import torch
+    n = 160
+    say(f"case: collisions, captured 3-step graph, {n} envs, pipelines {pipes}")
+    env_rom = (np.arange(n) % 4).astype(np.uint16)
+    o, g = make_pair(objects_roms(), env_rom, gpu_kw={"pipelines": pipes}, seed=31, render_mode=1,
+                     collisions=True)
+    g.set_launch(16, 0, 256)
+    rng = np.random.default_rng(8)
+    graph = g.capture(n=n, steps=3, want_frames=True)
+    side = torch.zeros(1 << 20, device="cuda")
+    for rep in range(4):
+        acts = rng.integers(0, 18, (3, n)).astype(np.uint8)
+        obs, rew, done, frames = graph.launch(torch.from_numpy(acts).cuda())
+        side.add_(1.0)
+        torch.cuda.synchronize()
+        for j in range(3):
+            oo, orr, od, of = o.step(acts[j], want_frames=True)
+            tag = f"collisions graph replay {rep} step {j}"
+            assert np.array_equal(done[j].cpu().numpy(), od), tag + ": done"
+            assert np.array_equal(rew[j].cpu().numpy(), orr), tag + ": reward"
+            assert np.array_equal(obs[j].cpu().numpy(), oo), tag + ": obs"
+            assert np.array_equal(frames[j].cpu().numpy(), of), tag + ": frames"
+        compare_all(o, g, n, f"after replay {rep}")
+        step_both(o, g, rng.integers(0, 18, n), want_frames=False, tag=f"eager step after replay {rep}")
+    graph.close()
+    assert g.poll_errors() == o.poll_errors()
+    g.close()
+    o.close()
+
+
+def test_collisions_pipelines_overlap():
+    """Two pipelines on two streams step disjoint env sets of objects
+    cartridges with tracked latches at the same time."""
+    import torch
+    n = 192
+    say(f"case: collisions, 2 pipelines on 2 streams, {n} envs")
+    env_rom = (np.arange(n) % 4).astype(np.uint16)
+    o, g = make_pair(objects_roms(), env_rom, gpu_kw={"pipelines": 2}, seed=6, render_mode=1, collisions=True)
+    g.set_launch(8, 0, 256)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    rng = np.random.default_rng(19)
+    for k in range(6):
+        perm = rng.permutation(n).astype(np.int32)
+        ids_a, ids_b = perm[:90], perm[90:180]
+        act_a, act_b = rng.integers(0, 18, 90), rng.integers(0, 18, 90)
+        ra = g.step(torch.from_numpy(act_a.astype(np.uint8)).cuda(), env_ids=ids_a, pipe=0, stream=s1,
+                    want_frames=True)
+        rb = g.step(torch.from_numpy(act_b.astype(np.uint8)).cuda(), env_ids=ids_b, pipe=1, stream=s2,
+                    want_frames=True)
+        torch.cuda.synchronize()
+        for ids, act, res, name in ((ids_a, act_a, ra, "a"), (ids_b, act_b, rb, "b")):
+            oo, orr, od, of = o.step(act, env_ids=ids, want_frames=True)
+            tag = f"collisions pipelines step {k} half {name}"
+            assert np.array_equal(res[2].cpu().numpy(), od), tag + ": done"
+            assert np.array_equal(res[1].cpu().numpy(), orr), tag + ": reward"
+            assert np.array_equal(res[0].cpu().numpy(), oo), tag + ": obs"
+            assert np.array_equal(res[3].cpu().numpy(), of), tag + ": frames"
+    compare_all(o, g, n, "after pipelined steps")
+    assert g.poll_errors() == o.poll_errors()
+    g.close()
+    o.close()

@@ -3,10 +3,10 @@
 // What they compute (paper, Section 3): the "TIA kernel" that turns the
 // logged register writes into the 160x210 frame, run only for frames that are
 // needed -- the observation is the pixelwise maximum of the last two frames
-// of the step.  Unlike the paper's one-thread-per-game TIA kernel, rows and
-// pixels are drawn in parallel (the paper names this as future work): each
-// thread draws a 16-pixel segment of one row from the row's snapshot and the
-// writes logged inside it.
+// of the step.  Unlike the paper's one-thread-per-game TIA kernel, rows are
+// drawn in parallel (the paper names this as future work): each thread draws
+// one row from the row's snapshot and the writes logged inside it, 16 pixels
+// at a time, applying each write once.
 //
 // Pixel rule (TIA register semantics; the objects as in tia_draw.h): VBLANK
 // D1, an early HMOVE's blank (pixels 0-7) or a pixel outside the frame -> 0;
@@ -92,9 +92,11 @@ __device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0, uint32_t row
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// 16 pixels of row `row` starting at x0, packed little-endian into a uint4:
-// the row snapshot, then each logged write from its x position on
-__device__ __forceinline__ uint4 render_segment(const uint8_t* frame_log, int row, uint32_t x0) {
+// Row `row` drawn left to right, 16 pixels at a time: the row snapshot, then
+// each logged write from its x position on, every write applied once.
+// emit(seg, q) receives pixels 16 seg .. 16 seg + 15 packed little-endian.
+template <class Emit>
+__device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, Emit&& emit) {
     const uint8_t* rec = frame_log + row * kRowBytes;
     const uint4 s = *reinterpret_cast<const uint4*>(rec);
     const uint4 s2 = *reinterpret_cast<const uint4*>(rec + 16);
@@ -102,35 +104,41 @@ __device__ __forceinline__ uint4 render_segment(const uint8_t* frame_log, int ro
     unpack(r, s, s2);
     const uint32_t cnt = (s.w >> 24) & 0x1F;
     const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + kSnapBytes);
-    if (r.outside && cnt == 0) return make_uint4(0, 0, 0, 0);
+    if (r.outside && cnt == 0) {
+        for (int seg = 0; seg < kCols / 16; ++seg) emit(seg, make_uint4(0, 0, 0, 0));
+        return;
+    }
     uint32_t ei = 0;
     uint32_t e = cnt ? ents[0] : 0;
-    while (ei < cnt && (e & 0xFF) <= x0) {          // writes that take effect before the segment
-        apply(r, e);
-        ++ei;
-        e = ei < cnt ? ents[ei] : 0;
-    }
-    uint4 out = make_uint4(0, 0, 0, 0);
-    uint32_t start = 0;                             // first pixel of the current run
-    for (;;) {
-        const bool more = ei < cnt && (e & 0xFF) < x0 + 16;
-        const uint32_t end = more ? (e & 0xFF) - x0 : 16;
-        const uint4 px = draw16(r, x0, (uint32_t)row);
-        const uint32_t run = ((1u << end) - 1) & ~((1u << start) - 1);
-        out.x = pick(byte_masks(run & 0xF), px.x, out.x);
-        out.y = pick(byte_masks((run >> 4) & 0xF), px.y, out.y);
-        out.z = pick(byte_masks((run >> 8) & 0xF), px.z, out.z);
-        out.w = pick(byte_masks((run >> 12) & 0xF), px.w, out.w);
-        if (!more) break;
-        const uint32_t xe = e & 0xFF;
-        while (ei < cnt && (e & 0xFF) == xe) {      // every write at this pixel, in order
+    for (int seg = 0; seg < kCols / 16; ++seg) {
+        const uint32_t x0 = 16u * (uint32_t)seg;
+        while (ei < cnt && (e & 0xFF) <= x0) {      // writes that take effect before the segment
             apply(r, e);
             ++ei;
             e = ei < cnt ? ents[ei] : 0;
         }
-        start = end;
+        uint4 out = make_uint4(0, 0, 0, 0);
+        uint32_t start = 0;                         // first pixel of the current run
+        for (;;) {
+            const bool more = ei < cnt && (e & 0xFF) < x0 + 16;
+            const uint32_t end = more ? (e & 0xFF) - x0 : 16;
+            const uint4 px = draw16(r, x0, (uint32_t)row);
+            const uint32_t run = ((1u << end) - 1) & ~((1u << start) - 1);
+            out.x = pick(byte_masks(run & 0xF), px.x, out.x);
+            out.y = pick(byte_masks((run >> 4) & 0xF), px.y, out.y);
+            out.z = pick(byte_masks((run >> 8) & 0xF), px.z, out.z);
+            out.w = pick(byte_masks((run >> 12) & 0xF), px.w, out.w);
+            if (!more) break;
+            const uint32_t xe = e & 0xFF;
+            while (ei < cnt && (e & 0xFF) == xe) {  // every write at this pixel, in order
+                apply(r, e);
+                ++ei;
+                e = ei < cnt ? ents[ei] : 0;
+            }
+            start = end;
+        }
+        emit(seg, out);
     }
-    return out;
 }
 
 // bytewise maximum of two packed 4 x u8 words
@@ -145,22 +153,23 @@ __device__ __forceinline__ uint32_t max4u8(uint32_t a, uint32_t b) {
 }
 
 constexpr int kSegs = kCols / 16;            // 10 segments per row
-constexpr int kFrameSegs = kRows * kSegs;    // 2100
 
 // Frames that only go to the frames output (render mode ALL, slots before the
-// last two).  grid = (n, n_slots - 2), block 64..512 threads.
-__global__ void __launch_bounds__(512) k_render_frames(RenderArgs A) {
-    const uint32_t i = blockIdx.x;
-    const int slot = blockIdx.y;
-    const StepInfo si = A.info[i];
-    const bool valid = (si.slots >> slot) & 1;
-    const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
-    uint8_t* dst = A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes;
-    for (int sidx = threadIdx.x; sidx < kFrameSegs; sidx += blockDim.x) {
-        const int row = sidx / kSegs, seg = sidx - row * kSegs;
-        const uint4 q = valid ? render_segment(lg, row, seg * 16) : make_uint4(0, 0, 0, 0);
-        *reinterpret_cast<uint4*>(dst + row * kCols + seg * 16) = q;
+// last two): one thread per row of every (env, slot) frame.  grid =
+// ceil(n * n_front * 210 / block), block 64..512 threads.
+__global__ void __launch_bounds__(512) k_render_frames(RenderArgs A, uint32_t n_front) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t fr = t / kRows, row = t - fr * kRows;
+    if (fr >= A.n * n_front) return;
+    const uint32_t i = fr / n_front, slot = fr - i * n_front;
+    const bool valid = (A.info[i].slots >> slot) & 1;
+    uint8_t* dst = A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes + row * kCols;
+    if (!valid) {
+        for (int seg = 0; seg < kSegs; ++seg) *reinterpret_cast<uint4*>(dst + seg * 16) = make_uint4(0, 0, 0, 0);
+        return;
     }
+    const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
+    render_row(lg, (int)row, [&](int seg, const uint4 q) { *reinterpret_cast<uint4*>(dst + seg * 16) = q; });
 }
 
 // The last two frame slots: frames output (optional) and the observation.
@@ -182,20 +191,25 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
         const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
         uint8_t* dst = A.frames ? A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes : nullptr;
         if (!valid && !dst) continue;
-        for (int sidx = threadIdx.x; sidx < kFrameSegs; sidx += blockDim.x) {
-            const int row = sidx / kSegs, seg = sidx - row * kSegs;
-            const uint4 q = valid ? render_segment(lg, row, seg * 16) : make_uint4(0, 0, 0, 0);
-            if (dst) *reinterpret_cast<uint4*>(dst + row * kCols + seg * 16) = q;
-            if (want_obs && valid) {
-                const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
-                uint32_t* mrow = s_m + (row * kCols + seg * 16) / 4;
+        for (int row = threadIdx.x; row < kRows; row += blockDim.x) {
+            auto emit = [&](int seg, const uint4 q) {
+                if (dst) *reinterpret_cast<uint4*>(dst + row * kCols + seg * 16) = q;
+                if (want_obs && valid) {
+                    const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+                    uint32_t* mrow = s_m + (row * kCols + seg * 16) / 4;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    uint32_t g = 0;
+                    for (int j = 0; j < 4; ++j) {
+                        uint32_t g = 0;
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) g |= (uint32_t)s_lut[((wv[j] >> (8 * b)) & 0xFF) >> 1] << (8 * b);
-                    mrow[j] = first ? g : max4u8(mrow[j], g);
+                        for (int b = 0; b < 4; ++b) g |= (uint32_t)s_lut[((wv[j] >> (8 * b)) & 0xFF) >> 1] << (8 * b);
+                        mrow[j] = first ? g : max4u8(mrow[j], g);
+                    }
                 }
+            };
+            if (valid) {
+                render_row(lg, row, emit);
+            } else {
+                for (int seg = 0; seg < kSegs; ++seg) emit(seg, make_uint4(0, 0, 0, 0));
             }
         }
         if (want_obs && valid) first = false;
@@ -227,7 +241,9 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
 }
 
 void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s) {
-    hipLaunchKernelGGL(k_render_frames, dim3(a.n, n_front_slots), dim3(block), 0, s, a);
+    const uint64_t rows = (uint64_t)a.n * n_front_slots * kRows;
+    hipLaunchKernelGGL(k_render_frames, dim3((uint32_t)((rows + block - 1) / block)), dim3(block), 0, s, a,
+                       n_front_slots);
 }
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s) {
     hipLaunchKernelGGL(k_render_obs, dim3(a.n), dim3(block), 0, s, a);

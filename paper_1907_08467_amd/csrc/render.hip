@@ -155,27 +155,29 @@ __device__ __forceinline__ uint32_t max4u8(uint32_t a, uint32_t b) {
 constexpr int kSegs = kCols / 16;            // 10 segments per row
 
 // Frames that only go to the frames output (render mode ALL, slots before the
-// last two): one thread per row of every (env, slot) frame.  grid =
-// ceil(n * n_front * 210 / block), block 64..512 threads.
-__global__ void __launch_bounds__(512) k_render_frames(RenderArgs A, uint32_t n_front) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t fr = t / kRows, row = t - fr * kRows;
-    if (fr >= A.n * n_front) return;
-    const uint32_t i = fr / n_front, slot = fr - i * n_front;
+// last two).  grid = (n, n_slots - 2), block 64..512 threads: a thread per
+// row draws into an LDS copy of the frame, which the block then writes out
+// in whole 16-byte-per-lane runs (rows written by single threads straight to
+// HBM leave partial cache lines and double the write traffic).
+__global__ void __launch_bounds__(512) k_render_frames(RenderArgs A) {
+    __shared__ uint4 s_f[kFrameBytes / 16];
+    const uint32_t i = blockIdx.x, slot = blockIdx.y;
     const bool valid = (A.info[i].slots >> slot) & 1;
-    uint8_t* dst = A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes + row * kCols;
-    if (!valid) {
-        for (int seg = 0; seg < kSegs; ++seg) *reinterpret_cast<uint4*>(dst + seg * 16) = make_uint4(0, 0, 0, 0);
-        return;
+    uint4* dst = reinterpret_cast<uint4*>(A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes);
+    if (valid) {
+        const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
+        for (int row = threadIdx.x; row < kRows; row += blockDim.x)
+            render_row(lg, row, [&](int seg, const uint4 q) { s_f[row * kSegs + seg] = q; });
     }
-    const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
-    render_row(lg, (int)row, [&](int seg, const uint4 q) { *reinterpret_cast<uint4*>(dst + seg * 16) = q; });
+    __syncthreads();
+    for (int c = threadIdx.x; c < kFrameBytes / 16; c += blockDim.x) dst[c] = valid ? s_f[c] : make_uint4(0, 0, 0, 0);
 }
 
 // The last two frame slots: frames output (optional) and the observation.
 // grid = n, block 64..512 threads.
 __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
     __shared__ uint32_t s_m[kFrameBytes / 4];   // max gray of the two frames
+    __shared__ uint4 s_f[kFrameBytes / 16];     // the frame being drawn, for the frames output
     __shared__ uint8_t s_lut[128];
     const uint32_t i = blockIdx.x;
     const StepInfo si = A.info[i];
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
         if (!valid && !dst) continue;
         for (int row = threadIdx.x; row < kRows; row += blockDim.x) {
             auto emit = [&](int seg, const uint4 q) {
-                if (dst) *reinterpret_cast<uint4*>(dst + row * kCols + seg * 16) = q;
+                if (dst) s_f[row * kSegs + seg] = q;
                 if (want_obs && valid) {
                     const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
                     uint32_t* mrow = s_m + (row * kCols + seg * 16) / 4;
@@ -214,6 +216,11 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
         }
         if (want_obs && valid) first = false;
         __syncthreads();
+        if (dst) {                            // whole runs to HBM, then the stage is free again
+            uint4* d4 = reinterpret_cast<uint4*>(dst);
+            for (int c = threadIdx.x; c < kFrameBytes / 16; c += blockDim.x) d4[c] = s_f[c];
+            __syncthreads();
+        }
     }
     if (!A.obs) return;
     if (bad || (want_obs && first)) {     // no frame to show
@@ -241,9 +248,7 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
 }
 
 void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t block, hipStream_t s) {
-    const uint64_t rows = (uint64_t)a.n * n_front_slots * kRows;
-    hipLaunchKernelGGL(k_render_frames, dim3((uint32_t)((rows + block - 1) / block)), dim3(block), 0, s, a,
-                       n_front_slots);
+    hipLaunchKernelGGL(k_render_frames, dim3(a.n, n_front_slots), dim3(block), 0, s, a);
 }
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s) {
     hipLaunchKernelGGL(k_render_obs, dim3(a.n), dim3(block), 0, s, a);

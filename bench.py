@@ -29,12 +29,13 @@ sys.path.insert(0, ROOT)
 KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 # HBM bytes per launch on the plain 4096-env step, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a 256 MiB copy's readings (read x2.000, write x1.000);
-# reported only while the kernel source is the one they were taken on
-# (sha256 prefix), otherwise null.
+# reported only while the kernel source and the headers it includes are the
+# ones they were taken on (sha256 prefix of the files concatenated), otherwise
+# null.
 MEASURED_TRAFFIC = {
-    "k_interp": ("interp.hip", "624c9e9c266bcded", (1139.0 * 2.0 + 176040.4) * 1024),
-    "k_render_frames": ("render.hip", "5c2c68120efc3504", (94335.0 * 2.0 + 268935.7) * 1024),
-    "k_render_obs": ("render.hip", "5c2c68120efc3504", (94333.4 * 2.0 + 297231.5) * 1024),
+    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "803843c1811bcf42", (1240.0 * 2.0 + 206888.8) * 1024),
+    "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "b5ba528ee6bcec1e", (123786.5 * 2.0 + 268800.0) * 1024),
+    "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "b5ba528ee6bcec1e", (107944.9 * 2.0 + 297253.2) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
@@ -102,12 +103,15 @@ def cpu_baseline(w, roms, env_rom, steps):
 
 def measured_traffic(kernel):
     import hashlib
-    src, sha, nbytes = MEASURED_TRAFFIC[kernel]
-    path = os.path.join(ROOT, "paper_1907_08467_amd", "csrc", src)
-    if not os.path.exists(path):
-        return None
-    with open(path, "rb") as f:
-        return nbytes if hashlib.sha256(f.read()).hexdigest()[:16] == sha else None
+    srcs, sha, nbytes = MEASURED_TRAFFIC[kernel]
+    h = hashlib.sha256()
+    for src in srcs:
+        path = os.path.join(ROOT, "paper_1907_08467_amd", "csrc", src)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return nbytes if h.hexdigest()[:16] == sha else None
 
 
 def select_launch(env, args, n, want_frames, want_obs):

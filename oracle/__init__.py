@@ -33,6 +33,7 @@ class OracleConfig(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("render_mode", ctypes.c_uint32),
         ("collisions", ctypes.c_uint32),
+        ("noop_after_copy", ctypes.c_uint32),
         ("gray_lut", ctypes.c_uint8 * 128),
     ]
 
@@ -99,7 +100,8 @@ class Oracle:
     """Batched env API of the oracle, host arrays in and out."""
 
     def __init__(self, num_envs, gray_lut, frameskip=4, sticky_threshold=0, reset_cache_k=30,
-                 noop_max=30, startup_frames=64, seed=0, render_mode=RENDER_ALL, collisions=False):
+                 noop_max=30, startup_frames=64, seed=0, render_mode=RENDER_ALL, collisions=False,
+                 noop_after_copy=False):
         cfg = OracleConfig()
         cfg.num_envs = num_envs
         cfg.frameskip = frameskip
@@ -110,6 +112,7 @@ class Oracle:
         cfg.seed = seed
         cfg.render_mode = render_mode
         cfg.collisions = 1 if collisions else 0
+        cfg.noop_after_copy = 1 if noop_after_copy else 0
         for i, g in enumerate(bytes(gray_lut)):
             cfg.gray_lut[i] = g
         self.cfg = cfg

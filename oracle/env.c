@@ -32,7 +32,16 @@
  *    n_k = (R(seed, r, NOOPS, k) >> 32) mod (noop_max + 1); its obs is made
  *    from the last two of those frames;
  *  - reset pick: k = (R(seed, env, RESET, episode_idx) >> 32) mod K, then
- *    episode_idx += 1 and prev_action = NOOP.
+ *    episode_idx += 1 and prev_action = NOOP;
+ *  - no-ops after the copy (config noop_after_copy, the other reading of the
+ *    cache's random no-ops): the entries hold the state startup_frames - 2
+ *    frames into the start-up (no no-ops baked in, so all K are alike); a
+ *    reset copies one, then runs 2 + n NOOP frames with
+ *    n = (R(seed, env, NOOPS_AFTER, episode_idx) >> 32) mod (noop_max + 1)
+ *    (no sticky draw, no early stop, the step counter unchanged), and the
+ *    observation comes from the last two of them.  Since the start-up frames
+ *    are NOOP frames too, the env then holds exactly the state of power-on,
+ *    1 + startup_frames + n frames.
  *  RNG: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), used counter-based:
  *  R(seed, id, purpose, n) = mix(mix(mix(mix(seed + G) ^ id) ^ (purpose << 48)) ^ n).
  */
@@ -48,6 +57,7 @@
 #define STICKY 1
 #define RESET 2
 #define NOOPS 3
+#define NOOPS_AFTER 4
 
 static const uint64_t GAMMA = 0x9E3779B97F4A7C15ULL;
 
@@ -132,7 +142,7 @@ struct oracle_ctx {
 
 int oracle_create(const oracle_config* cfg, oracle_ctx** out) {
     if (!cfg || !out || cfg->num_envs == 0 || cfg->frameskip == 0 || cfg->reset_cache_k == 0 ||
-        cfg->render_mode > 1)
+        cfg->render_mode > 1 || (cfg->noop_after_copy && cfg->startup_frames < 2))
         return ORC_E_INVAL;
     oracle_ctx* c = (oracle_ctx*)calloc(1, sizeof(*c));
     if (!c) return ORC_E_NOMEM;
@@ -193,6 +203,7 @@ static void build_cache_entry(oracle_ctx* c, uint32_t r, uint32_t k) {
     m_set_action(&m, 0);
     uint32_t noops = (uint32_t)((oracle_rng(c->cfg.seed, r, NOOPS, k) >> 32) % (c->cfg.noop_max + 1));
     uint32_t total = 1 + c->cfg.startup_frames + noops;   /* frame 0 + start-up + no-ops */
+    if (c->cfg.noop_after_copy) total = 1 + c->cfg.startup_frames - 2;   /* the reset runs the rest */
     uint8_t* fb[2];
     fb[0] = (uint8_t*)malloc(2 * 210 * 160);
     fb[1] = fb[0] + 210 * 160;
@@ -217,8 +228,10 @@ static void build_cache_entry(oracle_ctx* c, uint32_t r, uint32_t k) {
     free(fb[0]);
 }
 
-/* Copy a cache entry into env e (eager reset) and return the cache obs. */
-static void reset_env(oracle_ctx* c, uint32_t e, uint8_t* obs_out) {
+/* Copy a cache entry into env e (eager reset) and return the cache obs; with
+   no-ops after the copy, run them and return the obs of their last two
+   frames.  Returns the error bits of those frames. */
+static uint32_t reset_env(oracle_ctx* c, uint32_t e, uint8_t* obs_out) {
     OMachine* m = &c->envs[e];
     uint32_t r = m->rom_id;
     uint32_t K = c->cfg.reset_cache_k;
@@ -236,7 +249,27 @@ static void reset_env(oracle_ctx* c, uint32_t e, uint8_t* obs_out) {
     m->prev_action = 0;
     m->err = 0;
     m_set_action(m, 0);
-    if (obs_out) memcpy(obs_out, rom->cache_obs + (size_t)k * 84 * 84, 84 * 84);
+    if (!c->cfg.noop_after_copy) {
+        if (obs_out) memcpy(obs_out, rom->cache_obs + (size_t)k * 84 * 84, 84 * 84);
+        return 0;
+    }
+    uint32_t n = (uint32_t)((oracle_rng(c->cfg.seed, e, NOOPS_AFTER, episode) >> 32) % (c->cfg.noop_max + 1));
+    uint32_t total = 2 + n;
+    int have[2] = {0, 0};                 /* slot s: frame total - 2 + s, emulated */
+    uint8_t* fb = (uint8_t*)calloc(2, 210 * 160);
+    for (uint32_t f = 0; f < total; f++) {
+        int slot = (int)f - (int)(total - 2);
+        m_run_frame(m, slot >= 0 ? fb + (size_t)slot * 210 * 160 : NULL, NULL);
+        if (slot >= 0) have[slot] = 1;
+        if (m->err) break;
+    }
+    if (obs_out) {
+        if (have[0] && have[1]) oracle_preprocess(fb, fb + 210 * 160, c->cfg.gray_lut, obs_out);
+        else if (have[0] || have[1]) oracle_preprocess(NULL, fb + (have[1] ? 210 * 160 : 0), c->cfg.gray_lut, obs_out);
+        else memset(obs_out, 0, 84 * 84);
+    }
+    free(fb);
+    return m->err;
 }
 
 int oracle_assign(oracle_ctx* c, const uint16_t* env_rom) {
@@ -345,7 +378,7 @@ static uint32_t step_env(oracle_ctx* c, uint32_t e, uint8_t action, uint8_t* obs
     else if (obs && k == 0)
         memset(obs, 0, 84 * 84);
     m->step_idx++;
-    if (is_done) reset_env(c, e, obs);
+    if (is_done) errs |= reset_env(c, e, obs);
     free(fb);
     return errs;
 }

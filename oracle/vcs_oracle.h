@@ -77,6 +77,8 @@ typedef struct {
     uint64_t seed;
     uint32_t render_mode;        /* ORC_RENDER_ALL or ORC_RENDER_LAST2        */
     uint32_t collisions;         /* 1: track the TIA collision latches        */
+    uint32_t noop_after_copy;    /* 1: the random no-ops run after each reset's
+                                    copy instead of being baked into the cache */
     uint8_t gray_lut[128];       /* gray value of colour index (c >> 1)       */
 } oracle_config;
 

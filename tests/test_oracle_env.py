@@ -197,3 +197,75 @@ def test_last2_frames_of_an_early_stop_are_zero():
     _, _, done, fr = o.step(np.array([0, 0], np.uint8), want_frames=True)
     assert done[0] == 1 and fr[0][0].any() and not fr[0][1].any()
     assert fr[1][0].any() and fr[1][1].any()
+
+
+def bare_run(n_frames):
+    """Power-on, then n_frames NOOP frames on the bare machine: the record and
+    the last two frames."""
+    st, frames, _, got = oracle.run_frames(oracle.power_on(ROM.data), ROM.data, n_frames)
+    assert got == n_frames
+    return st, frames
+
+
+def same_machine(a, b):
+    """Records equal but for the env bookkeeping (rom, step, episode, prev
+    action, error byte)."""
+    a, b = a.copy(), b.copy()
+    a[180:196] = b[180:196]
+    return not diff_records(a, b)
+
+
+def test_noop_after_copy_assign_reset_and_cache():
+    """No-ops after the copy: the cache holds the state two frames before the
+    end of the start-up; each reset runs 2 + n NOOP frames, n drawn from
+    R(seed, env, 4, episode) -- so an env holds exactly the bare machine after
+    1 + 64 + n frames, and the reset's obs is made from that run's last two
+    frames."""
+    o = make(6, seed=13, noop_after_copy=True, noop_max=7)
+    for k in range(30):                                      # all entries alike, 62 start-up frames in
+        st, _ = o.get_cache(0, k)
+        d = decode(st)
+        assert d["ram"][0x54] | (d["ram"][0x55] << 8) == 62
+    seen = set()
+    for e in range(6):
+        n = (oracle.rng(13, e, 4, 0) >> 32) % 8              # assign: episode 0 before the reset
+        seen.add(n)
+        st = o.get_state(e)
+        assert decode(st)["ram"][0x54] == 64 + n
+        ref, _ = bare_run(1 + 64 + n)
+        assert same_machine(st, ref)
+        assert decode(st)["step_idx"] == 0 and decode(st)["episode_idx"] == 1
+    assert len(seen) > 1
+    # an explicit reset: episode 1 -> 2, its own n, obs of the last two frames
+    ids = np.array([2, 4], np.int32)
+    obs = o.reset(ids)
+    for i, e in enumerate(ids):
+        n = (oracle.rng(13, int(e), 4, 1) >> 32) % 8
+        ref, frames = bare_run(1 + 64 + n)
+        assert same_machine(o.get_state(int(e)), ref)
+        assert np.array_equal(obs[i], oracle.preprocess(frames[-2], frames[-1], GRAY))
+        assert decode(o.get_state(int(e)))["episode_idx"] == 2
+
+
+def test_noop_after_copy_eager_reset():
+    o = make(2, seed=9, noop_after_copy=True)
+    T = ROM.manifest["T"]
+    o.step(np.array([0, 0], np.uint8))
+    st = o.get_state(1)
+    st[32 + 0x54], st[32 + 0x55] = (T - 2) & 0xFF, (T - 2) >> 8   # terminal two frames ahead
+    o.set_state(1, st)
+    ep = decode(st)["episode_idx"]
+    obs, rew, done, _ = o.step(np.array([0, 0], np.uint8))
+    assert done[1] == 1 and done[0] == 0
+    n = (oracle.rng(9, 1, 4, ep) >> 32) % 31
+    ref, frames = bare_run(1 + 64 + n)
+    after = o.get_state(1)
+    assert same_machine(after, ref)
+    assert np.array_equal(obs[1], oracle.preprocess(frames[-2], frames[-1], GRAY))
+    d = decode(after)
+    assert d["episode_idx"] == ep + 1 and d["step_idx"] == 2 and d["prev_action"] == 0
+
+
+def test_noop_after_copy_needs_two_startup_frames():
+    with pytest.raises(RuntimeError):
+        oracle.Oracle(2, GRAY, startup_frames=1, noop_after_copy=True)

@@ -105,6 +105,16 @@ typedef struct {
                                    read what the frame's pixels so far set, CXCLR
                                    clears them; every frame is then logged and scanned,
                                    at some cost); 0: they read 0 */
+    uint32_t noop_after_copy;   /* 0: the random no-op frames are baked into the
+                                   reset-cache entries (paper, Section 3: the cache
+                                   removes the per-reset frames); 1: the other
+                                   reading: the entries stop two frames before the
+                                   end of the start-up and every reset (assign,
+                                   vcs_reset, eager) runs 2 + n NOOP frames with
+                                   n = (R(seed, env, 4, episode) >> 32) mod
+                                   (noop_max + 1), no sticky draw, the step counter
+                                   unchanged; the reset's observation comes from the
+                                   last two of them.  Needs startup_frames >= 2. */
     uint8_t gray_lut[128];      /* gray level of colour index (colour >> 1)      */
 } vcs_config;
 

@@ -40,6 +40,7 @@ class VcsConfig(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("pipelines", ctypes.c_uint32),
         ("collisions", ctypes.c_uint32),
+        ("noop_after_copy", ctypes.c_uint32),
         ("gray_lut", ctypes.c_uint8 * 128),
     ]
 

@@ -45,6 +45,9 @@ struct TimedLaunch {
 struct Pipe {
     uint8_t* d_logs = nullptr;      // [max_batch][n_slots] row logs
     uint8_t* d_cxlogs = nullptr;    // [max_batch] logs of unrendered frames (tracked collisions)
+    uint16_t* d_nfpo = nullptr;     // [max_batch] no-ops after the copy: frames each reset env runs
+    uint8_t* d_nooplogs = nullptr;  // [max_batch][2] row logs of those frames' last two
+    StepInfo* d_noopinfo = nullptr; // [max_batch]
     StepInfo* d_info = nullptr;     // [max_batch]
     uint8_t* d_valid = nullptr;     // [max_batch]
     Tile* d_tiles = nullptr;        // [tiles_cap]
@@ -348,6 +351,58 @@ int check_launch(const vcs_launch* l) {
     return VCS_OK;
 }
 
+// No-ops after the copy: the envs k_reset just restarted (P.d_nfpo[i] > 0)
+// run their 2 + n NOOP frames over the same tiles (the others run none),
+// logging the last two, whose observation then goes to obs[i] for those
+// positions only.  The step counter does not advance.
+static int enqueue_noops(vcs_ctx* c, Pipe& P, const Tile* tiles, const uint32_t* n_tiles, uint32_t grid,
+                         uint32_t n, uint8_t* obs, hipStream_t s) {
+    InterpArgs ia{};
+    ia.tiles = tiles;
+    ia.n_tiles = n_tiles;
+    ia.envs = c->d_envs;
+    ia.roms = c->d_roms;
+    ia.cmap = c->d_cmap;
+    ia.pre_off = c->d_pre_off;
+    ia.pre = c->d_pre;
+    ia.actions = nullptr;
+    ia.nframes_per_out = P.d_nfpo;
+    ia.nframes = 0;
+    ia.render_all = 0;
+    ia.log_enabled = obs ? 1 : 0;
+    ia.early_stop = 0;
+    ia.sticky_thr = 0;
+    ia.frameskip = c->cfg.frameskip;
+    ia.seed = c->cfg.seed;
+    ia.logs = P.d_nooplogs;
+    ia.n_slots = 2;
+    ia.info = P.d_noopinfo;
+    ia.reward = nullptr;
+    ia.done = nullptr;
+    ia.err_word = c->d_err;
+    ia.instr_total = P.d_instr;
+    ia.queue = nullptr;
+    ia.track = c->cfg.collisions ? 1 : 0;
+    ia.cx_logs = P.d_cxlogs;
+    ia.count_step = 0;
+    launch_interp(ia, grid, c->launch.tile_envs, c->rom_lds, s);
+    if (obs) {
+        RenderArgs ra{};
+        ra.logs = P.d_nooplogs;
+        ra.n_slots = 2;
+        ra.info = P.d_noopinfo;
+        ra.frames = nullptr;
+        ra.obs = obs;
+        ra.gray = c->d_gray;
+        ra.n = n;
+        ra.force_obs = 1;
+        ra.only = P.d_nfpo;
+        launch_render_obs(ra, c->launch.render_block, s);
+    }
+    HIP_OK(hipGetLastError());
+    return VCS_OK;
+}
+
 // The emulation part of one step on stream s with the scratch of pipeline
 // `pipe` (arguments checked): counters, id validation and tiles, the
 // interpreter (frames, row logs, reward, done) and the eager reset.
@@ -395,6 +450,8 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
     ia.queue = nullptr;
     ia.track = c->cfg.collisions ? 1 : 0;
     ia.cx_logs = P.d_cxlogs;
+    ia.count_step = 1;
+    const uint32_t full_grid = grid;
     if (c->launch.workers && c->launch.workers < grid) {
         ia.queue = P.d_queue;
         grid = c->launch.workers;
@@ -417,10 +474,13 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
     rs.K = c->cfg.reset_cache_k;
     rs.seed = c->cfg.seed;
     rs.obs = obs;
+    rs.nfpo = c->cfg.noop_after_copy ? P.d_nfpo : nullptr;
+    rs.noop_max = c->cfg.noop_max;
     begin_timed(c, 3, s);
     launch_reset(rs, s);
     end_timed(c, s);
     HIP_OK(hipGetLastError());
+    if (c->cfg.noop_after_copy) return enqueue_noops(c, P, tiles, n_tiles, full_grid, n, obs, s);
     return VCS_OK;
 }
 
@@ -488,6 +548,9 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
     if (cfg->max_batch > cfg->num_envs) return fail(VCS_E_INVAL, "max_batch > num_envs");
     if (1 + cfg->startup_frames + cfg->noop_max > 65535) return fail(VCS_E_INVAL, "cache build too long");
     if (cfg->pipelines > 8) return fail(VCS_E_INVAL, "pipelines must be in [0, 8]");
+    if (cfg->noop_after_copy > 1) return fail(VCS_E_INVAL, "noop_after_copy must be 0 or 1");
+    if (cfg->noop_after_copy && cfg->startup_frames < 2)
+        return fail(VCS_E_INVAL, "noop_after_copy needs startup_frames >= 2");
     int ndev = 0;
     HIP_OK(hipGetDeviceCount(&ndev));
     if (cfg->device < 0 || cfg->device >= ndev) return fail(VCS_E_INVAL, "bad device ordinal");
@@ -512,6 +575,9 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
     for (auto& P : c->pipes) {
         if (!rc) rc = alloc_n(c, &P.d_logs, B * c->n_slots * kFrameLogBytes, "row logs");
         if (!rc && cfg->collisions) rc = alloc_n(c, &P.d_cxlogs, B * kFrameLogBytes, "collision row logs");
+        if (!rc && cfg->noop_after_copy) rc = alloc_n(c, &P.d_nfpo, B, "reset no-op frame counts");
+        if (!rc && cfg->noop_after_copy) rc = alloc_n(c, &P.d_nooplogs, B * 2 * kFrameLogBytes, "reset no-op row logs");
+        if (!rc && cfg->noop_after_copy) rc = alloc_n(c, &P.d_noopinfo, B, "reset no-op info");
         if (!rc) rc = alloc_n(c, &P.d_info, B, "step info");
         if (!rc) rc = alloc_n(c, &P.d_valid, B, "id validity");
         if (!rc) rc = alloc_n(c, &P.d_tag, 1, "claim tag");
@@ -653,6 +719,85 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     return VCS_OK;
 }
 
+// No-ops after the copy at assign time: every env runs the frame counts
+// k_reset left in d_nf, in launches of at most max_batch envs (ROM-homogeneous
+// tiles of 64 built on the host; output position = env - first env).
+static int assign_noops(vcs_ctx* c, const uint16_t* d_nf, const uint16_t* env_rom_host) {
+    const uint32_t N = c->cfg.num_envs, R = c->n_roms, C = c->max_batch;
+    Tile* d_t = nullptr;
+    StepInfo* d_info = nullptr;
+    uint32_t* d_cnt = nullptr;
+    const uint32_t cap = (C + kLanes - 1) / kLanes + R;
+    int rc = alloc_n(c, &d_t, cap, "assign no-op tiles");
+    if (!rc) rc = alloc_n(c, &d_info, C, "assign no-op info");
+    if (!rc) rc = alloc_n(c, &d_cnt, 1, "assign no-op tile count");
+    for (uint32_t c0 = 0; c0 < N && !rc; c0 += C) {
+        const uint32_t cn = std::min(C, N - c0);
+        std::vector<Tile> tl;
+        for (uint32_t r = 0; r < R; ++r) {
+            Tile t;
+            std::memset(&t, 0xFF, sizeof(t));
+            t.rom = (int32_t)r;
+            t.count = 0;
+            for (uint32_t e = c0; e < c0 + cn; ++e) {
+                if (env_rom_host[e] != r) continue;
+                t.env[t.count] = (int32_t)e;
+                t.out[t.count] = (int32_t)(e - c0);
+                if (++t.count == kLanes) {
+                    tl.push_back(t);
+                    std::memset(&t, 0xFF, sizeof(t));
+                    t.rom = (int32_t)r;
+                    t.count = 0;
+                }
+            }
+            if (t.count) tl.push_back(t);
+        }
+        const uint32_t nt = (uint32_t)tl.size();
+        if (hipMemcpy(d_t, tl.data(), (size_t)nt * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_cnt, &nt, 4, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(VCS_E_HIP, "assign no-op upload failed");
+            break;
+        }
+        InterpArgs ia{};
+        ia.tiles = d_t;
+        ia.n_tiles = d_cnt;
+        ia.envs = c->d_envs;
+        ia.roms = c->d_roms;
+        ia.cmap = c->d_cmap;
+        ia.pre_off = c->d_pre_off;
+        ia.pre = c->d_pre;
+        ia.actions = nullptr;
+        ia.nframes_per_out = d_nf + c0;
+        ia.nframes = 0;
+        ia.render_all = 0;
+        ia.log_enabled = 0;
+        ia.early_stop = 0;
+        ia.sticky_thr = 0;
+        ia.frameskip = c->cfg.frameskip;
+        ia.seed = c->cfg.seed;
+        ia.logs = nullptr;
+        ia.n_slots = 2;
+        ia.info = d_info;
+        ia.reward = nullptr;
+        ia.done = nullptr;
+        ia.err_word = c->d_err;
+        ia.instr_total = nullptr;
+        ia.queue = nullptr;
+        ia.track = c->cfg.collisions ? 1 : 0;
+        ia.cx_logs = c->pipes[0].d_cxlogs;
+        ia.count_step = 0;
+        launch_interp(ia, nt, kLanes, c->rom_lds, nullptr);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            rc = fail(VCS_E_HIP, "assign no-op frames failed");
+            break;
+        }
+    }
+    dev_free(c, d_t, (size_t)cap * sizeof(Tile));
+    dev_free(c, d_info, (size_t)C * sizeof(StepInfo));
+    dev_free(c, d_cnt, 4);
+    return rc;
+}
+
 int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     if (!c || !env_rom_host) return fail(VCS_E_INVAL, "null argument");
     if (c->n_roms == 0) return fail(VCS_E_STATE, "vcs_load_roms first");
@@ -685,7 +830,9 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
             cst[r * K + k] = p0;
             const uint64_t draw = rng_draw(rng_prefix(c->cfg.seed, r, kNoopPurpose), k);
             const uint32_t noops = (uint32_t)((draw >> 32) % (c->cfg.noop_max + 1ull));
-            nfr[r * K + k] = (uint16_t)(1 + c->cfg.startup_frames + noops);
+            // no-ops after the copy: the entry stops two frames before the start-up's end
+            nfr[r * K + k] = (uint16_t)(c->cfg.noop_after_copy ? c->cfg.startup_frames - 1
+                                                               : 1 + c->cfg.startup_frames + noops);
         }
         for (uint32_t k0 = 0; k0 < K; k0 += kLanes) {
             Tile t;
@@ -752,6 +899,7 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     ia.instr_total = nullptr;
     ia.track = c->cfg.collisions ? 1 : 0;
     ia.cx_logs = d_clog + (size_t)M * 2 * kFrameLogBytes;
+    ia.count_step = 1;
     launch_interp(ia, n_ct, kLanes, c->rom_lds, nullptr);
     RenderArgs ra{};
     ra.logs = d_clog;
@@ -803,8 +951,22 @@ int vcs_assign(vcs_ctx* c, const uint16_t* env_rom_host) {
     rs.K = K;
     rs.seed = c->cfg.seed;
     rs.obs = nullptr;
+    uint16_t* d_nf = nullptr;
+    if (c->cfg.noop_after_copy) {
+        rc = alloc_n(c, &d_nf, N, "assign no-op frame counts");
+        if (rc) return rc;
+        rs.nfpo = d_nf;
+        rs.noop_max = c->cfg.noop_max;
+    }
     launch_reset(rs, nullptr);
     HIP_OK(hipGetLastError());
+    if (c->cfg.noop_after_copy) {
+        // each env runs its no-op frames, max_batch envs per launch (the
+        // collision scratch is sized for that); no observation is kept
+        rc = assign_noops(c, d_nf, env_rom_host);
+        dev_free(c, d_nf, (size_t)N * 2);
+        if (rc) return rc;
+    }
     HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemset(c->d_err, 0, 4));
     HIP_OK(hipMemset(c->d_err + 1, 0xFF, 4));
@@ -818,6 +980,7 @@ int vcs_reset(vcs_ctx* c, const int32_t* ids, uint32_t n, uint8_t* obs, void* st
     if (n > c->max_batch) return fail(VCS_E_INVAL, "n exceeds max_batch");
     if (n == 0) return VCS_OK;
     hipStream_t s = (hipStream_t)stream;
+    Pipe& P = c->pipes[0];
     ResetArgs rs{};
     rs.envs = c->d_envs;
     rs.ids = ids;
@@ -825,8 +988,20 @@ int vcs_reset(vcs_ctx* c, const int32_t* ids, uint32_t n, uint8_t* obs, void* st
     rs.num_envs = c->cfg.num_envs;
     rs.info = nullptr;
     rs.valid = nullptr;
-    if (ids) {
-        Pipe& P = c->pipes[0];
+    const Tile* tiles = c->d_tiles_all;
+    const uint32_t* n_tiles = c->d_n_tiles_all;
+    uint32_t grid = c->n_tiles_all;
+    if (c->cfg.noop_after_copy && (ids || n != c->cfg.num_envs)) {
+        // the no-op frames need tiles of the listed envs (validation included)
+        launch_step_begin(P.d_stepw, c->stepw_words, P.d_tag, s);
+        int rc = build_tiles(c, P, ids, n, nullptr, nullptr, s, &grid);
+        if (rc) return rc;
+        tiles = P.d_tiles;
+        n_tiles = P.d_n_tiles;
+        rs.valid = P.d_valid;
+    } else if (c->cfg.noop_after_copy) {
+        launch_step_begin(P.d_stepw + c->instr_off, c->stepw_words - c->instr_off, nullptr, s);
+    } else if (ids) {
         launch_step_begin(P.d_counts, c->n_roms, P.d_tag, s);
         launch_validate(ids, n, c->cfg.num_envs, c->d_env_rom, c->d_claim, P.d_tag, P.d_counts, P.d_valid,
                         nullptr, nullptr, nullptr, c->d_err, s);
@@ -837,10 +1012,13 @@ int vcs_reset(vcs_ctx* c, const int32_t* ids, uint32_t n, uint8_t* obs, void* st
     rs.K = c->cfg.reset_cache_k;
     rs.seed = c->cfg.seed;
     rs.obs = obs;
+    rs.nfpo = c->cfg.noop_after_copy ? P.d_nfpo : nullptr;
+    rs.noop_max = c->cfg.noop_max;
     begin_timed(c, 3, s);
     launch_reset(rs, s);
     end_timed(c, s);
     HIP_OK(hipGetLastError());
+    if (c->cfg.noop_after_copy) return enqueue_noops(c, P, tiles, n_tiles, grid, n, obs, s);
     return VCS_OK;
 }
 

@@ -91,6 +91,7 @@ __global__ void k_tile_fill(const int32_t* ids, uint32_t n, const uint16_t* env_
 __global__ void __launch_bounds__(64) k_reset(ResetArgs A) {
     const uint32_t i = blockIdx.x;
     if (i >= A.n) return;
+    if (A.nfpo && threadIdx.x == 0) A.nfpo[i] = 0;    // set below for a reset env
     if (A.valid && !A.valid[i]) {
         if (A.obs)
             for (int j = threadIdx.x; j < kObsBytes / 16; j += blockDim.x)
@@ -123,6 +124,13 @@ __global__ void __launch_bounds__(64) k_reset(ResetArgs A) {
             q.w &= 0xFFFFFF00u;
         }
         d4[threadIdx.x] = q;
+    }
+    if (A.nfpo) {       // no-ops after the copy: 2 + n frames to run, the obs comes from them
+        if (threadIdx.x == 0) {
+            const uint64_t d2 = rng_draw(rng_prefix(A.seed, (uint64_t)e, kNoopAfterPurpose), episode);
+            A.nfpo[i] = (uint16_t)(2 + (d2 >> 32) % ((uint64_t)A.noop_max + 1));
+        }
+        return;
     }
     if (A.obs) {
         const uint4* os = reinterpret_cast<const uint4*>(A.cache_obs + ((size_t)rom * A.K + k) * kObsBytes);

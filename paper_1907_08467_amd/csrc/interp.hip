@@ -1723,6 +1723,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             W.tia[c.tia_off + R_HMB] = 0;          // an earlier frame's blanked row is not this frame's
         };
 
+        if (nfr == 0) active = false;            // nothing to run (reset no-op frames of other envs)
         if (active) {
             if (act >= 18) {
                 c.err |= ERR_BAD_ACTION;
@@ -1889,7 +1890,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             E->instr += c.icount;
             E->prev_action = prev_action;
             E->err = c.err;
-            E->step_idx = step_idx + 1;
+            E->step_idx = step_idx + (A.count_step ? 1u : 0u);
             StepInfo si;
             si.k = (uint8_t)k;
             si.done = (uint8_t)done;

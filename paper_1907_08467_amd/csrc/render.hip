@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
     __shared__ uint4 s_f[kFrameBytes / 16];     // the frame being drawn, for the frames output
     __shared__ uint8_t s_lut[128];
     const uint32_t i = blockIdx.x;
+    if (A.only && A.only[i] == 0) return;        // not one of the positions asked for
     const StepInfo si = A.info[i];
     const bool bad = (si.err & ERR_BAD_ID) != 0;
     const bool want_obs = A.obs && !bad && (A.force_obs || !si.done);

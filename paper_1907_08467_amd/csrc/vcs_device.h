@@ -173,6 +173,7 @@ struct InterpArgs {
     uint32_t* queue;          // NULL: workgroup b runs tile b; else workgroups take
                               // tiles from this counter until it passes *n_tiles
     uint32_t track;           // collision latches tracked
+    uint32_t count_step;      // 1: the env's step counter advances (0: reset no-op frames)
     uint8_t* cx_logs;         // [n outputs][kFrameLogBytes]: logs of frames not rendered (track)
 };
 
@@ -189,7 +190,7 @@ __host__ __device__ inline uint64_t rng_prefix(uint64_t seed, uint64_t id, uint6
     return mix64(mix64(mix64(seed + kGamma) ^ id) ^ (purpose << 48));
 }
 __host__ __device__ inline uint64_t rng_draw(uint64_t prefix, uint64_t n) { return mix64(prefix ^ n); }
-constexpr uint64_t kStickyPurpose = 1, kResetPurpose = 2, kNoopPurpose = 3;
+constexpr uint64_t kStickyPurpose = 1, kResetPurpose = 2, kNoopPurpose = 3, kNoopAfterPurpose = 4;
 
 struct RenderArgs {
     const uint8_t* logs;      // [n][n_slots][kFrameLogBytes]
@@ -200,6 +201,7 @@ struct RenderArgs {
     const uint8_t* gray;      // [128]
     uint32_t n;
     uint32_t force_obs;       // also for envs that ended (cache build)
+    const uint16_t* only;     // NULL, or only positions with only[i] > 0 get an observation
 };
 
 struct ResetArgs {
@@ -214,6 +216,10 @@ struct ResetArgs {
     uint32_t K;
     uint64_t seed;
     uint8_t* obs;                // [n][84][84] or NULL
+    uint16_t* nfpo;              // NULL, or no-ops after the copy: [n] frames each position's
+                                 // env must run next (2 + n drawn for a reset one, else 0);
+                                 // the cache obs is then not copied
+    uint32_t noop_max;
 };
 
 // host launchers (one per kernel)

@@ -17,7 +17,7 @@ class VcsEnv:
 
     def __init__(self, roms, env_rom, gray_lut, frameskip=4, sticky_threshold=0, reset_cache_k=30,
                  noop_max=30, startup_frames=64, seed=0, render_mode=B.VCS_RENDER_ALL, max_batch=0,
-                 hbm_budget_bytes=0, device=0, pipelines=1, collisions=False):
+                 hbm_budget_bytes=0, device=0, pipelines=1, collisions=False, noop_after_copy=False):
         env_rom = np.ascontiguousarray(env_rom, dtype=np.uint16)
         cfg = B.VcsConfig()
         cfg.num_envs = int(env_rom.shape[0])
@@ -33,6 +33,7 @@ class VcsEnv:
         cfg.device = device
         cfg.pipelines = pipelines
         cfg.collisions = 1 if collisions else 0
+        cfg.noop_after_copy = 1 if noop_after_copy else 0
         for i, g in enumerate(bytes(gray_lut)):
             cfg.gray_lut[i] = g
         self.num_envs = cfg.num_envs

@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
-    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference", "schemes", "objects"], default="plain",
+    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference", "schemes", "objects", "noops"], default="plain",
                    help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
                         "serve: 131072 resident envs behind the env server; divergent: 32768 envs over 8 "
                         "branchy ROMs with sticky actions, with the per-step rate over the run; stack: the frame "
@@ -341,7 +341,7 @@ def bench_batching(args):
     }
 
 
-def bench_divergent(args):
+def bench_divergent(args, noop_after_copy=False, keep_step_ms=False):
     """32768 envs over 8 divergent ROMs (4 x 4 KB, 4 x F8), sticky actions
     p = 0.25, every frame rendered: raw frames/s and the per-step time over the
     run (the paper's FPS-against-step curve: envs start in step from the reset
@@ -350,7 +350,7 @@ def bench_divergent(args):
     from paper_1907_08467_amd.inputs.workloads import config
     w = config(3)
     n, K = w.n_envs, args.steps
-    env, roms, env_rom = gpu_env(w)
+    env, roms, env_rom = gpu_env(w, noop_after_copy=noop_after_copy)
     dev = torch.device("cuda", 0)
     launch, launch_from = select_launch(env, args, n, True, True)
     env.reset()                                # every env back to a cache state: the curve starts correlated
@@ -382,7 +382,25 @@ def bench_divergent(args):
                    "launch": launch, "launch_from": launch_from},
         "fps_by_step": {str(s): n * w.frameskip / (ms[s] * 1e-3) for s in pts},
         "errors": bits, "roofline": None, "cpu_baseline": None,
+        **({"step_ms": ms} if keep_step_ms else {}),
     }
+
+
+def bench_noops(args):
+    """The divergent workload with the reset no-ops run after each copy
+    (every reset then emulates 2 + n, n <= 30, NOOP frames inside the step)
+    against the same run with the no-ops baked into the cache (the paper's
+    design): raw frames/s, mean and longest step time of both."""
+    base = bench_divergent(args, keep_step_ms=True)
+    res = bench_divergent(args, noop_after_copy=True, keep_step_ms=True)
+    ms_b, ms_v = base.pop("step_ms"), res.pop("step_ms")
+    res["config"]["workload"] = res["config"]["workload"].replace(
+        "eager steps from a fresh reset", "eager steps from a fresh reset; reset no-ops (0-30 frames) run after "
+        "each reset's cache copy instead of being baked into the cache")
+    res["baked_noops"] = {"value": base["value"], "ms_per_step": base["ms_per_step"]}
+    res["mean_step_ms"] = {"noops_after_copy": sum(ms_v) / len(ms_v), "baked": sum(ms_b) / len(ms_b)}
+    res["max_step_ms"] = {"noops_after_copy": max(ms_v), "baked": max(ms_b)}
+    return res
 
 
 def cpu_baseline_sample(w, roms, env_rom, per_rom, steps):
@@ -669,7 +687,7 @@ def main():
         sys.exit(2)
     fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
           "divergent": bench_divergent, "stack": bench_stack, "inference": bench_inference,
-          "schemes": bench_schemes, "objects": lambda a: bench_plain(a, 7)}[args.workload]
+          "schemes": bench_schemes, "objects": lambda a: bench_plain(a, 7), "noops": bench_noops}[args.workload]
     print(json.dumps(fn(args)))
 
 

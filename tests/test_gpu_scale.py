@@ -35,7 +35,7 @@ def sample_envs(env_rom, per_rom, seed):
     return np.array(sorted(out), np.int32)
 
 
-def run_sampled(c, steps, per_rom, check_every):
+def run_sampled(c, steps, per_rom, check_every, **extra):
     import torch
     from paper_1907_08467_amd.env import VcsEnv
     w = config(c)
@@ -43,7 +43,7 @@ def run_sampled(c, steps, per_rom, check_every):
     roms = [(r.data, r.scheme) for r in w.roms()]
     env_rom = w.env_rom()
     cfg = dict(frameskip=w.frameskip, sticky_threshold=w.sticky_threshold, seed=w.rng_seed,
-               render_mode=w.render_mode, collisions=w.collisions)
+               render_mode=w.render_mode, collisions=w.collisions, **extra)
     g = VcsEnv(roms, env_rom, GRAY, **cfg)
     o = oracle.Oracle(w.n_envs, GRAY, **cfg)
     o.load_roms(roms)
@@ -90,6 +90,13 @@ def test_plain_batch_4096_sampled():
 def test_divergent_32768_sampled():
     """32768 envs over 8 ROMs (4 KB and F8), sticky actions p = 0.25."""
     run_sampled(3, steps=40, per_rom=12, check_every=20)
+
+
+def test_divergent_32768_noops_after_copy_sampled():
+    """The divergent configuration with the reset no-ops run after each copy:
+    assign-time no-ops for all 32768 envs (in launches of max_batch), then
+    150 steps, long enough for episodes of the sampled envs to end."""
+    run_sampled(3, steps=150, per_rom=8, check_every=50, noop_after_copy=True)
 
 
 def test_batching_65536_sampled():

@@ -62,6 +62,9 @@ def parse():
                         "schemes: 36864 envs over one ROM of every cartridge scheme")
     p.add_argument("--serve-seconds", type=float, default=20.0)
     p.add_argument("--serve-pipelines", type=int, default=3)
+    p.add_argument("--serve-open-waits", type=float, nargs="*", default=[128.0, 64.0, 32.0, 16.0],
+                   help="open-loop mean gaps between a client's requests (ms), one curve point each")
+    p.add_argument("--serve-open-seconds", type=float, default=3.0)
     p.add_argument("--graph", type=int, default=4,
                    help="plain workload: time steps captured G at a time in HIP graphs (two pipelines, each step's "
                         "render overlapping the next step's interpreter) after the eager steps, and report them as "
@@ -95,10 +98,33 @@ def cpu_baseline(w, roms, env_rom, steps):
         o.step(acts[s], want_frames=True)
     dt = time.perf_counter() - t0
     frames = w.n_envs * w.frameskip * steps
-    return {"value": frames / dt, "unit": "raw frames/s", "cores": oracle.get_threads(), "kind": "oracle",
+    cores = oracle.get_threads()
+    # one core: the first 256 envs for the same steps, from the same states
+    n1 = min(256, w.n_envs)
+    o1 = oracle.Oracle(n1, GRAY, frameskip=w.frameskip, seed=w.rng_seed, collisions=w.collisions)
+    o1.load_roms(roms)
+    o1.assign(env_rom[:n1])
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        for s in range(steps):
+            o1.step(acts[s][:n1], want_frames=True)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": frames / dt, "unit": "raw frames/s", "cores": cores, "kind": "oracle",
             "sample": f"{w.n_envs} envs x {steps} steps x frameskip {w.frameskip} ({frames} raw frames), "
                       f"every frame rendered + obs, same cartridge, seed and actions",
-            "seconds": dt}
+            "seconds": dt,
+            "single_core": {"value": n1 * w.frameskip * steps / dt1, "sample": f"{n1} envs x {steps} steps",
+                            "seconds": dt1},
+            "cpu_model": cpu_model, "host_cpus": os.cpu_count()}
 
 
 def measured_traffic(kernel):
@@ -659,8 +685,20 @@ def bench_serve(args):
     actors = ActorPool(64, n, mean_wait_s=2e-3, size_lo=64, size_hi=4096, seed0=5000)
     st = run_served(server, actors, seconds=args.serve_seconds)
     value = st["env_steps"] * w.frameskip / st["seconds"]
-    bits = env.poll_errors()[1]
     print(f"served: {st}", file=sys.stderr, flush=True)
+    # open loop: Poisson arrivals that do not wait for answers, from about the
+    # served capacity to four times it; the backlog left at the end is dropped
+    curve = []
+    for wait_ms in args.serve_open_waits:
+        op = ActorPool(64, n, mean_wait_s=wait_ms * 1e-3, size_lo=64, size_hi=4096, seed0=6000, open_loop=True)
+        so = run_served(EnvServer(backend, cap, n), op, seconds=args.serve_open_seconds)
+        offered = 64 / (wait_ms * 1e-3) * op.mean_size() * w.frameskip
+        curve.append({"mean_gap_ms": wait_ms, "offered_frames_s": offered,
+                      "served_frames_s": so["env_steps"] * w.frameskip / so["seconds"],
+                      "p50_ms": so["p50_ms"], "p99_ms": so["p99_ms"], "requests": so["requests"],
+                      "backlog_env_steps": so["backlog_env_steps"], "seconds": so["seconds"]})
+        print(f"open loop {wait_ms} ms: {curve[-1]}", file=sys.stderr, flush=True)
+    bits = env.poll_errors()[1]
     return {
         "metric": "raw emulated frames/s on 1 MI355X + p50/p99 step latency (served mode)",
         "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": st["batches"], "warmup": 0,
@@ -672,7 +710,8 @@ def bench_serve(args):
                                f"distinct env ids, continuous batching on {pipes} pipelines, 16 GiB budget",
                    "num_envs": n, "frameskip": w.frameskip, "render": "last two", "pipelines": pipes,
                    "max_batch": cap, "launch": launch, "launch_from": launch_from, "seconds": st["seconds"]},
-        "served": st, "fixed_batch": fixed, "errors": bits, "roofline": None, "cpu_baseline": None,
+        "served": st, "fixed_batch": fixed, "open_loop_curve": curve, "errors": bits, "roofline": None,
+        "cpu_baseline": None,
     }
 
 

@@ -246,13 +246,17 @@ class EnvServer:
 
 
 class ActorPool:
-    """Closed-loop simulated actors: after its response each actor waits an
-    exponential think time, then sends a request of floor(exp(U(ln lo, ln hi)))
-    distinct env ids drawn uniformly from all envs, with uniform actions."""
+    """Simulated actors.  Closed loop (the default): after its response each
+    actor waits an exponential think time, then sends a request of
+    floor(exp(U(ln lo, ln hi))) distinct env ids drawn uniformly from all
+    envs, with uniform actions.  Open loop: each actor sends at the times of
+    a Poisson process of that mean gap whether or not its earlier requests
+    were answered (the offered load then does not adapt to the server)."""
 
     def __init__(self, n_clients, num_envs, mean_wait_s=2e-3, size_lo=64, size_hi=4096, seed0=5000,
-                 n_actions=18):
+                 n_actions=18, open_loop=False):
         self.n, self.num_envs = n_clients, num_envs
+        self.open_loop = open_loop
         self.mean_wait = mean_wait_s
         self.lo, self.hi = size_lo, size_hi
         self.n_actions = n_actions
@@ -269,21 +273,31 @@ class ActorPool:
         for c in range(self.n):
             self.next_send[c] = t0 + self.rngs[c].exponential(self.mean_wait)
 
+    def mean_size(self):
+        """Expected request size: E floor(exp U(ln lo, ln hi))."""
+        ks = np.arange(self.lo, self.hi + 1, dtype=np.float64)
+        p = (np.log(np.minimum(ks + 1, self.hi)) - np.log(ks)) / (np.log(self.hi) - np.log(self.lo))
+        return float((ks * p).sum())
+
     def due(self, now):
         out = []
         for c in range(self.n):
-            if not self.outstanding[c] and self.next_send[c] <= now:
+            while (self.open_loop or not self.outstanding[c]) and self.next_send[c] <= now:
                 g = self.rngs[c]
                 k = self.size(c)
                 ids = g.choice(self.num_envs, size=k, replace=False).astype(np.int32)
                 act = g.integers(0, self.n_actions, k, dtype=np.uint8)
                 out.append(Request(c, ids, act, self.next_send[c]))
                 self.outstanding[c] = True
+                if not self.open_loop:
+                    break
+                self.next_send[c] += g.exponential(self.mean_wait)
         return out
 
     def responded(self, c, now):
         self.outstanding[c] = False
-        self.next_send[c] = now + self.rngs[c].exponential(self.mean_wait)
+        if not self.open_loop:
+            self.next_send[c] = now + self.rngs[c].exponential(self.mean_wait)
 
 
 def run_served(server, actors, seconds, clock=time.perf_counter, record=None):
@@ -309,6 +323,12 @@ def run_served(server, actors, seconds, clock=time.perf_counter, record=None):
         for r in actors.due(now):
             server.submit(r)
         server.poll()
+    backlog = 0
+    if actors.open_loop:
+        # an overloaded open loop never catches up: finish what is on the
+        # device, count the rest as backlog and drop it
+        backlog = int(sum(int((~r.sched).sum()) for r in server.pending))
+        server.pending = []
     server.drain()
     t1 = clock()
     server.on_result = user_cb
@@ -316,6 +336,7 @@ def run_served(server, actors, seconds, clock=time.perf_counter, record=None):
     return {
         "seconds": t1 - t0,
         "requests": int(lat.size),
+        "backlog_env_steps": backlog,
         "env_steps": int(server.env_steps - steps0),
         "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
         "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,

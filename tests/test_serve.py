@@ -137,3 +137,47 @@ def test_budget_sizing():
     assert 100_000 < m <= 131072
     with pytest.raises(ValueError):
         slots_for_budget(1 << 20, 131072, 16, 2, 1)
+
+
+def test_open_loop_actors_send_without_waiting():
+    """Open loop: an actor's Poisson send times do not wait for its answers,
+    so a client can have several requests outstanding; the arrival times are
+    the Poisson times themselves."""
+    a = ActorPool(3, 100, mean_wait_s=1e-3, size_lo=2, size_hi=8, seed0=9, open_loop=True)
+    a.start(0.0)
+    reqs = a.due(0.05)                       # 50 ms: about 50 requests per actor, none answered
+    per = np.bincount([r.client for r in reqs], minlength=3)
+    assert (per > 20).all() and (per < 100).all()
+    for c in range(3):
+        t = [r.t_arrival for r in reqs if r.client == c]
+        assert all(x < y for x, y in zip(t, t[1:])) and t[-1] <= 0.05
+    closed = ActorPool(3, 100, mean_wait_s=1e-3, size_lo=2, size_hi=8, seed0=9)
+    closed.start(0.0)
+    assert len(closed.due(0.05)) == 3        # closed loop: one outstanding request per actor
+    assert abs(a.mean_size() - np.mean([np.floor(np.exp(u)) for u in
+                                        np.random.default_rng(1).uniform(np.log(2), np.log(8), 100000)])) < 0.05
+
+
+def test_open_loop_overload_reports_backlog():
+    """Offered load far above what the backend serves: the run ends with a
+    backlog, which is dropped (not drained) and reported; the requests before
+    the first dropped one (all of them completed) equal their solo runs in
+    arrival order."""
+    from paper_1907_08467_amd.serve import run_served
+    n_envs = 32
+    backend = OracleBackend(make_oracle(n_envs), 2, 3)
+    clock = FakeClock()
+    actors = ActorPool(8, n_envs, mean_wait_s=1e-4, size_lo=4, size_hi=16, seed0=21, open_loop=True)
+    served = {}
+    server = EnvServer(backend, max_batch=8, num_envs=n_envs, clock=clock,
+                       on_result=lambda r, o, rw, d: served.update({r.seq: (r, o.copy(), rw.copy(), d.copy())}))
+    st = run_served(server, actors, seconds=0.02, clock=clock)
+    assert st["backlog_env_steps"] > 0 and st["requests"] == len(served) > 0
+    assert server.idle()
+    first_dropped = min(set(range(server.seq)) - set(served))
+    assert first_dropped > 0
+    solo = make_oracle(n_envs)
+    for seq in range(first_dropped):
+        req, obs, rew, done = served[seq]
+        o_obs, o_rew, o_done, _ = solo.step(req.actions, env_ids=req.ids)
+        assert np.array_equal(o_rew, rew) and np.array_equal(o_obs, obs), f"request {seq}"

@@ -117,3 +117,27 @@ def test_assign_noops_in_several_launches():
     compare_all(o, g, n, "after a listed step")
     g.close()
     o.close()
+
+
+SHAPED = [((8, 0, 128), S_4K, 0), ((16, 1, 512), S_F8, 1), ((1, 0, 64), S_4K, 1)]
+
+
+@pytest.mark.parametrize("shape,scheme,mode", SHAPED, ids=[f"w{s[0][0]}-p{s[0][1]}-r{s[0][2]}_s{s[1]}_m{s[2]}"
+                                                           for s in SHAPED])
+def test_noops_collisions_under_launch_shapes(shape, scheme, mode):
+    """No-ops after the copy together with tracked latches under narrow,
+    persistent and one-env-per-wave launch shapes."""
+    seed = 6400 + 3 * scheme + mode + shape[0]
+    say(f"case: noops + collisions, launch {shape}, scheme {scheme}, render mode {mode}, seed {seed}")
+    rom, sch = fuzz_cart(seed, scheme=scheme, cx=True)
+    n = 40
+    o, g = make_pair([(rom, sch)], np.zeros(n, np.uint16), seed=seed, frameskip=3, render_mode=mode,
+                     collisions=True, noop_after_copy=True, noop_max=6, startup_frames=5)
+    g.set_launch(*shape)
+    rng = np.random.default_rng(seed)
+    for s in range(110):                       # 330 frames: past every fuzz cartridge's episode length
+        step_both(o, g, rng.integers(0, 18, n), want_frames=True, tag=f"shaped step {s}")
+    compare_all(o, g, n, "end")
+    assert max(int(decode(o.get_state(e))["episode_idx"]) for e in range(n)) > 1
+    g.close()
+    o.close()

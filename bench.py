@@ -265,10 +265,11 @@ def bench_plain(args, c=2):
                    else "eager step calls"},
         "eager": {"value": eager_value, "ms_per_step": eager_ms},
         "graph": graph_res,
+        # counter figures exist for the plain 4096-env step only
         "roofline": dict(interp_roofline(kern, instr_last, n, w.frameskip),
-                         traffic=measured_traffic("k_interp") if n == 4096 else None),
+                         traffic=measured_traffic("k_interp") if (n == 4096 and c == 2) else None),
         "render_roofline": dict(render_roofline(kern, n, w.frameskip, True),
-                                traffic={k: measured_traffic(k) if n == 4096 else None
+                                traffic={k: measured_traffic(k) if (n == 4096 and c == 2) else None
                                          for k in ("k_render_frames", "k_render_obs")}),
         "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
         "emulated_instr_per_step": instr_last,

@@ -1605,8 +1605,11 @@ __device__ __forceinline__ uint32_t take_tile(uint32_t* queue) {
 // which would otherwise need 32 KB of LDS per wave and cut the waves per CU
 // by three).
 // TRACK: collision latches tracked (the scan code exists only in that
-// instantiation, so the other keeps its registers).
-template <int LL, int RC, bool TRACK>
+// instantiation, so the other keeps its registers).  NOOPS: the reset no-op
+// frames of restarted envs (envs with no frames to run leave at once, the
+// step counter stays); a separate instantiation, so the step's kernel keeps
+// its code.
+template <int LL, int RC, bool TRACK, bool NOOPS>
 __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t* __restrict__ pre_all) {
     __shared__ uint32_t s_rom[RC ? RC / 4 + 4 : 1];
     __shared__ uint32_t s_ram[(LL + 1) * kRamStride / 4];
@@ -1723,7 +1726,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             W.tia[c.tia_off + R_HMB] = 0;          // an earlier frame's blanked row is not this frame's
         };
 
-        if (nfr == 0) active = false;            // nothing to run (reset no-op frames of other envs)
+        if constexpr (NOOPS) {
+            if (nfr == 0) active = false;        // not restarted: nothing to run
+        }
         if (active) {
             if (act >= 18) {
                 c.err |= ERR_BAD_ACTION;
@@ -1890,7 +1895,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             E->instr += c.icount;
             E->prev_action = prev_action;
             E->err = c.err;
-            E->step_idx = step_idx + (A.count_step ? 1u : 0u);
+            E->step_idx = step_idx + (NOOPS ? 0u : 1u);
             StepInfo si;
             si.k = (uint8_t)k;
             si.done = (uint8_t)done;
@@ -1957,25 +1962,28 @@ void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, ui
     hipLaunchKernelGGL(k_predecode, dim3((n + 255) / 256), dim3(256), 0, s, rom, info, pre, track);
 }
 
-template <bool TRACK>
+template <bool TRACK, bool NOOPS>
 static void launch_interp_t(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s) {
     if (rom_lds == 0) {
         if (tile_envs <= 32)
-            hipLaunchKernelGGL((k_interp<32, 0, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+            hipLaunchKernelGGL((k_interp<32, 0, TRACK, NOOPS>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
         else
-            hipLaunchKernelGGL((k_interp<64, 0, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+            hipLaunchKernelGGL((k_interp<64, 0, TRACK, NOOPS>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
     } else if (tile_envs <= 32) {
-        hipLaunchKernelGGL((k_interp<32, 8192, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+        hipLaunchKernelGGL((k_interp<32, 8192, TRACK, NOOPS>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
     } else {
-        hipLaunchKernelGGL((k_interp<64, 8192, TRACK>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
+        hipLaunchKernelGGL((k_interp<64, 8192, TRACK, NOOPS>), dim3(grid), dim3(kLanes), 0, s, a, a.pre);
     }
 }
 
 void launch_interp(const InterpArgs& a, uint32_t grid, uint32_t tile_envs, uint32_t rom_lds, hipStream_t s) {
-    if (a.track)
-        launch_interp_t<true>(a, grid, tile_envs, rom_lds, s);
-    else
-        launch_interp_t<false>(a, grid, tile_envs, rom_lds, s);
+    if (a.track) {
+        if (a.count_step) launch_interp_t<true, false>(a, grid, tile_envs, rom_lds, s);
+        else launch_interp_t<true, true>(a, grid, tile_envs, rom_lds, s);
+    } else {
+        if (a.count_step) launch_interp_t<false, false>(a, grid, tile_envs, rom_lds, s);
+        else launch_interp_t<false, true>(a, grid, tile_envs, rom_lds, s);
+    }
 }
 
 }  // namespace vcs

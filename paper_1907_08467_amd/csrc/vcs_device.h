@@ -173,7 +173,8 @@ struct InterpArgs {
     uint32_t* queue;          // NULL: workgroup b runs tile b; else workgroups take
                               // tiles from this counter until it passes *n_tiles
     uint32_t track;           // collision latches tracked
-    uint32_t count_step;      // 1: the env's step counter advances (0: reset no-op frames)
+    uint32_t count_step;      // 1: a step (the env's step counter advances); 0: the reset no-op
+                              // frames of the envs whose frame count is not 0
     uint8_t* cx_logs;         // [n outputs][kFrameLogBytes]: logs of frames not rendered (track)
 };
 

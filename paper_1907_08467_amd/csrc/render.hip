@@ -177,8 +177,9 @@ __global__ void __launch_bounds__(512) k_render_frames(RenderArgs A) {
 // grid = n, block 64..512 threads.
 __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
     __shared__ uint32_t s_m[kFrameBytes / 4];   // max gray of the two frames
-    __shared__ uint4 s_f[kFrameBytes / 16];     // the frame being drawn, for the frames output
     __shared__ uint8_t s_lut[128];
+    extern __shared__ uint4 s_f[];               // the frame being drawn, for the frames output: launched
+                                                 // with kFrameBytes of dynamic LDS only when A.frames
     const uint32_t i = blockIdx.x;
     if (A.only && A.only[i] == 0) return;        // not one of the positions asked for
     const StepInfo si = A.info[i];
@@ -252,7 +253,9 @@ void launch_render_frames(const RenderArgs& a, uint32_t n_front_slots, uint32_t 
     hipLaunchKernelGGL(k_render_frames, dim3(a.n, n_front_slots), dim3(block), 0, s, a);
 }
 void launch_render_obs(const RenderArgs& a, uint32_t block, hipStream_t s) {
-    hipLaunchKernelGGL(k_render_obs, dim3(a.n), dim3(block), 0, s, a);
+    // without a frames output the frame copy in LDS is not needed, and twice
+    // as many workgroups fit on a compute unit
+    hipLaunchKernelGGL(k_render_obs, dim3(a.n), dim3(block), a.frames ? (size_t)kFrameBytes : 0, s, a);
 }
 
 }  // namespace vcs

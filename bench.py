@@ -34,10 +34,10 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 # null.
 MEASURED_TRAFFIC = {
     "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "c39579adf9bdd30d", (1334.2 * 2.0 + 206888.6) * 1024),
-    "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "90426fce9e4762c3",
-                        (123727.2 * 2.0 + 268800.0) * 1024),
-    "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "90426fce9e4762c3",
-                     (107919.9 * 2.0 + 297252.8) * 1024),
+    "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "70d4c62ee9a7fa24",
+                        (123909.9 * 2.0 + 268800.0) * 1024),
+    "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "70d4c62ee9a7fa24",
+                     (107924.7 * 2.0 + 297252.9) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9

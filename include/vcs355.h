@@ -136,20 +136,27 @@ int vcs_load_roms(vcs_ctx* ctx, uint32_t n_roms, const uint8_t* const* rom_host,
 
 /* env_rom_host[num_envs]: the ROM of every env.  Builds each ROM's reset cache
    on the device (power-on, run to the first frame end, startup_frames NOOP
-   frames, n_k NOOP frames) and puts every env into a cache state
-   (as vcs_reset).  Synchronises the device. */
+   frames, n_k NOOP frames; with noop_after_copy: startup_frames - 2 frames
+   and no no-ops) and puts every env into a cache state (as vcs_reset, its
+   no-op frames included).  Synchronises the device. */
 int vcs_assign(vcs_ctx* ctx, const uint16_t* env_rom_host);
 
 /* Restart envs env_ids_dev[0..n) (NULL = envs 0..n-1) from a random cache
-   entry; obs_dev[n][84][84] (may be NULL) receives their observations. */
+   entry (with noop_after_copy, then their 2 + n NOOP frames);
+   obs_dev[n][84][84] (may be NULL) receives their observations: the cache
+   entry's, or with noop_after_copy the one made from the last two of those
+   frames.  Listed ids out of range or repeated are skipped (obs 0) and set
+   VCS_ERR_BAD_ID. */
 int vcs_reset(vcs_ctx* ctx, const int32_t* env_ids_dev, uint32_t n, uint8_t* obs_dev, void* stream);
 
 /* One env step for envs env_ids_dev[0..n) (NULL = envs 0..n-1) with
    actions_dev[n] in [0, 18).  Outputs, indexed like env_ids_dev:
-     obs_dev[n][84][84]    observation (the cache entry's for envs that ended)
+     obs_dev[n][84][84]    observation (for envs that ended: the cache entry's,
+                           or with noop_after_copy the one after their no-ops)
      reward_dev[n]         change of the BCD score byte at $D0 over the step
      done_dev[n]           1 when RAM[$D1] became non-zero (or the env faulted);
                            the env is then already restarted from the cache
+                           (its no-op frames run, with noop_after_copy)
      frames_dev            NULL, or [n][F][210][160] palette-index frames with
                            F = frameskip (RENDER_ALL) or 2 (RENDER_LAST2, the
                            frames frameskip-2 and frameskip-1); frames that

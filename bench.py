@@ -62,7 +62,7 @@ def parse():
                         "branchy ROMs with sticky actions, with the per-step rate over the run; stack: the frame "
                         "stack of 16384 envs; inference: 4096 envs whose actions come from the policy CNN; "
                         "schemes: 36864 envs over one ROM of every cartridge scheme")
-    p.add_argument("--serve-seconds", type=float, default=20.0)
+    p.add_argument("--serve-seconds", type=float, default=60.0)
     p.add_argument("--serve-pipelines", type=int, default=3)
     p.add_argument("--serve-open-waits", type=float, nargs="*", default=[128.0, 64.0, 32.0, 16.0],
                    help="open-loop mean gaps between a client's requests (ms), one curve point each")

@@ -725,7 +725,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the envs are independent and "
-              "shard by env id, but this build measures the single-GPU path.", file=sys.stderr)
+              "shard by env id, but this benchmark measures the single-GPU path.", file=sys.stderr)
         sys.exit(2)
     fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
           "divergent": bench_divergent, "stack": bench_stack, "inference": bench_inference,

@@ -67,7 +67,7 @@ def parse():
     p.add_argument("--serve-open-waits", type=float, nargs="*", default=[128.0, 64.0, 32.0, 16.0],
                    help="open-loop mean gaps between a client's requests (ms), one curve point each")
     p.add_argument("--serve-open-seconds", type=float, default=3.0)
-    p.add_argument("--graph", type=int, default=4,
+    p.add_argument("--graph", type=int, default=16,
                    help="plain workload: time steps captured G at a time in HIP graphs (two pipelines, each step's "
                         "render overlapping the next step's interpreter) after the eager steps, and report them as "
                         "the value; 0 = eager steps only")

@@ -287,15 +287,19 @@ static void cart_write(OMachine* m, uint16_t a, uint8_t v) {
     if (has_superchip(m->scheme) && lo < 0x80) m->xram[lo] = v;   /* writes to the read port do nothing */
 }
 
-static uint8_t tia_read(const OMachine* m, uint16_t reg) {
+/* TIA read register reg, with the collision latches `cx` the read sees */
+static uint8_t tia_read_with(const OMachine* m, uint16_t reg, uint16_t cx) {
     if ((reg & 0x0F) < 8)              /* CXM0P .. CXPPMM: latches in D7, D6 */
-        return m->track_cx ? (uint8_t)(((m->cx >> (2 * (reg & 7))) & 3) << 6) : 0;
+        return m->track_cx ? (uint8_t)(((cx >> (2 * (reg & 7))) & 3) << 6) : 0;
     switch (reg & 0x0F) {
     case 0x0C: return m->inpt4;        /* INPT4: fire button of player 0 */
     case 0x0D: return 0x80;            /* INPT5: player 1 button never pressed */
-    default: return 0x00;              /* collisions, paddles, undriven bits */
+    default: return 0x00;              /* paddles, undriven bits */
     }
 }
+
+/* a data read at the access cycle: the beam has drawn that cycle's clocks */
+static uint8_t tia_read(const OMachine* m, uint16_t reg) { return tia_read_with(m, reg, m->cx); }
 
 static uint8_t riot_read(const OMachine* m, uint16_t a) {
     if ((a & 0x04) == 0) {
@@ -405,13 +409,29 @@ static uint8_t bus_read(OMachine* m, uint16_t addr) {
     return riot_read(m, a);
 }
 
-/* instruction-fetch bus (also zero-page pointers): the same map without
-   side effects; the cartridge area always shows ROM (the Superchip RAM window
-   is for data only) and the collision latches read 0 */
+static void beam_cycle(OMachine* m, uint64_t c);
+
+/* The collision latches as a read during cycle c sees them: the pixels
+   through colour clock 3c+2, the clocks of c included, as for a data read.
+   The beam has passed the cycles before c; the rest is drawn on a copy of
+   the machine (no frame buffer), so nothing here changes. */
+static uint16_t latches_during(const OMachine* m, uint64_t c) {
+    OMachine s = *m;
+    s.fb = NULL;
+    for (uint64_t k = s.beam_cycle; k <= c; k++) beam_cycle(&s, k);
+    return s.cx;
+}
+
+/* instruction-fetch bus (also zero-page pointers), used at the first cycle
+   of an instruction: the same map without side effects.  The cartridge area
+   always shows ROM (the Superchip RAM window is for data only); a collision
+   register shows its latches, which the TIA drives on every read of it. */
 static uint8_t bus_peek(const OMachine* m, uint16_t addr) {
     uint16_t a = addr & 0x1FFF;
     if (a & 0x1000) return rom_byte(m, a);
-    if ((a & 0x80) == 0) return (a & 0x0F) < 8 ? 0 : tia_read(m, a);
+    if ((a & 0x80) == 0)
+        return (a & 0x0F) < 8 && m->track_cx ? tia_read_with(m, a, latches_during(m, m->beam_cycle))
+                                             : tia_read(m, a);
     if ((a & 0x200) == 0) return m->ram[a & 0x7F];
     return riot_read(m, a);
 }

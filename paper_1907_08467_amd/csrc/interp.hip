@@ -247,7 +247,8 @@ struct Cpu {
     uint8_t* xram;            // the env's Superchip RAM (in its DevEnv)
     uint32_t slot, slots;     // its slot; slots completed so far
     int32_t open_row;
-    uint32_t open_cnt;
+    uint32_t open_cnt;        // entries logged in the open row
+    uint32_t open_base;       // stream index of the open row's first entry
     uint32_t icount;
     uint32_t ucount;          // instructions executed in wave-uniform mode
     int32_t hmb_line;         // line (relative to the base line) an early HMOVE blanked, or -1
@@ -284,10 +285,11 @@ __device__ __forceinline__ uint32_t tia_read(Cpu& c, const Wave& W, uint32_t a, 
     }
     return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);      // untracked latches read 0 here too
 }
-// the same without side effects (instruction fetch, zero-page pointers): the
-// latches read 0 there
-__device__ __forceinline__ uint32_t tia_peek(const Cpu& c, uint32_t a) {
+// The same for an instruction fetch (kernel loop), whose caller has scanned
+// the latches through the fetch cycle's pixels first.
+__device__ __forceinline__ uint32_t tia_peek(const Cpu& c, const Wave& W, uint32_t a) {
     const uint32_t r = a & 0x0F;
+    if (W.track && r < 8) return ((c.cx >> (2 * r)) & 3) << 6;
     return r == 0x0C ? c.inpt4 : (r == 0x0D ? 0x80u : 0u);
 }
 
@@ -322,18 +324,21 @@ __device__ __forceinline__ uint32_t rd(Cpu& c, const Wave& W, uint32_t addr, uin
     return riot_read(c, W, a, t);
 }
 
-// read without side effects (instruction fetch, zero-page pointers); the
-// cartridge area shows ROM even in the Superchip RAM window
+// instruction fetch at cycle t, without side effects; the cartridge area
+// shows ROM even in the Superchip RAM window
 __device__ __forceinline__ uint32_t peek(const Cpu& c, const Wave& W, uint32_t addr, uint32_t t) {
     const uint32_t a = addr & 0x1FFF;
     if (a & 0x1000) return W.rom[rom_off(W, c.bank, a)];
-    if (!(a & 0x80)) return tia_peek(c, a);
+    if (!(a & 0x80)) return tia_peek(c, W, a);
     if (!(a & 0x200)) return W.ram[c.ram_off + (a & 0x7F)];
     return riot_read(c, W, a, t);
 }
 
-__device__ __forceinline__ uint32_t zp_peek(const Cpu& c, const Wave& W, uint32_t z) {
-    return (z & 0x80) ? (uint32_t)W.ram[c.ram_off + (z & 0x7F)] : tia_peek(c, z);
+// zero-page pointer byte, fetched with the instruction at its first cycle:
+// RAM, or a TIA read register (a latch read sees the pixels through
+// `through`, like a data read)
+__device__ __forceinline__ uint32_t zp_fetch(Cpu& c, const Wave& W, uint32_t z, int32_t through) {
+    return (z & 0x80) ? (uint32_t)W.ram[c.ram_off + (z & 0x7F)] : tia_read(c, W, z, through);
 }
 
 // data write at cycle t; TIA writes are queued in slot K of the instruction
@@ -485,17 +490,22 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
     }
     case IZX: {
         const uint32_t z = (b1 + c.x) & 0xFF;
-        ea = zp_peek(c, W, z) | (zp_peek(c, W, (z + 1) & 0xFF) << 8);
+        const int32_t th = 3 * (int32_t)c.cyc + 2;
+        ea = zp_fetch(c, W, z, th) | (zp_fetch(c, W, (z + 1) & 0xFF, th) << 8);
         break;
     }
     case IZY: {
-        const uint32_t base = zp_peek(c, W, b1) | (zp_peek(c, W, (b1 + 1) & 0xFF) << 8);
+        const int32_t th = 3 * (int32_t)c.cyc + 2;
+        const uint32_t base = zp_fetch(c, W, b1, th) | (zp_fetch(c, W, (b1 + 1) & 0xFF, th) << 8);
         ea = (base + c.y) & 0xFFFF;
         if ((d >> DW_PEN) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
         break;
     }
     default: break;
     }
+    // a pointer taken from latches not scanned yet names no address: stop
+    // before any access (the caller scans the log and runs it again)
+    if (W.track && c.cx_need >= 0) return;
     const uint32_t next = (c.pc + ((d >> DW_LEN) & 3)) & 0xFFFF;
     uint32_t npc = next;
     if (md == REL) {
@@ -656,31 +666,36 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
 // ------------------------------------------------------------ row log
 
 __device__ __forceinline__ void log_finalize(Cpu& c) {
-    if (c.open_row >= 0 && c.open_cnt) c.log[c.open_row * kRowBytes + 15] = (uint8_t)c.open_cnt;
+    if (c.open_row >= 0 && c.open_cnt) c.log[c.open_row * kSnapBytes + 15] = (uint8_t)c.open_cnt;
 }
 
 // Take the snapshots of every row up to `target` (inclusive) from the
-// registers as they are now.
+// registers as they are now; the new rows' entries start where the open
+// row's end.
 __device__ __forceinline__ void log_advance(Cpu& c, const Wave& W, int32_t target) {
     if (target > kRows - 1) target = kRows - 1;
     while (c.open_row < target) {
         log_finalize(c);
         c.open_row++;
+        c.open_base += c.open_cnt;
         c.open_cnt = 0;
         const uint32_t* s = reinterpret_cast<const uint32_t*>(W.tia + c.tia_off);
-        uint4* d = reinterpret_cast<uint4*>(c.log + c.open_row * kRowBytes);
+        uint4* d = reinterpret_cast<uint4*>(c.log + c.open_row * kSnapBytes);
         d[0] = make_uint4(s[0], s[1], s[2], s[3] & 0x00FFFFFFu);
-        d[1] = make_uint4(s[4], s[5], s[6], s[7]);
+        d[1] = make_uint4(s[4], s[5], s[6], (s[7] & 0xFFFF0000u) | c.open_base);
     }
 }
 
+// The entry of a write in the open row.  Every write logs at most one entry
+// and a row's count stays within its bound, so the guard (an error bit
+// instead of a truncated row) is never expected to fire.
 __device__ __forceinline__ void log_entry(Cpu& c, int32_t row, uint32_t x, uint32_t code, uint32_t v0, uint32_t v1) {
     if (row < 0 || row >= kRows) return;
-    if (c.open_cnt >= (uint32_t)kRowEntries) {
+    if (c.open_cnt >= kCountMask || c.open_base + c.open_cnt >= (uint32_t)kFrameEntries) {
         c.err |= ERR_LOG;
         return;
     }
-    *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + kSnapBytes + 4 * c.open_cnt) =
+    *reinterpret_cast<uint32_t*>(c.log + kSnapArea + 4 * (c.open_base + c.open_cnt)) =
         x | (code << 8) | (v0 << 16) | (v1 << 24);
     c.open_cnt++;
 }
@@ -701,7 +716,7 @@ __device__ __forceinline__ void log_close(Cpu& c, const Wave& W, uint32_t t) {
     log_event(c, W, t, R_END, 0, 0);
     log_finalize(c);
     for (int32_t r = c.open_row + 1; r < kRows; ++r) {
-        uint4* d = reinterpret_cast<uint4*>(c.log + r * kRowBytes);
+        uint4* d = reinterpret_cast<uint4*>(c.log + r * kSnapBytes);
         d[0] = make_uint4(0, 0, 0, kRowOutside << 24);
         d[1] = make_uint4(0, 0, 0, 0);
     }
@@ -728,15 +743,15 @@ __device__ __forceinline__ void cx_scan(Cpu& c, const Wave& W, int32_t row_end, 
     while (c.cx_row < row_end || (c.cx_row == row_end && c.cx_x < x_end && row_end < kRows)) {
         const int32_t r = c.cx_row;
         const uint32_t xe = r < row_end ? 160u : (uint32_t)x_end;
-        const uint8_t* rec = c.log + r * kRowBytes;
+        const uint8_t* rec = c.log + r * kSnapBytes;
         const uint4 sa = reinterpret_cast<const uint4*>(rec)[0], sb = reinterpret_cast<const uint4*>(rec)[1];
-        const uint32_t cnt = r == c.open_row ? c.open_cnt : ((sa.w >> 24) & 0x1F);
-        const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + kSnapBytes);
+        const uint32_t cnt = r == c.open_row ? c.open_cnt : ((sa.w >> 24) & kCountMask);
+        const uint32_t* ents = reinterpret_cast<const uint32_t*>(c.log + kSnapArea) + (sb.w & 0xFFFF);
         const bool whole = c.cx_x == 0 && xe == 160;
         if (whole && cnt == pcnt) {
             const uint32_t hmb = (sb.z >> 8) & 0xFF;
             bool same = sa.x == pa.x && sa.y == pa.y && sa.z == pa.z && ((sa.w ^ pa.w) & 0x80FFFFFFu) == 0 &&
-                        sb.x == pb.x && sb.y == pb.y && sb.z == pb.z && sb.w == pb.w &&
+                        sb.x == pb.x && sb.y == pb.y && sb.z == pb.z && ((sb.w ^ pb.w) & 0xFFFF0000u) == 0 &&
                         hmb != (uint32_t)r && hmb != (uint32_t)r + 1;
             for (uint32_t i = 0; same && i < cnt; ++i) same = ents[i] == pents[i];
             if (same) {
@@ -876,10 +891,7 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, u
         const bool release = !(v & 2) && was;
         const uint32_t mode = R[R_NUSIZ0 + i] & 7;
         const uint32_t pos = (R[R_P0X + i] + (mode == 5 ? 6u : mode == 7 ? 10u : 3u)) % 160;
-        if (lg) {
-            if (release) log_event(c, W, t, R_M0X + i, pos, 0);
-            log_event(c, W, t, i ? R_FLAGS2 : R_FLAGS, fl, 0);
-        }
+        if (lg) log_event(c, W, t, R_RESMP + i, fl, release ? pos : R[R_M0X + i]);
         if (release) R[R_M0X + i] = (uint8_t)pos;
         set_flag_reg(R, 7 + i, v, fl);
         return;
@@ -891,12 +903,9 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, u
         const uint32_t m1 = (uint32_t)(((int32_t)R[R_M1X] - hm_delta(R[R_HMM1]) + 160) % 160);
         const uint32_t bl = (uint32_t)(((int32_t)R[R_BLX] - hm_delta(R[R_HMBL]) + 160) % 160);
         const uint32_t ln = (t + 1) / 76, h = 3 * (t + 1 - 76 * ln);
-        if (lg) {
-            log_event(c, W, t, R_HMOVE, p0, p1);
-            log_event(c, W, t, R_M0X, m0, 0);
-            log_event(c, W, t, R_M1X, m1, 0);
-            log_event(c, W, t, R_BLX, bl, 0);
-        }
+        if (lg)   // one entry: the renderer applies the five motion nibbles itself
+            log_event(c, W, t, R_HMOVE | ((R[R_HMBL] >> 4) & 15), ((c.hmp0 >> 4) & 15) | (c.hmp1 & 0xF0),
+                      ((R[R_HMM0] >> 4) & 15) | (R[R_HMM1] & 0xF0));
         R[R_P0X] = (uint8_t)p0; R[R_P1X] = (uint8_t)p1;
         R[R_M0X] = (uint8_t)m0; R[R_M1X] = (uint8_t)m1; R[R_BLX] = (uint8_t)bl;
         if (h < 68) {                           // written in the horizontal blank: pixels 0-7 of the line blank
@@ -950,7 +959,7 @@ __device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_read
 // instructions this path does not cover (indirect modes, JMP (ind), RTI, BRK,
 // indexed accesses outside RAM/cartridge), which the per-lane path executes.
 struct Fast {
-    uint32_t pc, bank, cyc, cap, orow, ocnt;
+    uint32_t pc, bank, cyc, cap, orow, ocnt, obase;
     int32_t fl;
     uint32_t logon;
     uint32_t partial;   // 1: other running lanes are elsewhere; stop at the next line start
@@ -1052,24 +1061,25 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
         target = target > kRows - 1 ? kRows - 1 : target;
         if ((int32_t)F.orow <= target) {
             if (F.orow > 0) {
-                if (F.ocnt) c.log[(F.orow - 1) * kRowBytes + 15] = (uint8_t)F.ocnt;
+                if (F.ocnt) c.log[(F.orow - 1) * kSnapBytes + 15] = (uint8_t)F.ocnt;
             }
+            F.obase += F.ocnt;       // the new rows' entries start after the open row's
+            F.ocnt = 0;
             const uint32_t* src = reinterpret_cast<const uint32_t*>(R);
             const uint4 snap0 = make_uint4(src[0], src[1], src[2], src[3] & 0x00FFFFFFu);
-            const uint4 snap1 = make_uint4(src[4], src[5], src[6], src[7]);
+            const uint4 snap1 = make_uint4(src[4], src[5], src[6], (src[7] & 0xFFFF0000u) | F.obase);
             do {    // F.orow holds the open row + 1 (0 = none)
-                uint4* d = reinterpret_cast<uint4*>(c.log + F.orow * kRowBytes);
+                uint4* d = reinterpret_cast<uint4*>(c.log + F.orow * kSnapBytes);
                 d[0] = snap0;
                 d[1] = snap1;
                 F.orow++;
             } while ((int32_t)F.orow <= target);
-            F.ocnt = 0;
         }
         if (vis) {
             if ((uint32_t)row < (uint32_t)kRows) {
-                // the row is the open one here; a full row is left to the per-lane path
-                if (F.ocnt >= (uint32_t)kRowEntries) return 0;
-                *reinterpret_cast<uint32_t*>(c.log + row * kRowBytes + kSnapBytes + 4 * F.ocnt) =
+                // the row is the open one here; past the guard the per-lane path records the error
+                if (F.ocnt >= kCountMask || F.obase + F.ocnt >= (uint32_t)kFrameEntries) return 0;
+                *reinterpret_cast<uint32_t*>(c.log + kSnapArea + 4 * (F.obase + F.ocnt)) =
                     (h - 68) | (code << 8) | (v0 << 16);
                 F.ocnt++;
             }
@@ -1492,6 +1502,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
     F.fl = rfl(c.fl);
     F.orow = (uint32_t)(rfl(c.open_row) + 1);
     F.ocnt = rfl(c.open_cnt);
+    F.obase = rfl(c.open_base);
     F.logon = rfl(c.log != nullptr ? 1u : 0u);
     uint32_t done_n = 0;       // instructions executed on this path
     uint32_t st = FS_EXIT;
@@ -1563,6 +1574,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
     c.bank = F.bank;
     c.open_row = (int32_t)F.orow - 1;
     c.open_cnt = F.ocnt;
+    c.open_base = F.obase;
     return done_n > 0 || capped;
 }
 #undef VCS_FAST_64
@@ -1694,6 +1706,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
         c.log = nullptr;
         c.open_row = -1;
         c.open_cnt = 0;
+        c.open_base = 0;
         c.tqm = 0;
         c.ev = 0;
         uint32_t k = 0, done = 0;
@@ -1721,6 +1734,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             }
             c.open_row = -1;
             c.open_cnt = 0;
+            c.open_base = 0;
             c.cx_row = 0;
             c.cx_x = 0;
             W.tia[c.tia_off + R_HMB] = 0;          // an earlier frame's blanked row is not this frame's
@@ -1754,9 +1768,11 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 const int lead = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(c.cyc == tmin));
                 const uint32_t pc0 = rdl(c.pc, lead), bk0 = rdl(c.bank, lead);
                 const int32_t fl0 = rdl(c.fl, lead), or0 = rdl(c.open_row, lead);
-                const uint32_t oc0 = rdl(c.open_cnt, lead), lg0 = rdl(c.log != nullptr ? 1u : 0u, lead);
+                const uint32_t oc0 = rdl(c.open_cnt, lead), ob0 = rdl(c.open_base, lead);
+                const uint32_t lg0 = rdl(c.log != nullptr ? 1u : 0u, lead);
                 const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == tmin && c.fl == fl0 &&
-                                  c.open_row == or0 && c.open_cnt == oc0 && (c.log != nullptr ? 1u : 0u) == lg0;
+                                  c.open_row == or0 && c.open_cnt == oc0 && c.open_base == ob0 &&
+                                  (c.log != nullptr ? 1u : 0u) == lg0;
                 const uint32_t partial = __builtin_amdgcn_ballot_w64(!same) != 0 ? 1u : 0u;
                 if (same) uni = run_fast<TRACK>(c, W, W.pre, ended, end_t, partial);
             }
@@ -1784,6 +1800,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                         b1 = (v >> 8) & 0xFF;
                         b2 = (v >> 16) & 0xFF;
                     } else {
+                        // bytes fetched from the TIA read registers show the
+                        // latches through the fetch cycle's pixels, 3t+2
+                        if constexpr (TRACK) cx_catch_up(c, W, 3 * (int32_t)c.cyc + 2);
                         op = peek(c, W, pc, c.cyc);
                         b1 = peek(c, W, pc + 1, c.cyc);
                         b2 = peek(c, W, pc + 2, c.cyc);

@@ -97,13 +97,13 @@ __device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0, uint32_t row
 // emit(seg, q) receives pixels 16 seg .. 16 seg + 15 packed little-endian.
 template <class Emit>
 __device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, Emit&& emit) {
-    const uint8_t* rec = frame_log + row * kRowBytes;
+    const uint8_t* rec = frame_log + row * kSnapBytes;
     const uint4 s = *reinterpret_cast<const uint4*>(rec);
     const uint4 s2 = *reinterpret_cast<const uint4*>(rec + 16);
     Regs r;
     unpack(r, s, s2);
-    const uint32_t cnt = (s.w >> 24) & 0x1F;
-    const uint32_t* ents = reinterpret_cast<const uint32_t*>(rec + kSnapBytes);
+    const uint32_t cnt = (s.w >> 24) & kCountMask;
+    const uint32_t* ents = reinterpret_cast<const uint32_t*>(frame_log + kSnapArea) + (s2.w & 0xFFFF);
     if (r.outside && cnt == 0) {
         for (int seg = 0; seg < kCols / 16; ++seg) emit(seg, make_uint4(0, 0, 0, 0));
         return;

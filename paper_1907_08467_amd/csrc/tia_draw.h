@@ -61,14 +61,32 @@ __device__ __forceinline__ void set_byte(Regs& r, uint32_t i, uint32_t v) {
     }
 }
 
+// position p moved by HMOVE with motion nibble n (a signed 4-bit amount,
+// positive to the left), wrapping at 160
+__device__ __forceinline__ uint32_t hm_move(uint32_t p, uint32_t n) {
+    int32_t q = (int32_t)p - (((int32_t)(n & 15) ^ 8) - 8);
+    q += q < 0 ? 160 : 0;
+    q -= q >= 160 ? 160 : 0;
+    return (uint32_t)q;
+}
+
 // one logged write: x | code << 8 | v0 << 16 | v1 << 24
 __device__ __forceinline__ void apply(Regs& r, uint32_t e) {
     const uint32_t code = (e >> 8) & 0xFF, v0 = (e >> 16) & 0xFF, v1 = e >> 24;
     if (code == R_END) {
         r.outside = true;
-    } else if (code == R_HMOVE) {
-        set_byte_in<3>(r, 0, v0);                                   // P0, P1 positions
-        set_byte_in<3>(r, 8, v1);
+    } else if (code >= R_HMOVE) {                                   // all five objects by their motion
+        set_byte_in<3>(r, 0, hm_move(rb<R_P0X>(r), v0));
+        set_byte_in<3>(r, 8, hm_move(rb<R_P1X>(r), v0 >> 4));
+        set_byte_in<5>(r, 0, hm_move(rb<R_M0X>(r), v1));
+        set_byte_in<5>(r, 8, hm_move(rb<R_M1X>(r), v1 >> 4));
+        set_byte_in<5>(r, 16, hm_move(rb<R_BLX>(r), code));
+    } else if (code == R_RESMP) {                                   // RESMP0: flags, missile 0 position
+        set_byte_in<5>(r, 24, v0);
+        set_byte_in<5>(r, 0, v1);
+    } else if (code == R_RESMP + 1) {                               // RESMP1: flags 2, missile 1 position
+        set_byte_in<6>(r, 0, v0);
+        set_byte_in<5>(r, 8, v1);
     } else if (code == R_GRP0) {                                    // GRP1 to its delayed register
         set_byte_in<4>(r, 8, rb<R_GRP1>(r));
         set_byte_in<2>(r, 16, v0);

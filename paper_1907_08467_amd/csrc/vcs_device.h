@@ -3,9 +3,10 @@
 // Env state lives in HBM as one 384-byte record per env (DevEnv).  A step
 // loads a tile of 64 envs into one wave: RAM into LDS, CPU registers into
 // VGPRs.  The interpreter writes, for each frame it renders, a row log: per
-// scanline row a 16-byte snapshot of the render registers at the row's first
-// visible pixel plus the register writes that land inside the row, so the
-// render kernel can draw every row and pixel independently.
+// scanline row a 32-byte snapshot of the render registers at the row's first
+// visible pixel, and the register writes that land inside the row as 4-byte
+// entries packed row after row into one stream, so the render kernel can
+// draw every row and pixel independently and reads only the entries logged.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,10 +23,22 @@ constexpr int kFirstRow = 34;          // frame row 0 = scanline 34 of the frame
 constexpr int kObs = 84;
 constexpr int kObsBytes = kObs * kObs;
 constexpr int kFrameBytes = kRows * kCols;
-constexpr int kRowEntries = 24;        // max register writes inside one row's visible part
+// Row log of one frame: the 210 row snapshots, then the entry stream.
+// Every emulated TIA write logs at most one entry.  The writes whose effect
+// lands in one row's visible part (colour clocks 68..227 of a line) are made
+// at 53 consecutive access cycles; all writes of an instruction happen at
+// its last cycle, so the densest sequence is a BRK (3 pushes) at the first
+// of those cycles, seven more 7-cycle BRKs and a 3-cycle store: 25 writes.
+// A row also takes the frame-end entry, so a frame logs at most 210 * 25 + 1
+// entries.
+constexpr int kRowEntries = 25;        // max register writes inside one row's visible part
 constexpr int kSnapBytes = 32;         // row snapshot: the render registers R[0..31]
-constexpr int kRowBytes = kSnapBytes + 4 * kRowEntries;   // snapshot + entries = 128
-constexpr int kFrameLogBytes = kRows * kRowBytes;         // 26,880
+constexpr int kSnapArea = 6784;        // 210 snapshots (6,720 B), padded to whole 128-byte lines
+constexpr int kFrameEntries = 5280;    // entry stream capacity >= 210 * 25 + 1, in whole lines
+constexpr int kFrameLogBytes = kSnapArea + 4 * kFrameEntries;   // 27,904
+constexpr uint32_t kCountMask = 0x1F;  // snapshot byte 15: entries in the row (<= 26)
+// snapshot bytes 28-29: index of the row's first entry in the stream (R[28..31]
+// are no registers)
 constexpr int kTiaRegs = 48;           // render registers + full-byte copies (R[0..47])
 constexpr int kRomSlot = 32768;        // bytes per ROM slot (smaller ROMs use its start)
 
@@ -45,8 +58,9 @@ enum : int {
     R_ENAM0 = 32, R_ENAM1, R_ENABL, R_ENABL_OLD, R_VDELP0, R_VDELP1, R_VDELBL, R_RESMP0, R_RESMP1,
     R_HMM0 = 41, R_HMM1, R_HMBL,
     // entry-only codes
-    R_HMOVE = 26,            // v0, v1: new P0 and P1 positions (M0, M1, BL follow as position entries)
-    R_END = 27
+    R_END = 27,              // the frame ended: pixels from here on are outside
+    R_RESMP = 0x30,          // + i: RESMPx; v0 = the new R_FLAGS (x = 0) / R_FLAGS2 (x = 1), v1 = missile x's position
+    R_HMOVE = 0x40           // | BL motion nibble: HMOVE; v0 = P0 | P1 << 4, v1 = M0 | M1 << 4 motion nibbles
 };
 // snapshot byte 15: number of entries in the row, bit 7 = row outside the frame
 constexpr uint32_t kRowOutside = 0x80;

@@ -280,3 +280,132 @@ def test_collisions_pipelines_overlap():
     assert g.poll_errors() == o.poll_errors()
     g.close()
     o.close()
+
+
+# ---------------------------------------------------------------- fetches
+# Bytes fetched with an instruction (pointer bytes, operand bytes, opcodes)
+# from the TIA read registers show the collision latches, as the oracle's
+# pins define it (the latches through the fetch cycle's pixels, 3t+2).
+
+def fetch_programs():
+    from test_oracle_tia_objects import (BALL_ON_P0, M0_ON_P0, P0_OVER_PF, P1_ON_M0, PTR_READS, fetch_rom,
+                                         rom_with, timing_rom)
+    return [("pointer P0-PF", rom_with(P0_OVER_PF, per_frame_end=PTR_READS), 0x20, 0x5A),
+            ("pointer P0-PF+BL", rom_with(P0_OVER_PF + BALL_ON_P0, per_frame_end=PTR_READS), 0x20, 0xA5),
+            ("operand M0-P0", fetch_rom(M0_ON_P0), 0x22, 0x40),
+            ("operand M0-P0/P1", fetch_rom(M0_ON_P0 + P1_ON_M0), 0x22, 0xC0),
+            ("pointer timing 18", timing_rom(18), 0x20, 0x00),
+            ("pointer timing 19", timing_rom(19), 0x20, 0x5A)]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_fetches_read_latches(mode):
+    """Each program on the GPU and the oracle, latches tracked: states,
+    frames and the RAM byte the fetch decided, every step."""
+    for name, rom, addr, want in fetch_programs():
+        n = 8
+        say(f"case: fetch reads latches, {name}, render_mode {mode}")
+        o, g = make_pair([(rom, 0)], np.zeros(n, np.uint16), seed=3, frameskip=4, render_mode=mode,
+                         collisions=True)
+        rng = np.random.default_rng(3)
+        for s in range(3):
+            step_both(o, g, rng.integers(0, 18, n), want_frames=True, tag=f"{name} step {s}")
+            compare_all(o, g, n, f"{name} step {s}")
+        assert int(decode(o.get_state(0))["ram"][addr & 0x7F]) == want, name
+        ge, oe = g.poll_errors(), o.poll_errors()
+        assert ge == oe and ge[1] == 0, (name, ge, oe)
+        g.close()
+        o.close()
+
+
+# ---------------------------------------------------------------- row log
+# Rows with as many logged writes as a program can make: 24 back-to-back
+# STA HMOVE (18 land in the visible part, each moving all five objects),
+# RESMP set/release toggles on both missiles, a chain of 8 JSRs whose
+# pushes walk down the TIA registers from RESBL to NUSIZ1, and a BRK
+# pushing into REFP0, CTRLPF and COLUBK (its handler continues the frame:
+# a stack in the TIA cannot be pulled back).
+
+def storm_cart():
+    hm = "    sta WSYNC\n" + "    sta HMOVE\n" * 24
+    resmp = "    sta WSYNC\n    lda #2\n    ldy #0\n" + \
+            "    sta RESMP0\n    sty RESMP0\n    sta RESMP1\n    sty RESMP1\n" * 5
+    jsr = "    sta WSYNC\n    ldx #$14\n    txs\n" + "".join(f"    jsr j{k}_%d\nj{k}_%d:\n" for k in range(8)) + \
+          "    ldx #$FF\n    txs\n"
+    body = []
+    for i in range(48):
+        body.append([hm, resmp, jsr.replace("%d", str(i))][i % 3])
+    body.append("    sta WSYNC\n    ldx #$0B\n    txs\n" + "    nop\n" * 12 + "    brk\n    .byte $EA\nafter_brk:\n")
+    src = f"""
+reset:
+    ldx #$FF
+    txs
+    lda #$FF
+    sta GRP0
+    lda #$3C
+    sta GRP1
+    lda #2
+    sta ENAM0
+    sta ENAM1
+    sta ENABL
+    lda #$15
+    sta NUSIZ0
+    lda #$27
+    sta NUSIZ1
+    lda #$10
+    sta HMP0
+    lda #$F0
+    sta HMP1
+    lda #$20
+    sta HMM0
+    lda #$E0
+    sta HMM1
+    lda #$70
+    sta HMBL
+frame:
+    sta WSYNC
+    lda #2
+    sta VSYNC
+    lda #0
+    sta VSYNC
+    sta VBLANK
+    ldx #40
+top:
+    sta WSYNC
+    dex
+    bne top
+{"".join(body)}    ldx #170
+bottom:
+    sta WSYNC
+    dex
+    bne bottom
+    jmp frame
+brkh:
+    ldx #$FF
+    txs
+    jmp after_brk
+    .org $1FFC
+    .word reset
+    .word brkh
+"""
+    rom, _ = cart(src)
+    return rom
+
+
+@pytest.mark.parametrize("mode,track", [(0, False), (1, False), (0, True), (1, True)])
+def test_row_log_storms(mode, track):
+    """Parity on rows far past the old per-row capacity (7 HMOVEs), with no
+    error bit: frames, rewards, states every step."""
+    rom = storm_cart()
+    n = 16
+    say(f"case: row-log storms, render_mode {mode}, collisions {track}")
+    o, g = make_pair([(rom, 0)], np.zeros(n, np.uint16), seed=4, frameskip=4, render_mode=mode,
+                     collisions=track)
+    rng = np.random.default_rng(4)
+    for s in range(6):
+        step_both(o, g, rng.integers(0, 18, n), want_frames=True, tag=f"storm step {s}")
+        compare_all(o, g, n, f"storm step {s}")
+    ge, oe = g.poll_errors(), o.poll_errors()
+    assert ge == oe and ge[1] == 0, (ge, oe)
+    g.close()
+    o.close()

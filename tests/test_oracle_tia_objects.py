@@ -251,3 +251,143 @@ rest:
     rom, _ = cart(prog(20, vblank=True))
     _, d = run(rom, track=True)
     assert d["ram"][0x20] == 0                     # nothing is drawn, so nothing collides, in VBLANK
+
+
+# Fetches that read the latches.  The TIA drives D7/D6 of a collision
+# register on every read cycle of it, whoever reads: zero-page pointer bytes
+# and instruction bytes fetched from $00-$07 (and mirrors) see the latches as
+# a data read would.  Fetches happen at the instruction's first cycle t and,
+# like a data read at cycle t, see the pixels through colour clock 3t+2.
+
+# P0 on pixels 66-73 over playfield PF2 (pixels 48-79): CXP0FB D7 on every
+# visible row; with the ball (2 wide from 65) over P0 too: CXP0FB D7 and D6
+P0_OVER_PF = "    lda #$FF\n    sta PF2\n    sta GRP0\n    lda #$36\n    sta COLUP0\n" \
+             "    sta WSYNC\n" + AT42 + "    sta RESP0\n"
+BALL_ON_P0 = "    lda #2\n    sta ENABL\n    lda #$10\n    sta CTRLPF\n    sta WSYNC\n" + AT42 + "    sta RESBL\n"
+# markers at the RAM bytes a latch-valued pointer can name
+MARKS = "    lda #$5A\n    sta $80\n    lda #$A5\n    sta $C0\n"
+PTR_READS = MARKS + "    ldy #0\n    lda ($02),y\n    sta $A0\n    ldx #4\n    lda ($FE,x)\n    sta $A1\n"
+
+
+@pytest.mark.parametrize("setup,want", [("", 0x00), (P0_OVER_PF, 0x5A), (P0_OVER_PF + BALL_ON_P0, 0xA5)])
+def test_pointer_bytes_read_latches(setup, want):
+    """LDA ($02),Y and LDA ($FE,X) with X = 4 take their pointer from
+    CXP0FB/CXP1FB: low byte $80 (P0-PF) names RAM $80, $C0 (P0-PF and P0-BL)
+    names RAM $C0, $00 names TIA register $00 (CXM0P, 0 here); the high
+    byte ($00 or $80, CXP1FB) only sets address bits that the 13-bit bus
+    drops."""
+    _, d = run(rom_with(setup, per_frame_end=PTR_READS), track=True)
+    assert int(d["ram"][0x20]) == want and int(d["ram"][0x21]) == want
+    _, d = run(rom_with(setup, per_frame_end=PTR_READS), track=False)
+    assert int(d["ram"][0x20]) == 0 and int(d["ram"][0x21]) == 0     # untracked: the pointer is $0000
+
+
+def fetch_rom(setup):
+    """LDY #imm with its opcode at $00FF (RAM) and its operand at $0100, which
+    the 13-bit bus maps to TIA read register 0 (CXM0P); the next opcode
+    comes from $0101 (CXM1P, 0 here: BRK), whose handler stores Y."""
+    src = f"""
+reset:
+    sta WSYNC
+{setup}
+frame:
+    sta WSYNC
+    lda #2
+    sta VSYNC
+    lda #0
+    sta VSYNC
+    lda #$A0
+    sta $FF
+    jmp $00FF
+back:
+    ldx #0
+lines:
+    sta WSYNC
+    dex
+    bne lines
+    jmp frame
+brkh:
+    sty $A2
+    tsx
+    lda $0102,x
+    sta $A3
+    pla
+    pla
+    pla
+    jmp back
+    .org $1FFC
+    .word reset
+    .word brkh
+"""
+    rom, _ = cart(src)
+    return rom
+
+
+M0_ON_P0 = "    lda #$FF\n    sta GRP0\n    lda #2\n    sta ENAM0\n    lda #$10\n    sta NUSIZ0\n" \
+           "    sta WSYNC\n" + AT42 + "    sta RESP0\n    sta WSYNC\n" + AT42 + "    sta RESM0\n"
+P1_ON_M0 = "    lda #$FF\n    sta GRP1\n    sta WSYNC\n" + AT42 + "    sta RESP1\n"
+
+
+@pytest.mark.parametrize("setup,want", [("", 0x00), (M0_ON_P0, 0x40), (M0_ON_P0 + P1_ON_M0, 0xC0)])
+def test_operand_fetch_reads_latches(setup, want):
+    """The operand byte of LDY # fetched from $0100 is CXM0P: D6 = M0-P0,
+    D7 = M0-P1 (M0 2 wide from 65 meets the players on 66).  BRK at $0101
+    pushes the return address $0103: its low byte lands at $0102 + S."""
+    _, d = run(fetch_rom(setup), track=True)
+    assert int(d["ram"][0x22]) == want and int(d["ram"][0x23]) == 0x03
+    _, d = run(fetch_rom(setup), track=False)
+    assert int(d["ram"][0x22]) == 0
+
+
+def timing_rom(nops):
+    """On the read line: CXCLR (cycles 0-2), LDA zp (3-5), `nops` NOPs, then
+    LDA ($07),Y (Y = 0) at t = 6 + 2 nops; the result goes to RAM $A0."""
+    src = f"""
+reset:
+    lda #$FF
+    sta GRP0
+    sta GRP1
+    lda #$5A
+    sta $80
+    sta WSYNC
+{AT42}    sta RESP0
+    sta WSYNC
+{AT42}    sta RESP1
+frame:
+    sta WSYNC
+    lda #2
+    sta VSYNC
+    lda #0
+    sta VSYNC
+    ldx #59
+    ldy #0
+lines:
+    sta WSYNC
+    dex
+    bne lines
+    sta WSYNC
+    sta CXCLR
+    lda $F0
+""" + "    nop\n" * nops + """    lda ($07),y
+    sta $A0
+    ldx #0
+rest:
+    sta WSYNC
+    dex
+    bne rest
+    jmp frame
+"""
+    rom, _ = cart(src)
+    return rom
+
+
+@pytest.mark.parametrize("nops,want", [(18, 0x00), (19, 0x5A)])
+def test_pointer_fetch_timing(nops, want):
+    """P0 and P1 (both on 66-73) meet from colour clock 68 + 66 = 134.  The
+    pointer low byte (CXPPMM) is fetched at t = 6 + 2 nops and sees clocks
+    through 3t+2: t = 42 -> 128 (pointer $00, A = CXM0P = 0), t = 44 -> 134
+    (pointer $80, A = RAM $80 = $5A).  A pointer read at the access cycle
+    t+4 would latch already at t = 42; one that saw only the cycles before t
+    would not latch at t = 44."""
+    _, d = run(timing_rom(nops), track=True)
+    assert int(d["ram"][0x20]) == want

@@ -83,7 +83,13 @@ enum {
 
 typedef struct {
     uint32_t num_envs;          /* resident envs */
-    uint32_t frameskip;         /* frames per step, >= 1 (the paper uses 4) */
+    uint32_t frameskip;         /* frames per step: 1..255, and at most 8 with
+                                   VCS_RENDER_ALL (every frame of a step gets a
+                                   frame slot; a step records which slots it
+                                   completed in 8 bits); VCS_E_INVAL otherwise.
+                                   The paper counts 4 emulated frames per
+                                   training frame (Section 1, the footnote on
+                                   raw frames). */
     uint32_t sticky_threshold;  /* a frame repeats the previous frame's action
                                    when (R(seed, env, 1, step*frameskip+f) >> 32)
                                    < threshold; floor(p * 2^32); 0 = off   */
@@ -125,7 +131,10 @@ typedef struct vcs_ctx vcs_ctx;
 int vcs_create(const vcs_config* cfg, vcs_ctx** out);
 void vcs_destroy(vcs_ctx* ctx);
 
-/* Copy n_roms cartridges to the device.  rom_bytes[r] must be a size the
+/* The cartridges the consoles run (paper, Section 3: the first kernel reads
+   the ROM instructions of each emulated console; the emulator runs the
+   console, not game-specific code, so any cartridge loads).
+   Copy n_roms cartridges to the device.  rom_bytes[r] must be a size the
    scheme takes (see VCS_BANK_*; VCS_E_ROM otherwise).  Bank hotspots switch
    on any data access, before it; instruction fetches see ROM even in the
    Superchip RAM window, and a read of its write port returns 0.  Power-on
@@ -134,14 +143,20 @@ void vcs_destroy(vcs_ctx* ctx);
 int vcs_load_roms(vcs_ctx* ctx, uint32_t n_roms, const uint8_t* const* rom_host,
                   const uint32_t* rom_bytes, const uint32_t* scheme);
 
-/* env_rom_host[num_envs]: the ROM of every env.  Builds each ROM's reset cache
+/* The reset cache (paper, Section 3: instead of emulating the start of every
+   episode, an env that ends restarts from one of a set of cached initial
+   states, each made by 64 start-up frames and a random number of no-op
+   frames, up to 30; 30 states per game).
+   env_rom_host[num_envs]: the ROM of every env.  Builds each ROM's reset cache
    on the device (power-on, run to the first frame end, startup_frames NOOP
    frames, n_k NOOP frames; with noop_after_copy: startup_frames - 2 frames
    and no no-ops) and puts every env into a cache state (as vcs_reset, its
    no-op frames included).  Synchronises the device. */
 int vcs_assign(vcs_ctx* ctx, const uint16_t* env_rom_host);
 
-/* Restart envs env_ids_dev[0..n) (NULL = envs 0..n-1) from a random cache
+/* The environment's reset (paper, Section 3: a reset copies one of the
+   cached initial states, chosen at random, into the env).
+   Restart envs env_ids_dev[0..n) (NULL = envs 0..n-1) from a random cache
    entry (with noop_after_copy, then their 2 + n NOOP frames);
    obs_dev[n][84][84] (may be NULL) receives their observations: the cache
    entry's, or with noop_after_copy the one made from the last two of those
@@ -149,7 +164,13 @@ int vcs_assign(vcs_ctx* ctx, const uint16_t* env_rom_host);
    VCS_ERR_BAD_ID. */
 int vcs_reset(vcs_ctx* ctx, const int32_t* env_ids_dev, uint32_t n, uint8_t* obs_dev, void* stream);
 
-/* One env step for envs env_ids_dev[0..n) (NULL = envs 0..n-1) with
+/* The environment's step (paper, Section 1: environments execute a set of
+   actions and produce observable states and rewards; its footnote on raw
+   frames: every emulated frame counts, one in four becomes training input;
+   Section 3: the input of the learner is the pixelwise maximum of the last
+   two frames of four, frames are rendered in GPU memory, and an env whose
+   episode ended restarts from a cached initial state).
+   One env step for envs env_ids_dev[0..n) (NULL = envs 0..n-1) with
    actions_dev[n] in [0, 18).  Outputs, indexed like env_ids_dev:
      obs_dev[n][84][84]    observation (for envs that ended: the cache entry's,
                            or with noop_after_copy the one after their no-ops)

@@ -1,19 +1,27 @@
 """Throughput of the batched emulation step on one MI355X.
 
-Workload: the plain batched configuration -- 4096 envs of one seeded 4 KB
-synthetic cartridge, frameskip 4, every frame rendered to 210x160 and kept in
-HBM plus the 84x84 gray max-of-two observation, uniform random actions
-(PCG64 seed 1), no sticky actions.  Actions for every timed step are resident
-in HBM before the timed region starts.  K eager step calls are timed first
-(with per-kernel HIP events), then K steps run as HIP graphs of G steps
-whose renders overlap the next step's interpreter; the graph rate is the
-value, the eager rate is reported beside it.  --workload batching / serve
-print the batching-form and served-form lines instead.
+Default (--workload metric): the configurations the metric is quoted on.
+ - The value: the batching form, 65,536 envs over 16 seeded synthetic
+   cartridges (8 x 4 KB, 8 x F8) in Zipf 1.2 populations, frameskip 4, the
+   last two frames of each step rendered into the 84x84 gray max-of-two
+   observation, launch shape from the autotuner, steps captured in HIP
+   graphs on two pipelines; the plain kernel (64 envs per wave, eager calls)
+   on the same inputs beside it.  Exactly --steps steps are timed.
+ - The served form: 131,072 resident envs over the same cartridges behind
+   the env server, 64 closed-loop actors, continuous batching; raw frames/s
+   and p50/p99 request latency over --metric-serve-seconds, the fixed-batch
+   reference and an open-loop overload curve.
+ - The plain 4096-env step (one cartridge, every frame rendered to HBM) as
+   the baseline, over --c2-steps eager steps and as many in graphs, a window
+   that crosses the first episode ends and their resets.
+Actions for every timed step are resident in HBM before the timed region
+starts.  Per-kernel times come from HIP events on the launch stream.
 
 Prints one JSON line: raw emulated frames/s (= env steps x frameskip / s), the
-roofline of the dominant kernel (timed with HIP events on the launch stream)
-and the CPU oracle's rate on the host cores for a bounded sample of the same
-workload.
+roofline of the dominant kernel, the interpreter's active-lane utilisation,
+and the CPU oracle's rates on the host cores (configuration 1 in full and
+bounded samples of the other two).  Other --workload values print the line
+of one configuration.
 """
 import argparse
 import json
@@ -51,17 +59,29 @@ POLICY_FLOPS_PER_ENV = sum(2 * m * n * k for m, n, k in POLICY_GEMMS)
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=1000)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=8)
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=16)
-    p.add_argument("--workload", choices=["plain", "batching", "serve", "divergent", "stack", "inference", "schemes", "objects", "noops"], default="plain",
-                   help="plain: 4096 envs, 1 ROM, every frame (the headline); batching: 65536 envs over 16 ROMs; "
-                        "serve: 131072 resident envs behind the env server; divergent: 32768 envs over 8 "
-                        "branchy ROMs with sticky actions, with the per-step rate over the run; stack: the frame "
-                        "stack of 16384 envs; inference: 4096 envs whose actions come from the policy CNN; "
-                        "schemes: 36864 envs over one ROM of every cartridge scheme")
+    p.add_argument("--cpu-c4-steps", type=int, default=2,
+                   help="steps of the oracle's 65,536-env batching sample (metric workload)")
+    p.add_argument("--c2-steps", type=int, default=600,
+                   help="metric workload: timed steps of the plain 4096-env baseline (eager, then graphs); 600 "
+                        "steps cross the first episode ends and their resets")
+    p.add_argument("--metric-serve-seconds", type=float, default=20.0)
+    p.add_argument("--metric-open-waits", type=float, nargs="*", default=[64.0, 32.0, 16.0])
+    p.add_argument("--count-episodes", action="store_true",
+                   help="plain workloads: count the episodes that end in each timed window")
+    p.add_argument("--workload", choices=["metric", "plain", "batching", "serve", "divergent", "stack", "inference",
+                                          "schemes", "objects", "noops"], default="metric",
+                   help="metric (default): the batching form of 65536 envs over 16 ROMs (the value), the served "
+                        "form of 131072 resident envs (p50/p99) and the plain 4096-env step; plain: 4096 envs, "
+                        "1 ROM, every frame; batching: 65536 envs over 16 ROMs; serve: 131072 resident envs "
+                        "behind the env server; divergent: 32768 envs over 8 branchy ROMs with sticky actions, "
+                        "with the per-step rate over the run; stack: the frame stack of 16384 envs; inference: "
+                        "4096 envs whose actions come from the policy CNN; schemes: 36864 envs over one ROM of "
+                        "every cartridge scheme")
     p.add_argument("--serve-seconds", type=float, default=60.0)
     p.add_argument("--serve-pipelines", type=int, default=3)
     p.add_argument("--serve-open-waits", type=float, nargs="*", default=[128.0, 64.0, 32.0, 16.0],
@@ -142,6 +162,21 @@ def measured_traffic(kernel):
     return nbytes if h.hexdigest()[:16] == sha else None
 
 
+def graph_len(k, cap):
+    """The longest graph of at most `cap` steps whose launches cover exactly
+    k steps."""
+    for g in range(min(cap, k), 0, -1):
+        if k % g == 0:
+            return g
+    return 1
+
+
+def episodes_ended(env):
+    """Episodes ended so far, summed over every env (state record bytes
+    188..191); synchronises."""
+    return sum(int.from_bytes(bytes(env.get_state(e)[188:192]), "little") for e in range(env.num_envs))
+
+
 def select_launch(env, args, n, want_frames, want_obs):
     if args.launch == "auto":
         launch, tune_ms = env.autotune(n=n, steps=3, want_frames=want_frames, want_obs=want_obs)
@@ -169,6 +204,12 @@ def interp_roofline(kern, instr, n, frameskip):
             "work_per_launch": f"{instr} emulated 6502 instructions ({n} envs x {frameskip} frames)"}
 
 
+def lane_util(instr, passes):
+    """Active-lane utilisation of the interpreter: emulated instructions
+    (summed over envs) over the lanes its waves' instruction passes offer."""
+    return instr / (64.0 * passes) if passes else 0.0
+
+
 def render_roofline(kern, n, frames_per_step, with_frames):
     fb = (n * frames_per_step * 210 * 160 if with_frames else 0) + n * 84 * 84
     t = (kern["k_render_frames"]["mean_ms"] + kern["k_render_obs"]["mean_ms"]) * 1e-3
@@ -194,12 +235,11 @@ def bench_plain(args, c=2):
     w = config(c)
     if args.envs != w.n_envs:
         w.n_envs = args.envs
-    G = args.graph
+    K, W = args.steps, args.warmup
+    G = graph_len(K, args.graph) if args.graph else 0
     env, roms, env_rom = gpu_env(w, pipelines=2 if G else 1)
     dev = torch.device("cuda", 0)
-    n, K, W = w.n_envs, args.steps, args.warmup
-    if G:
-        K = max(G, K - K % G)
+    n = w.n_envs
     launch, launch_from = select_launch(env, args, n, True, True)
     acts = torch.from_numpy(w.actions(steps=2 * K + W)).to(dev)
     obs = torch.empty((n, 84, 84), dtype=torch.uint8, device=dev)
@@ -213,6 +253,7 @@ def bench_plain(args, c=2):
     instr_one = env.last_step_instructions()   # instructions of the last warmup step
     print(f"warmup done: {W} steps; instructions in one step {instr_one}", file=sys.stderr, flush=True)
 
+    ep0 = episodes_ended(env) if args.count_episodes else None
     env.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -221,7 +262,8 @@ def bench_plain(args, c=2):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     env.timing(False)
-    instr_last, instr_uniform = env.last_step_stats()
+    ep1 = episodes_ended(env) if args.count_episodes else None
+    instr_last, instr_uniform, passes = env.last_step_counts()
     kern = kernel_table(env)
     value = eager_value = n * w.frameskip * K / dt
     eager_ms = dt / K * 1e3
@@ -240,7 +282,10 @@ def bench_plain(args, c=2):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         value = n * w.frameskip * K / dt
-        graph_res = {"value": value, "ms_per_step": dt / K * 1e3, "steps_per_graph": G}
+        graph_res = {"value": value, "ms_per_step": dt / K * 1e3, "steps_per_graph": G,
+                     "steps": f"{W + K + 2 * G}..{W + 2 * K + 2 * G - 1}"}
+        if args.count_episodes:
+            graph_res["episodes_ended"] = episodes_ended(env) - ep1
         print(f"timed {K} graph steps in {dt:.3f}s", file=sys.stderr, flush=True)
     first, bits = env.poll_errors()
     print(f"errors {bits:#x}", file=sys.stderr, flush=True)
@@ -265,7 +310,8 @@ def bench_plain(args, c=2):
                    "launch": launch, "launch_from": launch_from,
                    "steps_as": f"HIP graphs of {G} steps, render overlapping the next interpreter" if G
                    else "eager step calls"},
-        "eager": {"value": eager_value, "ms_per_step": eager_ms},
+        "eager": {"value": eager_value, "ms_per_step": eager_ms, "steps": f"{W}..{W + K - 1}",
+                  "episodes_ended": None if ep0 is None else ep1 - ep0},
         "graph": graph_res,
         # counter figures exist for the plain 4096-env step only
         "roofline": dict(interp_roofline(kern, instr_last, n, w.frameskip),
@@ -276,6 +322,7 @@ def bench_plain(args, c=2):
         "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
         "emulated_instr_per_step": instr_last,
         "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
+        "lane_utilisation": lane_util(instr_last, passes), "wave_passes": passes,
         "errors": bits,
         "cpu_baseline": cpu,
     }
@@ -289,9 +336,8 @@ def bench_batching(args):
     from paper_1907_08467_amd.inputs.workloads import config
     w = config(4)
     n = w.n_envs
-    G = 4                                    # steps per captured graph
-    K = max(G, args.steps - args.steps % G)
-    W = args.warmup
+    K, W = args.steps, args.warmup
+    G = graph_len(K, 4)                      # steps per captured graph
     dev = torch.device("cuda", 0)
     acts = torch.from_numpy(w.actions(steps=K + W)).to(dev)
     res = {}
@@ -338,11 +384,12 @@ def bench_batching(args):
             torch.cuda.synchronize()
             env.timing(False)
             kern = kernel_table(env)
-        instr_last, instr_uniform = env.last_step_stats()
+        instr_last, instr_uniform, passes = env.last_step_counts()
         bits = env.poll_errors()[1]
         finals[form] = [t.cpu().numpy() for t in last]
         res[form] = {"value": n * w.frameskip * K / dt, "ms_per_step": dt / K * 1e3, "launch": launch,
                      "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
+                     "lane_utilisation": lane_util(instr_last, passes), "wave_passes": passes,
                      "launch_from": launch_from, "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
                      "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
                      "render_roofline": render_roofline(kern, n, 2, False), "errors": bits}
@@ -718,6 +765,92 @@ def bench_serve(args):
     }
 
 
+def cpu_legs(args):
+    """The oracle on the host cores: configuration 1 in full, and bounded
+    samples of the plain 4096-env step and of the 65,536-env batching
+    workload (the same cartridges, seeds, actions and render modes)."""
+    import oracle
+    from paper_1907_08467_amd.inputs.palette import GRAY
+    from paper_1907_08467_amd.inputs.workloads import config
+    legs = {}
+    for key, c, steps, with_frames in (("c1_full", 1, None, True), ("plain_4096", 2, args.cpu_steps, True),
+                                       ("batching_65536", 4, args.cpu_c4_steps, False)):
+        w = config(c)
+        steps = w.steps if steps is None else steps
+        roms = [(r.data, r.scheme) for r in w.roms()]
+        env_rom = w.env_rom()
+        print(f"cpu baseline {key}: oracle, {w.n_envs} envs x {steps} steps", file=sys.stderr, flush=True)
+        o = oracle.Oracle(w.n_envs, GRAY, frameskip=w.frameskip, seed=w.rng_seed, render_mode=w.render_mode,
+                          sticky_threshold=w.sticky_threshold, collisions=w.collisions)
+        o.load_roms(roms)
+        o.assign(env_rom)
+        acts = w.actions(steps=steps)
+        t0 = time.perf_counter()
+        for s in range(steps):
+            o.step(acts[s], want_frames=with_frames)
+        dt = time.perf_counter() - t0
+        frames = w.n_envs * w.frameskip * steps
+        o.close()
+        legs[key] = {"value": frames / dt, "unit": "raw frames/s", "cores": oracle.get_threads(), "kind": "oracle",
+                     "sample": f"{w.name}: {w.n_envs} envs x {steps} steps x frameskip {w.frameskip} "
+                               f"({frames} raw frames){', frames copied out' if with_frames else ''}",
+                     "seconds": dt}
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    head = dict(legs["batching_65536"])
+    head["legs"] = legs
+    head["cpu_model"] = cpu_model
+    head["host_cpus"] = os.cpu_count()
+    return head
+
+
+def bench_metric(args):
+    """The metric's own configurations on one GPU: the batching form of
+    65,536 envs (the value; the plain kernel on the same inputs beside it),
+    the served form of 131,072 resident envs with p50/p99 step latency, and
+    the plain 4096-env step as the baseline, each over exactly the steps
+    named; the oracle's rates on the host cores."""
+    import copy
+    import torch
+    t_start = time.perf_counter()
+    res = bench_batching(args)
+    torch.cuda.empty_cache()
+    print(f"batching done at {time.perf_counter() - t_start:.0f}s", file=sys.stderr, flush=True)
+    a2 = copy.copy(args)
+    a2.serve_seconds = args.metric_serve_seconds
+    a2.serve_open_waits = args.metric_open_waits
+    served = bench_serve(a2)
+    torch.cuda.empty_cache()
+    print(f"serving done at {time.perf_counter() - t_start:.0f}s", file=sys.stderr, flush=True)
+    a3 = copy.copy(args)
+    a3.steps, a3.envs, a3.no_cpu_baseline, a3.count_episodes = args.c2_steps, 4096, True, True
+    plain = bench_plain(a3, 2)
+    torch.cuda.empty_cache()
+    print(f"plain step done at {time.perf_counter() - t_start:.0f}s", file=sys.stderr, flush=True)
+    res["metric"] = "raw emulated frames/s on 1 MI355X + p50/p99 step latency (served mode)"
+    res["config"]["workload"] = "batching form (the largest fixed batch): " + res["config"]["workload"]
+    res["served"] = {"value": served["value"], "unit": "raw frames/s", "p50_ms": served["latency_ms"]["p50"],
+                     "p99_ms": served["latency_ms"]["p99"], "workload": served["config"]["workload"],
+                     "seconds": served["served"]["seconds"], "requests": served["served"]["requests"],
+                     "batches": served["served"]["batches"], "stats": served["served"],
+                     "fixed_batch": served["fixed_batch"], "open_loop_curve": served["open_loop_curve"],
+                     "errors": served["errors"], "launch": served["config"]["launch"],
+                     "max_batch": served["config"]["max_batch"]}
+    res["plain_batch_4096"] = {k: plain[k] for k in ("value", "steps", "warmup", "ms_per_step", "config", "eager",
+                                                     "graph", "roofline", "render_roofline", "kernels_ms",
+                                                     "emulated_instr_per_step", "uniform_mode_fraction",
+                                                     "lane_utilisation", "wave_passes", "errors")}
+    res["errors"] |= served["errors"] | plain["errors"]
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_legs(args)
+    res["bench_seconds"] = time.perf_counter() - t_start
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration_mib:
@@ -727,7 +860,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the envs are independent and "
               "shard by env id, but this benchmark measures the single-GPU path.", file=sys.stderr)
         sys.exit(2)
-    fn = {"plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
+    fn = {"metric": bench_metric, "plain": bench_plain, "batching": bench_batching, "serve": bench_serve,
           "divergent": bench_divergent, "stack": bench_stack, "inference": bench_inference,
           "schemes": bench_schemes, "objects": lambda a: bench_plain(a, 7), "noops": bench_noops}[args.workload]
     print(json.dumps(fn(args)))

@@ -81,6 +81,7 @@ def _declare(L):
     L.vcs_poll_errors.argtypes = [_vp, _vp, _vp]
     L.vcs_last_step_instructions.argtypes = [_vp, _vp]
     L.vcs_last_step_stats.argtypes = [_vp, _vp]
+    L.vcs_last_step_counts.argtypes = [_vp, _vp]
     L.vcs_timing.argtypes = [_vp, ctypes.c_int]
     L.vcs_kernel_time.argtypes = [_vp, ctypes.c_int, _vp, _vp]
     L.vcs_set_launch.argtypes = [_vp, ctypes.POINTER(VcsLaunch)]
@@ -102,8 +103,10 @@ def _declare(L):
     L.vcs_policy_destroy.restype = None
     L.vcs_last_error.argtypes = []
     L.vcs_last_error.restype = ctypes.c_char_p
-    for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_step_pipe", "vcs_get_state",
+    for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_step_pipe",
+                 "vcs_get_state",
                  "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions", "vcs_last_step_stats",
+                 "vcs_last_step_counts",
                  "vcs_timing", "vcs_kernel_time", "vcs_set_launch", "vcs_get_launch", "vcs_autotune",
                  "vcs_graph_create", "vcs_graph_launch", "vcs_stack_create", "vcs_stack_push",
                  "vcs_policy_create", "vcs_policy_act"):
@@ -207,6 +210,12 @@ def vcs_last_step_stats(h):
     v = (ctypes.c_uint64 * 2)()
     check(lib.vcs_last_step_stats(h, v), "vcs_last_step_stats")
     return v[0], v[1]
+
+
+def vcs_last_step_counts(h):
+    v = (ctypes.c_uint64 * 3)()
+    check(lib.vcs_last_step_counts(h, v), "vcs_last_step_counts")
+    return v[0], v[1], v[2]
 
 
 def vcs_timing(h, enable):

@@ -52,7 +52,8 @@ struct Pipe {
     uint8_t* d_valid = nullptr;     // [max_batch]
     Tile* d_tiles = nullptr;        // [tiles_cap]
     uint32_t* d_n_tiles = nullptr;
-    uint32_t* d_tag = nullptr;      // claim tag: pipeline index + 8 x (calls that validated ids)
+    uint32_t* d_tag = nullptr;      // claim tag: residue + 16 x (calls that validated ids)
+    uint32_t residue = 0;           // its tags' residue mod 16: the pipeline index
     uint32_t* d_stepw = nullptr;
     uint32_t* d_counts = nullptr;
     unsigned long long* d_instr = nullptr;
@@ -406,22 +407,25 @@ static int enqueue_noops(vcs_ctx* c, Pipe& P, const Tile* tiles, const uint32_t*
 // The emulation part of one step on stream s with the scratch of pipeline
 // `pipe` (arguments checked): counters, id validation and tiles, the
 // interpreter (frames, row logs, reward, done) and the eager reset.
-int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
-                int32_t* reward, uint8_t* done, uint8_t* frames, hipStream_t s) {
-    Pipe& P = c->pipes[pipe];
+// P: the scratch (a pipeline's, or the shared static one); n_slots / render_all:
+// the frame slots its row logs hold and whether every frame is logged (the
+// context's render mode, or 2 and the last two frames).
+int enqueue_sim_on(vcs_ctx* c, Pipe& P, uint32_t n_slots, bool render_all, const int32_t* ids,
+                   const uint8_t* actions, uint32_t n, uint8_t* obs, int32_t* reward, uint8_t* done, uint8_t* frames,
+                   hipStream_t s) {
     const Tile* tiles = c->d_tiles_all;
     const uint32_t* n_tiles = c->d_n_tiles_all;
     uint32_t grid = c->n_tiles_all;
     const bool listed = ids || n != c->cfg.num_envs;
     if (listed) {
         // counts, offsets, fill, instruction counters and queue; advance the tag
-        launch_step_begin(P.d_stepw, c->stepw_words, P.d_tag, s);
+        launch_step_begin(P.d_stepw, c->stepw_words, P.d_tag, P.residue, s);
         int rc = build_tiles(c, P, ids, n, reward, done, s, &grid);
         if (rc) return rc;
         tiles = P.d_tiles;
         n_tiles = P.d_n_tiles;
     } else {
-        launch_step_begin(P.d_stepw + c->instr_off, c->stepw_words - c->instr_off, nullptr, s);
+        launch_step_begin(P.d_stepw + c->instr_off, c->stepw_words - c->instr_off, nullptr, 0, s);
     }
     InterpArgs ia{};
     ia.tiles = tiles;
@@ -434,14 +438,14 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
     ia.actions = actions;
     ia.nframes_per_out = nullptr;
     ia.nframes = c->cfg.frameskip;
-    ia.render_all = c->cfg.render_mode == VCS_RENDER_ALL;
+    ia.render_all = render_all ? 1 : 0;
     ia.log_enabled = (obs || frames) ? 1 : 0;
     ia.early_stop = 1;
     ia.sticky_thr = c->cfg.sticky_threshold;
     ia.frameskip = c->cfg.frameskip;
     ia.seed = c->cfg.seed;
     ia.logs = P.d_logs;
-    ia.n_slots = c->n_slots;
+    ia.n_slots = n_slots;
     ia.info = P.d_info;
     ia.reward = reward;
     ia.done = done;
@@ -484,24 +488,30 @@ int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* ac
     return VCS_OK;
 }
 
+int enqueue_sim(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
+                int32_t* reward, uint8_t* done, uint8_t* frames, hipStream_t s) {
+    return enqueue_sim_on(c, c->pipes[pipe], c->n_slots, c->cfg.render_mode == VCS_RENDER_ALL, ids, actions, n, obs,
+                          reward, done, frames, s);
+}
+
 // Render of one step from pipeline `pipe`'s row logs: frames output and
 // observations.  Needs only that step's interpreter launch; the env state is
 // not touched, so it may overlap the next step's interpreter on another
 // pipeline.
-int enqueue_render(vcs_ctx* c, uint32_t pipe, uint32_t n, uint8_t* obs, uint8_t* frames, hipStream_t s) {
-    Pipe& P = c->pipes[pipe];
+int enqueue_render_on(vcs_ctx* c, Pipe& P, uint32_t n_slots, uint32_t n, uint8_t* obs, uint8_t* frames,
+                      hipStream_t s) {
     RenderArgs ra{};
     ra.logs = P.d_logs;
-    ra.n_slots = c->n_slots;
+    ra.n_slots = n_slots;
     ra.info = P.d_info;
     ra.frames = frames;
     ra.obs = obs;
     ra.gray = c->d_gray;
     ra.n = n;
     ra.force_obs = 0;
-    if (frames && c->n_slots > 2) {
+    if (frames && n_slots > 2) {
         begin_timed(c, 1, s);
-        launch_render_frames(ra, c->n_slots - 2, c->launch.render_block, s);
+        launch_render_frames(ra, n_slots - 2, c->launch.render_block, s);
         end_timed(c, s);
     }
     if (obs || frames) {
@@ -511,6 +521,10 @@ int enqueue_render(vcs_ctx* c, uint32_t pipe, uint32_t n, uint8_t* obs, uint8_t*
     }
     HIP_OK(hipGetLastError());
     return VCS_OK;
+}
+
+int enqueue_render(vcs_ctx* c, uint32_t pipe, uint32_t n, uint8_t* obs, uint8_t* frames, hipStream_t s) {
+    return enqueue_render_on(c, c->pipes[pipe], c->n_slots, n, obs, frames, s);
 }
 
 // One whole step on stream s.
@@ -591,8 +605,10 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
               hipMemset(c->d_claim, 0xFF, (size_t)cfg->num_envs * 4) == hipSuccess &&
               hipMemset(c->d_err, 0, 4) == hipSuccess && hipMemset(c->d_err + 1, 0xFF, 4) == hipSuccess &&
               hipMemset(c->d_envs, 0, (size_t)cfg->num_envs * sizeof(DevEnv)) == hipSuccess;
-    for (uint32_t p = 0; p < c->pipes.size() && ok; ++p)
+    for (uint32_t p = 0; p < c->pipes.size() && ok; ++p) {
+        c->pipes[p].residue = p;
         ok = hipMemcpy(c->pipes[p].d_tag, &p, 4, hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (!ok) {
         vcs_destroy(c);
         return fail(VCS_E_HIP, "initial device copies failed");
@@ -689,14 +705,14 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     if (!rc) rc = alloc_n(c, &c->d_cmap, n_roms, "ROM mappings");
     if (!rc) rc = alloc_n(c, &c->d_pre_off, n_roms, "ROM mappings");
     const uint32_t instr_off = (3 * n_roms + 1) & ~1u;   // 8-byte aligned counters
-    c->stepw_words = instr_off + 5;
+    c->stepw_words = instr_off + 7;
     c->instr_off = instr_off;
     for (auto& P : c->pipes) {
         if (!rc) rc = alloc_n(c, &P.d_stepw, c->stepw_words, "per-call counters");
         if (rc) break;
         P.d_counts = P.d_stepw;
-        P.d_instr = reinterpret_cast<unsigned long long*>(P.d_stepw + instr_off);
-        P.d_queue = P.d_stepw + instr_off + 4;
+        P.d_instr = reinterpret_cast<unsigned long long*>(P.d_stepw + instr_off);   // 3 counters
+        P.d_queue = P.d_stepw + instr_off + 6;
     }
     if (!rc) rc = ensure_tile_buffer(c);
     if (rc) return rc;
@@ -993,16 +1009,16 @@ int vcs_reset(vcs_ctx* c, const int32_t* ids, uint32_t n, uint8_t* obs, void* st
     uint32_t grid = c->n_tiles_all;
     if (c->cfg.noop_after_copy && (ids || n != c->cfg.num_envs)) {
         // the no-op frames need tiles of the listed envs (validation included)
-        launch_step_begin(P.d_stepw, c->stepw_words, P.d_tag, s);
+        launch_step_begin(P.d_stepw, c->stepw_words, P.d_tag, P.residue, s);
         int rc = build_tiles(c, P, ids, n, nullptr, nullptr, s, &grid);
         if (rc) return rc;
         tiles = P.d_tiles;
         n_tiles = P.d_n_tiles;
         rs.valid = P.d_valid;
     } else if (c->cfg.noop_after_copy) {
-        launch_step_begin(P.d_stepw + c->instr_off, c->stepw_words - c->instr_off, nullptr, s);
+        launch_step_begin(P.d_stepw + c->instr_off, c->stepw_words - c->instr_off, nullptr, 0, s);
     } else if (ids) {
-        launch_step_begin(P.d_counts, c->n_roms, P.d_tag, s);
+        launch_step_begin(P.d_counts, c->n_roms, P.d_tag, P.residue, s);
         launch_validate(ids, n, c->cfg.num_envs, c->d_env_rom, c->d_claim, P.d_tag, P.d_counts, P.d_valid,
                         nullptr, nullptr, nullptr, c->d_err, s);
         rs.valid = P.d_valid;
@@ -1111,6 +1127,16 @@ int vcs_last_step_stats(vcs_ctx* c, uint64_t* out2) {
     if (c->pipes[0].d_instr) HIP_OK(hipMemcpy(v, c->pipes[0].d_instr, 16, hipMemcpyDeviceToHost));
     out2[0] = v[0];
     out2[1] = v[1];
+    return VCS_OK;
+}
+
+int vcs_last_step_counts(vcs_ctx* c, uint64_t* out3) {
+    if (!c || !out3) return fail(VCS_E_INVAL, "null argument");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    HIP_OK(hipDeviceSynchronize());
+    unsigned long long v[3] = {0, 0, 0};
+    if (c->pipes[0].d_instr) HIP_OK(hipMemcpy(v, c->pipes[0].d_instr, 24, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 3; ++i) out3[i] = v[i];
     return VCS_OK;
 }
 

@@ -16,12 +16,14 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
 }
 
 // Start of a step or reset call: clear the per-call counters and, when the
-// call validates ids, advance its pipeline's claim tag by 8 (tags of the up
-// to 8 pipelines stay distinct: tag mod 8 is the pipeline).  Kernels only
-// (no memset), so a captured call replays correctly.
-__global__ void k_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag) {
+// call validates ids, move its claim tag to the next value of its residue
+// mod 16 (the up to 8 pipelines use residues 0-7, the scratch of the entry
+// point that allocates nothing uses 8, so tags of different scratch sets
+// never meet and each one only grows).  Kernels only (no memset), so a
+// captured call replays correctly.
+__global__ void k_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, uint32_t residue) {
     for (uint32_t i = threadIdx.x; i < n_zero; i += blockDim.x) zero[i] = 0;
-    if (tag && threadIdx.x == 0) *tag = *tag + 8;
+    if (tag && threadIdx.x == 0) *tag = ((*tag + 16u) & ~15u) | residue;
 }
 
 // Validate the ids of one call and count the valid ones per ROM.  An id out
@@ -145,8 +147,8 @@ void launch_reset(const ResetArgs& a, hipStream_t s) {
 void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
 }
-void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, hipStream_t s) {
-    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, zero, n_zero, tag);
+void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, uint32_t residue, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, zero, n_zero, tag, residue);
 }
 void launch_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, const uint16_t* env_rom,
                      uint32_t* claim, const uint32_t* tag, uint32_t* counts, uint8_t* valid, StepInfo* info,

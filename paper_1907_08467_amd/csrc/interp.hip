@@ -255,6 +255,8 @@ struct Cpu {
     uint32_t cx;              // collision latches (bit 2r+1 / 2r = D7 / D6 of CX register r)
     int32_t cx_row, cx_x;     // the frame's pixels before (row, x) are in cx
     int32_t cx_need;          // >= 0: a latch read needs the pixels through this clock scanned first
+    int32_t ptr_memo;         // >= 0: the (zp,X) address / (zp),Y base of the instruction being run
+                              // again, fixed by the run that had scanned through its fetch cycle
     uint32_t log_scratch;     // the row log is the collision scratch copy, not a rendered frame
 };
 
@@ -489,14 +491,25 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
         break;
     }
     case IZX: {
-        const uint32_t z = (b1 + c.x) & 0xFF;
-        const int32_t th = 3 * (int32_t)c.cyc + 2;
-        ea = zp_fetch(c, W, z, th) | (zp_fetch(c, W, (z + 1) & 0xFF, th) << 8);
+        if (c.ptr_memo >= 0) {
+            ea = (uint32_t)c.ptr_memo;
+        } else {
+            const uint32_t z = (b1 + c.x) & 0xFF;
+            const int32_t th = 3 * (int32_t)c.cyc + 2;
+            ea = zp_fetch(c, W, z, th) | (zp_fetch(c, W, (z + 1) & 0xFF, th) << 8);
+            if (W.track && c.cx_need < 0) c.ptr_memo = (int32_t)ea;   // its latches are final
+        }
         break;
     }
     case IZY: {
-        const int32_t th = 3 * (int32_t)c.cyc + 2;
-        const uint32_t base = zp_fetch(c, W, b1, th) | (zp_fetch(c, W, (b1 + 1) & 0xFF, th) << 8);
+        uint32_t base;
+        if (c.ptr_memo >= 0) {
+            base = (uint32_t)c.ptr_memo;
+        } else {
+            const int32_t th = 3 * (int32_t)c.cyc + 2;
+            base = zp_fetch(c, W, b1, th) | (zp_fetch(c, W, (b1 + 1) & 0xFF, th) << 8);
+            if (W.track && c.cx_need < 0) c.ptr_memo = (int32_t)base;
+        }
         ea = (base + c.y) & 0xFFFF;
         if ((d >> DW_PEN) & 1) n += ((base ^ ea) & 0xFF00) ? 1 : 0;
         break;
@@ -504,7 +517,10 @@ __device__ __forceinline__ void exec_generic(uint32_t d, Cpu& c, const Wave& W, 
     default: break;
     }
     // a pointer taken from latches not scanned yet names no address: stop
-    // before any access (the caller scans the log and runs it again)
+    // before any access (the caller scans the log and runs it again).  A
+    // pointer that was read keeps its value for the runs that follow (a data
+    // access later in the instruction may need the scan carried further,
+    // past the pixels the pointer fetch saw).
     if (W.track && c.cx_need >= 0) return;
     const uint32_t next = (c.pc + ((d >> DW_LEN) & 3)) & 0xFFFF;
     uint32_t npc = next;
@@ -1656,6 +1672,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
         Cpu c;
         c.ram_off = (lane < LL ? lane : LL) * kRamStride;
         c.tia_off = (lane < LL ? lane : LL) * kTiaStride;
+        c.ptr_memo = -1;
         DevEnv* E = active ? &A.envs[env] : nullptr;
         uint64_t base_line = 0;
         uint32_t prev_action = 0, act = 0, step_idx = 0, score0 = 0, nfr = A.nframes;
@@ -1711,6 +1728,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
         c.ev = 0;
         uint32_t k = 0, done = 0;
         uint32_t f = 0;
+        uint32_t passes = 0;       // the wave's instruction passes (one per group instruction or opcode pass)
 
         auto begin_frame = [&]() {
             uint32_t eff = act;
@@ -1764,8 +1782,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             // of the earliest one (the whole wave when all lanes agree).
             bool uni = false;
             const uint32_t tmin = wave_min(active ? c.cyc : 0xFFFFFFFFu);
+            const int lead = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(active && c.cyc == tmin));
+            uint32_t ran = 0;          // instructions the group ran on the scalar path
             if (active) {
-                const int lead = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(c.cyc == tmin));
                 const uint32_t pc0 = rdl(c.pc, lead), bk0 = rdl(c.bank, lead);
                 const int32_t fl0 = rdl(c.fl, lead), or0 = rdl(c.open_row, lead);
                 const uint32_t oc0 = rdl(c.open_cnt, lead), ob0 = rdl(c.open_base, lead);
@@ -1774,8 +1793,13 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                                   c.open_row == or0 && c.open_cnt == oc0 && c.open_base == ob0 &&
                                   (c.log != nullptr ? 1u : 0u) == lg0;
                 const uint32_t partial = __builtin_amdgcn_ballot_w64(!same) != 0 ? 1u : 0u;
-                if (same) uni = run_fast<TRACK>(c, W, W.pre, ended, end_t, partial);
+                if (same) {
+                    const uint32_t ic0 = c.icount;
+                    uni = run_fast<TRACK>(c, W, W.pre, ended, end_t, partial);
+                    ran = c.icount - ic0;
+                }
             }
+            passes += (uint32_t)__builtin_amdgcn_readlane((int)ran, lead);
             const bool ran_uniform = __any(uni);
             const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;
             if (go) {
@@ -1815,6 +1839,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             // one pass per distinct opcode among the lanes that fetched one
             bool todo = want;
             while (__any(todo)) {
+                ++passes;
                 if (todo) {
                     const uint32_t sop = __builtin_amdgcn_readfirstlane(op);
                     // an opaque scalar copy: inside the branch below the compiler
@@ -1840,6 +1865,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                             c.ev = 0;
                         } else {
                             todo = false;
+                            if constexpr (TRACK) c.ptr_memo = -1;
                         }
                     }
                 }
@@ -1935,6 +1961,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 atomicAdd(&A.instr_total[1], (unsigned long long)c.ucount);
             }
         }
+        if (A.instr_total && lane == 0) atomicAdd(&A.instr_total[2], (unsigned long long)passes);
         if (!A.queue) break;
         __syncthreads();   // every lane is done with the LDS of this tile
         tile_id = take_tile(A.queue);

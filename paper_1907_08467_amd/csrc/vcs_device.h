@@ -183,7 +183,8 @@ struct InterpArgs {
     int32_t* reward;          // [n outputs] or NULL
     uint8_t* done;            // [n outputs] or NULL
     uint32_t* err_word;       // [0] bits, [1] smallest env id with an error
-    unsigned long long* instr_total;
+    unsigned long long* instr_total;   // [0] instructions (summed over lanes), [1] of them on the
+                                       // scalar path, [2] wave instruction passes; or NULL
     uint32_t* queue;          // NULL: workgroup b runs tile b; else workgroups take
                               // tiles from this counter until it passes *n_tiles
     uint32_t track;           // collision latches tracked
@@ -267,7 +268,7 @@ inline size_t policy_swizzle_index(uint32_t c, uint32_t k, uint32_t NT) {
 void launch_argmax(const float* logits, uint32_t n, uint8_t* actions, hipStream_t s);
 void launch_stack(uint8_t* ring, uint8_t* head, const int32_t* ids, uint32_t n, uint32_t num_envs, uint32_t depth,
                   uint32_t bits, const uint8_t* obs, const uint8_t* done, uint8_t* out, hipStream_t s);
-void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, hipStream_t s);
+void launch_step_begin(uint32_t* zero, uint32_t n_zero, uint32_t* tag, uint32_t residue, hipStream_t s);
 void launch_validate(const int32_t* ids, uint32_t n, uint32_t num_envs, const uint16_t* env_rom,
                      uint32_t* claim, const uint32_t* tag, uint32_t* counts, uint8_t* valid, StepInfo* info,
                      int32_t* reward, uint8_t* done, uint32_t* err_word, hipStream_t s);

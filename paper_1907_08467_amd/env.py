@@ -122,6 +122,11 @@ class VcsEnv:
     def last_step_stats(self):
         return B.vcs_last_step_stats(self._h)
 
+    def last_step_counts(self):
+        """(instructions, of them on the wave-uniform path, wave instruction
+        passes) of the last step; lane utilisation = instr / (64 * passes)."""
+        return B.vcs_last_step_counts(self._h)
+
     def timing(self, enable):
         B.vcs_timing(self._h, enable)
 

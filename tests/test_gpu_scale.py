@@ -35,7 +35,9 @@ def sample_envs(env_rom, per_rom, seed):
     return np.array(sorted(out), np.int32)
 
 
-def run_sampled(c, steps, per_rom, check_every, **extra):
+def run_sampled(c, steps, per_rom, check_every, min_dones=0, **extra):
+    """min_dones: episodes that must end among the sampled envs (so the
+    eager reset from the cache runs at full size, in the same launch)."""
     import torch
     from paper_1907_08467_amd.env import VcsEnv
     w = config(c)
@@ -78,18 +80,23 @@ def run_sampled(c, steps, per_rom, check_every, **extra):
     say(f"c{c}: {ids.size} sampled envs x {steps} steps agree; episodes ended among them: {dones}; "
         f"gpu error bits {errs_g[1]:#x}")
     assert errs_g[1] == 0
+    assert dones >= min_dones, f"c{c}: only {dones} episodes ended among the sampled envs"
     g.close()
     o.close()
 
 
 def test_plain_batch_4096_sampled():
-    """All 4096 envs of the plain batched step, frameskip 4, every frame."""
-    run_sampled(2, steps=60, per_rom=96, check_every=20)
+    """All 4096 envs of the plain batched step, frameskip 4, every frame, for
+    480 steps: the cartridge ends an episode after 1938 frames and the cache
+    entries start 65-95 frames in, so every env ends its first episode
+    between steps 461 and 469 and restarts from the cache in that step."""
+    run_sampled(2, steps=480, per_rom=96, check_every=40, min_dones=90)
 
 
 def test_divergent_32768_sampled():
-    """32768 envs over 8 ROMs (4 KB and F8), sticky actions p = 0.25."""
-    run_sampled(3, steps=40, per_rom=12, check_every=20)
+    """32768 envs over 8 ROMs (4 KB and F8), sticky actions p = 0.25, 160
+    steps: the ROMs whose episodes last 584 and 655 frames end them."""
+    run_sampled(3, steps=160, per_rom=12, check_every=40, min_dones=12)
 
 
 def test_divergent_32768_noops_after_copy_sampled():
@@ -100,8 +107,9 @@ def test_divergent_32768_noops_after_copy_sampled():
 
 
 def test_batching_65536_sampled():
-    """65536 envs, 16 ROMs in Zipf populations, last two frames rendered."""
-    run_sampled(4, steps=30, per_rom=6, check_every=15)
+    """65536 envs, 16 ROMs in Zipf populations, last two frames rendered, 160
+    steps: the ROMs whose episodes last 546 and 666 frames end them."""
+    run_sampled(4, steps=160, per_rom=6, check_every=40, min_dones=6)
 
 
 def test_plain_batch_4096_all_envs_states():

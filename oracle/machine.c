@@ -43,14 +43,18 @@
  *    when it is released), the ball (ENABL, CTRLPF size), vertical delay (a
  *    GRP0 write copies GRP1 to its old register, a GRP1 write copies GRP0 and
  *    ENABL), RESM/RESBL at h < 68 ? 2 : h - 68 + 4, HMOVE moving all five by
- *    their HM nibbles and, when written before colour clock 68, blanking
- *    pixels 0-7 of its line; priority P0/M0 > P1/M1 > PF/BL > BK (PF/BL
- *    first with CTRLPF D2), the ball in COLUPF.
+ *    the extra motion pulses that fall in horizontal blank (the HM nibble's
+ *    signed motion for a strobe early in the blank, less for later ones)
+ *    and, when written before colour clock 68, blanking pixels 0-7 of its
+ *    line; priority P0/M0 > P1/M1 > PF/BL > BK (PF/BL first with CTRLPF
+ *    D2), the ball in COLUPF.
  *  - Collisions (when tracked): the 15 latches set at every drawn pixel of
  *    the 210 frame rows (VBLANK clear, outside an HMOVE blank) where two
  *    objects meet; a read at access cycle t sees pixels up to colour clock
- *    3t+2; CXCLR clears them; untracked, they read 0, and instruction fetches
- *    and zero-page pointer fetches (no side effects) always read them as 0.
+ *    3t+2; CXCLR clears them; untracked, they read 0.  The TIA drives them
+ *    on every read cycle of a collision register, so an opcode, operand or
+ *    zero-page pointer byte fetched from one shows them too, through colour
+ *    clock 3t+2 of the instruction's first cycle t.
  *  - Undocumented opcodes: the stable ones (SLO, RLA, SRE, RRA, SAX, LAX,
  *    DCP, ISC, ANC, ALR, ARR, SBX, LAS, SBC #, and the NOPs of every width,
  *    which perform their read) run with the operations, cycle counts and
@@ -383,15 +387,33 @@ static void tia_write(OMachine* m, uint16_t reg, uint8_t v) {
         }
         break;
     }
-    case 0x2A: {                       /* HMOVE: every object by its signed high nibble, now */
+    case 0x2A: {
+        /* HMOVE.  After the strobe at clock h the TIA sends up to 15 extra
+           motion pulses, one every 4 clocks (clocks h+4, h+8, ..., the
+           count running on into the next line); an object takes its first
+           n = (HM nibble) XOR 8 of them, and a pulse moves it one pixel left
+           only where its position counter is not clocked anyway: in
+           horizontal blank (clocks 0-67 of a line, 0-75 on a line whose
+           blank the strobe extended).  A strobe before clock 68 extends its
+           line's blank by 8 clocks, which withholds 8 ordinary clocks (8
+           pixels right).  The strobe early in the blank gives the nibble's
+           signed motion; late strobes lose the pulses that fall in the
+           visible part.  The resulting move is applied now. */
         const uint8_t hm[5] = {m->hmp0, m->hmp1, m->hmm0, m->hmm1, m->hmbl};
         uint8_t* pos[5] = {&m->p0x, &m->p1x, &m->m0x, &m->m1x, &m->blx};
+        const int extended = h_eff < 68;
         for (int i = 0; i < 5; i++) {
-            int d = (hm[i] >> 4) & 0xF;
-            if (d >= 8) d -= 16;
-            *pos[i] = (uint8_t)(((int)*pos[i] - d + 160) % 160);
+            const int n = ((hm[i] >> 4) & 0xF) ^ 8;
+            int left = 0;
+            for (int k = 1; k <= n; k++) {
+                const uint32_t clk = h_eff + 4u * (uint32_t)k;   /* on the strobe's line, or past its end */
+                const int blank = clk < 228 ? clk < (extended ? 76u : 68u) : clk - 228 < 68;
+                if (blank) left++;
+            }
+            if (extended) left -= 8;
+            *pos[i] = (uint8_t)(((int)*pos[i] - left + 320) % 160);
         }
-        if (h_eff < 68) m->hmove_blank_line = (int64_t)((m->access_cycle + 1) / 76);
+        if (extended) m->hmove_blank_line = (int64_t)((m->access_cycle + 1) / 76);
         break;
     }
     case 0x2B: m->hmp0 = m->hmp1 = m->hmm0 = m->hmm1 = m->hmbl = 0; break;

@@ -846,7 +846,6 @@ __device__ __forceinline__ void set_flag_reg(uint8_t* R, uint32_t k, uint32_t v,
     R[k == 8 ? R_FLAGS2 : R_FLAGS] = (uint8_t)flags;
 }
 
-__device__ __forceinline__ int32_t hm_delta(uint32_t hm) { return sext8(hm & 0xF0) >> 4; }
 
 // Apply one queued TIA write of `v` to register `reg` made at cycle t: the
 // row-log entries of what it changes for the renderer, then the registers.
@@ -912,13 +911,13 @@ __device__ __forceinline__ void tia_apply(Cpu& c, const Wave& W, uint32_t reg, u
         set_flag_reg(R, 7 + i, v, fl);
         return;
     }
-    case 0x2A: {                                // HMOVE: every object by its motion nibble, now
-        const uint32_t p0 = (uint32_t)(((int32_t)R[R_P0X] - hm_delta(c.hmp0) + 160) % 160);
-        const uint32_t p1 = (uint32_t)(((int32_t)R[R_P1X] - hm_delta(c.hmp1) + 160) % 160);
-        const uint32_t m0 = (uint32_t)(((int32_t)R[R_M0X] - hm_delta(R[R_HMM0]) + 160) % 160);
-        const uint32_t m1 = (uint32_t)(((int32_t)R[R_M1X] - hm_delta(R[R_HMM1]) + 160) % 160);
-        const uint32_t bl = (uint32_t)(((int32_t)R[R_BLX] - hm_delta(R[R_HMBL]) + 160) % 160);
+    case 0x2A: {                                // HMOVE: every object by the pulses its blank takes, now
         const uint32_t ln = (t + 1) / 76, h = 3 * (t + 1 - 76 * ln);
+        const uint32_t p0 = hm_move(R[R_P0X], hmove_left(h, c.hmp0 >> 4));
+        const uint32_t p1 = hm_move(R[R_P1X], hmove_left(h, c.hmp1 >> 4));
+        const uint32_t m0 = hm_move(R[R_M0X], hmove_left(h, R[R_HMM0] >> 4));
+        const uint32_t m1 = hm_move(R[R_M1X], hmove_left(h, R[R_HMM1] >> 4));
+        const uint32_t bl = hm_move(R[R_BLX], hmove_left(h, R[R_HMBL] >> 4));
         if (lg)   // one entry: the renderer applies the five motion nibbles itself
             log_event(c, W, t, R_HMOVE | ((R[R_HMBL] >> 4) & 15), ((c.hmp0 >> 4) & 15) | (c.hmp1 & 0xF0),
                       ((R[R_HMM0] >> 4) & 15) | (R[R_HMM1] & 0xF0));

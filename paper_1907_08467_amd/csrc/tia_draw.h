@@ -61,10 +61,25 @@ __device__ __forceinline__ void set_byte(Regs& r, uint32_t i, uint32_t v) {
     }
 }
 
-// position p moved by HMOVE with motion nibble n (a signed 4-bit amount,
-// positive to the left), wrapping at 160
-__device__ __forceinline__ uint32_t hm_move(uint32_t p, uint32_t n) {
-    int32_t q = (int32_t)p - (((int32_t)(n & 15) ^ 8) - 8);
+// Pixels an object moves left on an HMOVE written at colour clock h of its
+// line, with motion nibble n (HMxx >> 4).  The strobe is followed by up to 15
+// extra motion pulses at clocks h + 4j (j = 1, 2, ...); the object takes the
+// first n ^ 8 of them, and a pulse moves it only in horizontal blank: clocks
+// 0-67 of a line, 0-75 on the strobe's line when the strobe came before
+// clock 68 (which extends that blank and so holds every object 8 pixels
+// back).  In closed form: before clock 68, min(n ^ 8, (75 - h) / 4) - 8 (the
+// nibble's signed value while h <= 15); from clock 68 on, the pulses from
+// j0 = (231 - h) / 4 on fall in the next line's blank: max(0, (n ^ 8) + 1 -
+// j0).
+__device__ __forceinline__ int32_t hmove_left(uint32_t h, uint32_t n) {
+    const int32_t pulses = (int32_t)((n & 15) ^ 8);
+    if (h < 68) return min(pulses, (int32_t)((75 - h) >> 2)) - 8;
+    return max(0, pulses + 1 - (int32_t)((231 - h) >> 2));
+}
+
+// position p moved `left` pixels to the left (-8..15), wrapping at 160
+__device__ __forceinline__ uint32_t hm_move(uint32_t p, int32_t left) {
+    int32_t q = (int32_t)p - left;
     q += q < 0 ? 160 : 0;
     q -= q >= 160 ? 160 : 0;
     return (uint32_t)q;
@@ -75,12 +90,13 @@ __device__ __forceinline__ void apply(Regs& r, uint32_t e) {
     const uint32_t code = (e >> 8) & 0xFF, v0 = (e >> 16) & 0xFF, v1 = e >> 24;
     if (code == R_END) {
         r.outside = true;
-    } else if (code >= R_HMOVE) {                                   // all five objects by their motion
-        set_byte_in<3>(r, 0, hm_move(rb<R_P0X>(r), v0));
-        set_byte_in<3>(r, 8, hm_move(rb<R_P1X>(r), v0 >> 4));
-        set_byte_in<5>(r, 0, hm_move(rb<R_M0X>(r), v1));
-        set_byte_in<5>(r, 8, hm_move(rb<R_M1X>(r), v1 >> 4));
-        set_byte_in<5>(r, 16, hm_move(rb<R_BLX>(r), code));
+    } else if (code >= R_HMOVE) {   // all five objects by their motion (a logged HMOVE lands in the row: h = x + 68)
+        const uint32_t h = (e & 0xFF) + 68;
+        set_byte_in<3>(r, 0, hm_move(rb<R_P0X>(r), hmove_left(h, v0)));
+        set_byte_in<3>(r, 8, hm_move(rb<R_P1X>(r), hmove_left(h, v0 >> 4)));
+        set_byte_in<5>(r, 0, hm_move(rb<R_M0X>(r), hmove_left(h, v1)));
+        set_byte_in<5>(r, 8, hm_move(rb<R_M1X>(r), hmove_left(h, v1 >> 4)));
+        set_byte_in<5>(r, 16, hm_move(rb<R_BLX>(r), hmove_left(h, code)));
     } else if (code == R_RESMP) {                                   // RESMP0: flags, missile 0 position
         set_byte_in<5>(r, 24, v0);
         set_byte_in<5>(r, 0, v1);

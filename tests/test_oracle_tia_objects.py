@@ -114,12 +114,60 @@ def test_resmp_release_centres_missile(nusiz, pos):
 def test_hmove_moves_missiles_and_ball():
     setup = "    lda #2\n    sta ENAM0\n    sta ENABL\n    lda #$36\n    sta COLUP0\n    lda #$44\n    sta COLUPF\n" \
             "    sta WSYNC\n" + AT42 + "    sta RESM0\n" + "    sta WSYNC\n" + "    nop\n" * 24 + "    sta RESBL\n" \
-            "    lda #$F0\n    sta HMM0\n    lda #$20\n    sta HMBL\n    sta HMOVE\n"
-    # RESBL: 24 NOPs -> access cycle 50 -> clock 153 -> position 89; HMM0 $F0 moves +1, HMBL $20 moves -2
+            "    lda #$F0\n    sta HMM0\n    lda #$20\n    sta HMBL\n    sta WSYNC\n    sta HMOVE\n"
+    # RESBL: 24 NOPs -> access cycle 50 -> clock 153 -> position 89; an HMOVE at the start of the
+    # blank (clock 9): HMM0 $F0 moves +1, HMBL $20 moves -2
     f, _ = run(rom_with(setup))
     assert lit(f[ROW]) == {66, 87} and f[ROW][66] == 0x36 and f[ROW][87] == 0x44
-    f, _ = run(rom_with(setup + "    sta HMCLR\n    sta HMOVE"))
-    assert lit(f[ROW]) == {66, 87}                    # HMCLR: a second HMOVE moves nothing
+    f, _ = run(rom_with(setup + "    sta HMCLR\n    sta WSYNC\n    sta HMOVE"))
+    assert lit(f[ROW]) == {66, 87}                    # HMCLR: an early second HMOVE moves nothing
+    # the first HMOVE late instead (no WSYNC before it: access cycle 63, clock 192): of the pulses
+    # at clocks 196, 200, ..., those from 228 on (the 9th and later) reach the next line's blank:
+    # HMM0 $F0 (7 pulses) moves nothing, HMBL $20 (10 pulses) moves 2 left
+    late = setup.replace("    sta WSYNC\n    sta HMOVE\n", "    sta HMOVE\n")
+    f, _ = run(rom_with(late))
+    assert lit(f[ROW]) == {65, 87}
+    # then HMCLR and a second late HMOVE (access cycle 69, clock 210): pulses 5-8 of the 8 that
+    # cleared registers let through land in the next blank: both move 4 left
+    f, _ = run(rom_with(late + "    sta HMCLR\n    sta HMOVE"))
+    assert lit(f[ROW]) == {61, 83}
+
+
+def pulse_rom(nops):
+    """HMP0 $70, HMP1 $80, HMM0 $00, HMM1 $30, HMBL $F0; P0 and P1 placed at 66,
+    M0, M1 and the ball at 65; then one line: `nops` NOPs and STA HMOVE,
+    whose write is at access cycle 2 nops + 2, clock h = 6 nops + 9."""
+    setup = "    lda #$70\n    sta HMP0\n    lda #$80\n    sta HMP1\n    lda #$00\n    sta HMM0\n" \
+            "    lda #$30\n    sta HMM1\n    lda #$F0\n    sta HMBL\n"
+    for reg in ("RESP0", "RESP1", "RESM0", "RESM1", "RESBL"):
+        setup += "    sta WSYNC\n" + AT42 + f"    sta {reg}\n"
+    setup += "    sta WSYNC\n" + "    nop\n" * nops + "    sta HMOVE\n"
+    return rom_with(setup)
+
+
+# Positions (P0, P1, M0, M1, BL) after one HMOVE at clock h = 6 nops + 9.  The objects take
+# n = 15, 0, 8, 11, 7 pulses (HM nibble XOR 8), at clocks h + 4, h + 8, ...; a pulse moves its
+# object one pixel left only in horizontal blank (clocks 0-67, 0-75 on a line whose blank an
+# HMOVE before clock 68 extended, which also holds it 8 pixels right).  Derived by hand:
+#  h =   9: blank to 76, pulses up to h + 64 = 73 count: all n   -> n - 8 left: 59 74 65 62 66
+#  h =  21: pulses up to 21 + 52 = 73: min(n, 13)                -> 61 74 65 62 66
+#  h =  39: pulses up to 39 + 36 = 75: min(n, 9)                 -> 65 74 65 64 66
+#  h =  63: pulses up to 63 + 12 = 75: min(n, 3)                 -> 71 74 70 70 70
+#  h =  69: no extension; every pulse (73 .. 129) in the visible part: none   -> 66 66 65 65 65
+#  h = 189: pulses from the 10th (189 + 40 = 229) in the next blank: n - 9    -> 60 66 65 63 65
+#  h = 207: from the 6th (207 + 24 = 231): n - 5                              -> 56 66 62 59 63
+#  h = 225: all (225 + 4 = 229): n                                            -> 51 66 57 54 58
+@pytest.mark.parametrize("nops,want", [(0, (59, 74, 65, 62, 66)), (2, (61, 74, 65, 62, 66)),
+                                       (5, (65, 74, 65, 64, 66)), (9, (71, 74, 70, 70, 70)),
+                                       (10, (66, 66, 65, 65, 65)), (30, (60, 66, 65, 63, 65)),
+                                       (33, (56, 66, 62, 59, 63)), (36, (51, 66, 57, 54, 58))])
+def test_hmove_pulse_timing(nops, want):
+    rom = pulse_rom(nops)
+    st, _, _, got_frames = oracle.run_frames(oracle.power_on(rom), rom, 2, actions=np.zeros(2, np.uint8))
+    assert got_frames == 2 and decode(st)["err"] == 0
+    st = np.asarray(st, np.uint8)
+    got = (int(st[176]), int(st[177]), int(st[221]), int(st[222]), int(st[223]))
+    assert got == want
 
 
 def test_hmove_blank():

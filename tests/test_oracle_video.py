@@ -153,8 +153,8 @@ def test_player_position_and_reflection():
 
 @pytest.mark.parametrize("hm,pos", [(0xF0, 67), (0x70, 59), (0x80, 74)])
 def test_hmove(hm, pos):
-    # one HMOVE in the setup moves the player by -signed(high nibble)
-    rom = _player_rom(0x80, extra=f"    lda #${hm:02X}\n    sta HMP0\n    sta HMOVE")
+    # one HMOVE at the start of a horizontal blank moves the player by -signed(high nibble)
+    rom = _player_rom(0x80, extra=f"    lda #${hm:02X}\n    sta HMP0\n    sta WSYNC\n    sta HMOVE")
     row = frames_of(rom)[-1][80]
     assert set(np.nonzero(row)[0].tolist()) == {pos}
 

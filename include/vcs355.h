@@ -194,6 +194,21 @@ int vcs_step(vcs_ctx* ctx, const int32_t* env_ids_dev, const uint8_t* actions_de
 int vcs_step_pipe(vcs_ctx* ctx, uint32_t pipe, const int32_t* env_ids_dev, const uint8_t* actions_dev, uint32_t n,
                   uint8_t* obs_dev, int32_t* reward_dev, uint8_t* done_dev, uint8_t* frames_dev, void* stream);
 
+/* vcs_step for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+   device or host allocation, no event, no synchronisation.  Its scratch (row
+   logs of the last two frames of each env, collision logs, step info, id
+   validity, tiles, counters) is a static device array of 43.7 MB that every
+   GPU the library runs on holds until the process ends, shared by every call
+   and context on that GPU: calls on one GPU that overlap in time (different
+   streams, or different host threads) race and must be serialised by the
+   caller.  Limits: n <= 512 envs per call, at most 1024 ROMs loaded, and a
+   context without noop_after_copy (VCS_E_INVAL otherwise).  Arguments and
+   results as vcs_step, without the frames output: observations, rewards,
+   done flags and env states equal those of vcs_step on the same inputs. */
+int vcs_step_noalloc(vcs_ctx* ctx, const int32_t* env_ids_dev, const uint8_t* actions_dev, uint32_t n,
+                     uint8_t* obs_dev, int32_t* reward_dev, uint8_t* done_dev, void* stream);
+
 /* Machine-state record (384 bytes, little-endian) of one env:
      0 A  1 X  2 Y  3 SP  4 P  5 bank state bits 0-7  6..7 PC
      8..15 cycle (start of the next instruction, since power-on)

@@ -75,6 +75,7 @@ def _declare(L):
     L.vcs_reset.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp]
     L.vcs_step.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp]
     L.vcs_step_pipe.argtypes = [_vp, ctypes.c_uint32, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp]
+    L.vcs_step_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp]
     L.vcs_get_state.argtypes = [_vp, ctypes.c_uint32, _vp]
     L.vcs_set_state.argtypes = [_vp, ctypes.c_uint32, _vp]
     L.vcs_get_cache.argtypes = [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp]
@@ -173,6 +174,11 @@ def vcs_step(h, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_p
 def vcs_step_pipe(h, pipe, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_ptr, stream):
     check(lib.vcs_step_pipe(h, pipe, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, frames_ptr, stream),
           "vcs_step_pipe")
+
+
+def vcs_step_noalloc(h, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, stream):
+    check(lib.vcs_step_noalloc(h, ids_ptr, actions_ptr, n, obs_ptr, reward_ptr, done_ptr, stream),
+          "vcs_step_noalloc")
 
 
 def vcs_get_state(h, env):

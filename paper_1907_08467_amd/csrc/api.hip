@@ -53,7 +53,7 @@ struct Pipe {
     Tile* d_tiles = nullptr;        // [tiles_cap]
     uint32_t* d_n_tiles = nullptr;
     uint32_t* d_tag = nullptr;      // claim tag: residue + 16 x (calls that validated ids)
-    uint32_t residue = 0;           // its tags' residue mod 16: the pipeline index
+    uint32_t residue = 0;           // its tags' residue mod 16: the pipeline index (8: the shared scratch)
     uint32_t* d_stepw = nullptr;
     uint32_t* d_counts = nullptr;
     unsigned long long* d_instr = nullptr;
@@ -112,7 +112,50 @@ struct vcs_ctx {
     std::vector<TimedLaunch> timed;
 };
 
+// ---------------------------------------------------------------- static scratch
+//
+// The scratch of vcs_step_noalloc: row logs for the last two frames of up to
+// kNoAllocEnvs envs, the logs of unrendered frames for tracked collisions,
+// step info, id validity, tiles, per-call counters and a claim tag, in one
+// file-scope device array.  Every GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress gives on that device (g_scratch, taken when a context
+// is created there).  All calls on one GPU share it.
+constexpr uint32_t kNoAllocEnvs = 512;
+constexpr uint32_t kNoAllocRoms = 1024;
+constexpr uint32_t kNoAllocTiles = kNoAllocEnvs + kNoAllocRoms;    // tiles of 1 env each, + one partial per ROM
+constexpr uint32_t kNoAllocStepw = 3 * kNoAllocRoms + 16;         // per-call words of kNoAllocRoms ROMs
+constexpr size_t sc_align(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kScLogs = 0;
+constexpr size_t kScCxLogs = kScLogs + sc_align((size_t)kNoAllocEnvs * 2 * kFrameLogBytes);
+constexpr size_t kScInfo = kScCxLogs + sc_align((size_t)kNoAllocEnvs * kFrameLogBytes);
+constexpr size_t kScValid = kScInfo + sc_align(kNoAllocEnvs * sizeof(StepInfo));
+constexpr size_t kScTiles = kScValid + sc_align(kNoAllocEnvs);
+constexpr size_t kScNTiles = kScTiles + sc_align((size_t)kNoAllocTiles * sizeof(Tile));
+constexpr size_t kScTag = kScNTiles + 256;
+constexpr size_t kScStepw = kScTag + 256;
+constexpr size_t kScratchBytes = kScStepw + sc_align(kNoAllocStepw * 4);   // 43.7 MB
+constexpr uint32_t kScratchResidue = 8;   // claim tags of the shared scratch: 8 mod 16
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 namespace {
+
+uint8_t* g_scratch[kMaxDevices] = {};   // scratch's address on each device (nullptr: not taken yet)
+
+// Take scratch's device address on `dev` (current) once; the array's host
+// name is no device address.
+int take_scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(VCS_E_INVAL, "device ordinal beyond the scratch table");
+    if (g_scratch[dev]) return VCS_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(VCS_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = static_cast<uint8_t*>(ptr);
+    return VCS_OK;
+}
 
 int dev_alloc(vcs_ctx* c, void** p, size_t bytes, const char* what) {
     if (c->cfg.hbm_budget_bytes && c->allocated + bytes > c->cfg.hbm_budget_bytes)
@@ -613,6 +656,11 @@ int vcs_create(const vcs_config* cfg, vcs_ctx** out) {
         vcs_destroy(c);
         return fail(VCS_E_HIP, "initial device copies failed");
     }
+    rc = take_scratch_address(cfg->device);   // with the device current
+    if (rc) {
+        vcs_destroy(c);
+        return rc;
+    }
     *out = c;
     return VCS_OK;
 }
@@ -1051,6 +1099,46 @@ int vcs_step_pipe(vcs_ctx* c, uint32_t pipe, const int32_t* ids, const uint8_t* 
     if (rc || n == 0) return rc;
     if (pipe >= c->pipes.size()) return fail(VCS_E_INVAL, "no such pipeline");
     return enqueue_step(c, pipe, ids, actions, n, obs, reward, done, frames, (hipStream_t)stream);
+}
+
+int vcs_step_noalloc(vcs_ctx* c, const int32_t* ids, const uint8_t* actions, uint32_t n, uint8_t* obs,
+                     int32_t* reward, uint8_t* done, void* stream) {
+    if (!c) return fail(VCS_E_INVAL, "null context");
+    if (!c->assigned) return fail(VCS_E_STATE, "vcs_assign first");
+    if (n == 0) return VCS_OK;
+    if (!actions || !reward || !done) return fail(VCS_E_INVAL, "actions, reward and done are required");
+    if (n > kNoAllocEnvs) return fail(VCS_E_INVAL, "vcs_step_noalloc takes at most 512 envs per call");
+    if (n > c->cfg.num_envs) return fail(VCS_E_INVAL, "n exceeds num_envs");
+    if (c->cfg.noop_after_copy) return fail(VCS_E_INVAL, "vcs_step_noalloc does not run reset no-ops after the copy");
+    if (c->n_roms > kNoAllocRoms) return fail(VCS_E_INVAL, "vcs_step_noalloc takes at most 1024 ROMs");
+    if ((n + c->launch.tile_envs - 1) / c->launch.tile_envs + c->n_roms > kNoAllocTiles ||
+        c->stepw_words > kNoAllocStepw)
+        return fail(VCS_E_INVAL, "the call's tiles or counters exceed the static scratch");
+    const int dev = c->cfg.device;
+    if (dev < 0 || dev >= kMaxDevices || !g_scratch[dev]) return fail(VCS_E_STATE, "scratch address not taken");
+    uint8_t* base = g_scratch[dev];   // the device address, never the array's host name
+    Pipe P;
+    P.d_logs = base + kScLogs;
+    P.d_cxlogs = c->cfg.collisions ? base + kScCxLogs : nullptr;
+    P.d_info = reinterpret_cast<StepInfo*>(base + kScInfo);
+    P.d_valid = base + kScValid;
+    P.d_tiles = reinterpret_cast<Tile*>(base + kScTiles);
+    P.d_n_tiles = reinterpret_cast<uint32_t*>(base + kScNTiles);
+    P.d_tag = reinterpret_cast<uint32_t*>(base + kScTag);
+    P.residue = kScratchResidue;
+    P.d_stepw = reinterpret_cast<uint32_t*>(base + kScStepw);
+    P.d_counts = P.d_stepw;
+    P.d_instr = reinterpret_cast<unsigned long long*>(P.d_stepw + c->instr_off);
+    P.d_queue = P.d_stepw + c->instr_off + 6;
+    // the step's kernels, with its counters and tiles cleared or rebuilt by
+    // kernels; no event or buffer is created here
+    const bool timing = c->timing;
+    c->timing = false;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = enqueue_sim_on(c, P, 2, false, ids, actions, n, obs, reward, done, nullptr, s);
+    if (!rc) rc = enqueue_render_on(c, P, 2, n, obs, nullptr, s);
+    c->timing = timing;
+    return rc;
 }
 
 int vcs_get_state(vcs_ctx* c, uint32_t env, uint8_t* out) {

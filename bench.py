@@ -263,7 +263,7 @@ def bench_plain(args, c=2):
     dt = time.perf_counter() - t0
     env.timing(False)
     ep1 = episodes_ended(env) if args.count_episodes else None
-    instr_last, instr_uniform, passes = env.last_step_counts()
+    instr_last, instr_uniform, passes, rounds = env.last_step_counts()
     kern = kernel_table(env)
     value = eager_value = n * w.frameskip * K / dt
     eager_ms = dt / K * 1e3
@@ -322,7 +322,7 @@ def bench_plain(args, c=2):
         "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
         "emulated_instr_per_step": instr_last,
         "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
-        "lane_utilisation": lane_util(instr_last, passes), "wave_passes": passes,
+        "lane_utilisation": lane_util(instr_last, passes), "wave_passes": passes, "wave_rounds": rounds,
         "errors": bits,
         "cpu_baseline": cpu,
     }
@@ -384,12 +384,13 @@ def bench_batching(args):
             torch.cuda.synchronize()
             env.timing(False)
             kern = kernel_table(env)
-        instr_last, instr_uniform, passes = env.last_step_counts()
+        instr_last, instr_uniform, passes, rounds = env.last_step_counts()
         bits = env.poll_errors()[1]
         finals[form] = [t.cpu().numpy() for t in last]
         res[form] = {"value": n * w.frameskip * K / dt, "ms_per_step": dt / K * 1e3, "launch": launch,
                      "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
                      "lane_utilisation": lane_util(instr_last, passes), "wave_passes": passes,
+                     "wave_rounds": rounds,
                      "launch_from": launch_from, "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
                      "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
                      "render_roofline": render_roofline(kern, n, 2, False), "errors": bits}

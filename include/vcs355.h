@@ -254,13 +254,15 @@ int vcs_last_step_stats(vcs_ctx* ctx, uint64_t* out2);
 
 /* Divergence of the last vcs_step (paper, Section 4: threads of one warp
    that take different branches run their paths one after another, and full
-   divergence would leave one thread of 32 busy).  out3[0]: instructions
-   emulated (summed over envs); out3[1]: those run on the wave-uniform path;
-   out3[2]: instruction passes of the interpreter's waves: one for each
+   divergence would leave one thread of 32 busy).  out4[0]: instructions
+   emulated (summed over envs); out4[1]: those run on the wave-uniform path;
+   out4[2]: instruction passes of the interpreter's waves: one for each
    instruction that a group of lanes ran together on the wave-uniform path,
-   and one for each opcode pass of the per-lane path.  Active-lane
-   utilisation = out3[0] / (64 * out3[2]).  Synchronises. */
-int vcs_last_step_counts(vcs_ctx* ctx, uint64_t* out3);
+   and one for each opcode pass of the per-lane path; out4[3]: scheduling
+   rounds of those waves (a group formed, then its run on the wave-uniform
+   path or a round of per-lane passes).  Active-lane utilisation =
+   out4[0] / (64 * out4[2]).  Synchronises. */
+int vcs_last_step_counts(vcs_ctx* ctx, uint64_t* out4);
 
 /* Average device time of the named kernel over the timed region: the caller
    brackets steps with vcs_timing(ctx, 1) ... vcs_timing(ctx, 0), then reads

@@ -105,7 +105,7 @@ def _declare(L):
     L.vcs_last_error.argtypes = []
     L.vcs_last_error.restype = ctypes.c_char_p
     for name in ("vcs_create", "vcs_load_roms", "vcs_assign", "vcs_reset", "vcs_step", "vcs_step_pipe",
-                 "vcs_get_state",
+                 "vcs_step_noalloc", "vcs_get_state",
                  "vcs_set_state", "vcs_get_cache", "vcs_poll_errors", "vcs_last_step_instructions", "vcs_last_step_stats",
                  "vcs_last_step_counts",
                  "vcs_timing", "vcs_kernel_time", "vcs_set_launch", "vcs_get_launch", "vcs_autotune",
@@ -219,9 +219,9 @@ def vcs_last_step_stats(h):
 
 
 def vcs_last_step_counts(h):
-    v = (ctypes.c_uint64 * 3)()
+    v = (ctypes.c_uint64 * 4)()
     check(lib.vcs_last_step_counts(h, v), "vcs_last_step_counts")
-    return v[0], v[1], v[2]
+    return v[0], v[1], v[2], v[3]
 
 
 def vcs_timing(h, enable):

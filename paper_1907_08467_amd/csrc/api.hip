@@ -753,14 +753,14 @@ int vcs_load_roms(vcs_ctx* c, uint32_t n_roms, const uint8_t* const* rom_host, c
     if (!rc) rc = alloc_n(c, &c->d_cmap, n_roms, "ROM mappings");
     if (!rc) rc = alloc_n(c, &c->d_pre_off, n_roms, "ROM mappings");
     const uint32_t instr_off = (3 * n_roms + 1) & ~1u;   // 8-byte aligned counters
-    c->stepw_words = instr_off + 7;
+    c->stepw_words = instr_off + 9;
     c->instr_off = instr_off;
     for (auto& P : c->pipes) {
         if (!rc) rc = alloc_n(c, &P.d_stepw, c->stepw_words, "per-call counters");
         if (rc) break;
         P.d_counts = P.d_stepw;
-        P.d_instr = reinterpret_cast<unsigned long long*>(P.d_stepw + instr_off);   // 3 counters
-        P.d_queue = P.d_stepw + instr_off + 6;
+        P.d_instr = reinterpret_cast<unsigned long long*>(P.d_stepw + instr_off);   // 4 counters
+        P.d_queue = P.d_stepw + instr_off + 8;
     }
     if (!rc) rc = ensure_tile_buffer(c);
     if (rc) return rc;
@@ -1129,7 +1129,7 @@ int vcs_step_noalloc(vcs_ctx* c, const int32_t* ids, const uint8_t* actions, uin
     P.d_stepw = reinterpret_cast<uint32_t*>(base + kScStepw);
     P.d_counts = P.d_stepw;
     P.d_instr = reinterpret_cast<unsigned long long*>(P.d_stepw + c->instr_off);
-    P.d_queue = P.d_stepw + c->instr_off + 6;
+    P.d_queue = P.d_stepw + c->instr_off + 8;
     // the step's kernels, with its counters and tiles cleared or rebuilt by
     // kernels; no event or buffer is created here
     const bool timing = c->timing;
@@ -1218,13 +1218,13 @@ int vcs_last_step_stats(vcs_ctx* c, uint64_t* out2) {
     return VCS_OK;
 }
 
-int vcs_last_step_counts(vcs_ctx* c, uint64_t* out3) {
-    if (!c || !out3) return fail(VCS_E_INVAL, "null argument");
+int vcs_last_step_counts(vcs_ctx* c, uint64_t* out4) {
+    if (!c || !out4) return fail(VCS_E_INVAL, "null argument");
     HIP_OK(hipSetDevice(c->cfg.device));
     HIP_OK(hipDeviceSynchronize());
-    unsigned long long v[3] = {0, 0, 0};
-    if (c->pipes[0].d_instr) HIP_OK(hipMemcpy(v, c->pipes[0].d_instr, 24, hipMemcpyDeviceToHost));
-    for (int i = 0; i < 3; ++i) out3[i] = v[i];
+    unsigned long long v[4] = {0, 0, 0, 0};
+    if (c->pipes[0].d_instr) HIP_OK(hipMemcpy(v, c->pipes[0].d_instr, 32, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 4; ++i) out4[i] = v[i];
     return VCS_OK;
 }
 

@@ -1728,6 +1728,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
         uint32_t k = 0, done = 0;
         uint32_t f = 0;
         uint32_t passes = 0;       // the wave's instruction passes (one per group instruction or opcode pass)
+        uint32_t rounds = 0;       // its scheduling rounds (group formed, then scalar run or per-lane passes)
 
         auto begin_frame = [&]() {
             uint32_t eff = act;
@@ -1780,6 +1781,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             // Scalar mode for the group of running lanes at exactly the place
             // of the earliest one (the whole wave when all lanes agree).
             bool uni = false;
+            ++rounds;
             const uint32_t tmin = wave_min(active ? c.cyc : 0xFFFFFFFFu);
             const int lead = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(active && c.cyc == tmin));
             uint32_t ran = 0;          // instructions the group ran on the scalar path
@@ -1835,8 +1837,13 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                     c.tqm = 0;
                 }
             }
-            // one pass per distinct opcode among the lanes that fetched one
+            // one pass per distinct opcode among the lanes that fetched one.
+            // The instruction is counted, and `ran_lane` set, where it
+            // completes: counting after the passes under the fetch mask
+            // counted more instructions than ran in waves whose lanes took
+            // the undocumented RRA / ISC at different places.
             bool todo = want;
+            uint32_t ran_lane = 0;
             while (__any(todo)) {
                 ++passes;
                 if (todo) {
@@ -1864,17 +1871,18 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                             c.ev = 0;
                         } else {
                             todo = false;
+                            ran_lane = 1;
+                            if (!(c.err & ERR_ILLEGAL)) c.icount++;
                             if constexpr (TRACK) c.ptr_memo = -1;
                         }
                     }
                 }
             }
-            if (want) {
+            if (ran_lane) {
                 if (c.err & ERR_ILLEGAL) {
                     ended = true;
                     end_t = c.cyc - 1;
                 } else {
-                    c.icount++;
                     const uint32_t t = c.ac;
                     apply_queue(c, W, t);
                     if (c.ev & EV_WSYNC) c.cyc = 76 * (t / 76 + 1);
@@ -1887,7 +1895,7 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             // Every iteration moves some lane on (the earliest lane always
             // runs); if none moved, stop the wave's frames with an error
             // instead of spinning.
-            if (!__any(want || uni || ended) && active) {
+            if (!__any(ran_lane != 0 || uni || ended) && active) {
                 c.err |= ERR_FRAME_CAP;
                 ended = true;
                 end_t = c.cyc;
@@ -1960,7 +1968,10 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 atomicAdd(&A.instr_total[1], (unsigned long long)c.ucount);
             }
         }
-        if (A.instr_total && lane == 0) atomicAdd(&A.instr_total[2], (unsigned long long)passes);
+        if (A.instr_total && lane == 0) {
+            atomicAdd(&A.instr_total[2], (unsigned long long)passes);
+            atomicAdd(&A.instr_total[3], (unsigned long long)rounds);
+        }
         if (!A.queue) break;
         __syncthreads();   // every lane is done with the LDS of this tile
         tile_id = take_tile(A.queue);

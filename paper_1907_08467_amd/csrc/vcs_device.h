@@ -184,7 +184,8 @@ struct InterpArgs {
     uint8_t* done;            // [n outputs] or NULL
     uint32_t* err_word;       // [0] bits, [1] smallest env id with an error
     unsigned long long* instr_total;   // [0] instructions (summed over lanes), [1] of them on the
-                                       // scalar path, [2] wave instruction passes; or NULL
+                                       // scalar path, [2] wave instruction passes, [3] wave
+                                       // scheduling rounds; or NULL
     uint32_t* queue;          // NULL: workgroup b runs tile b; else workgroups take
                               // tiles from this counter until it passes *n_tiles
     uint32_t track;           // collision latches tracked

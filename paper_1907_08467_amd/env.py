@@ -124,7 +124,8 @@ class VcsEnv:
 
     def last_step_counts(self):
         """(instructions, of them on the wave-uniform path, wave instruction
-        passes) of the last step; lane utilisation = instr / (64 * passes)."""
+        passes, wave scheduling rounds) of the last step; lane utilisation =
+        instr / (64 * passes)."""
         return B.vcs_last_step_counts(self._h)
 
     def timing(self, enable):

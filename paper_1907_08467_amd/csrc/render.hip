@@ -34,9 +34,22 @@ __device__ __forceinline__ uint32_t byte_masks(uint32_t n) { return ((n * 0x0020
 // (m & a) | (~m & b)
 __device__ __forceinline__ uint32_t pick(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
 
+// What a drawn pixel holds, as a word of four equal bytes: the colour index
+// (frames), or its gray level from the lookup table (observations: drawing
+// gray directly takes one table read per colour register instead of one per
+// pixel).
+struct ColourPal {
+    __device__ __forceinline__ uint32_t operator()(uint32_t c) const { return (c & 0xFE) * 0x01010101u; }
+};
+struct GrayPal {
+    const uint8_t* lut;       // 128 entries in LDS
+    __device__ __forceinline__ uint32_t operator()(uint32_t c) const { return (uint32_t)lut[(c & 0xFE) >> 1] * 0x01010101u; }
+};
+
 // the 16 pixels of the common case: one copy of each player at normal width,
 // no missile, no ball, no vertical delay, no HMOVE blank
-__device__ __forceinline__ uint4 draw16_plain(const Regs& r, uint32_t x0) {
+template <class Pal>
+__device__ __forceinline__ uint4 draw16_plain(const Regs& r, uint32_t x0, const Pal& pal) {
     if (r.outside || (rb<R_VBLANK>(r) & 2)) return make_uint4(0, 0, 0, 0);
     const bool right = x0 >= 80;
     const uint32_t ctrlpf = rb<R_CTRLPF>(r);
@@ -50,8 +63,8 @@ __device__ __forceinline__ uint4 draw16_plain(const Regs& r, uint32_t x0) {
     const uint32_t s1 = (rb<R_REFP1>(r) & 8) ? g1 : (__builtin_bitreverse32(g1) >> 24);
     const uint32_t m0 = window16s(s0, 8, rb<R_P0X>(r), x0), m1 = window16s(s1, 8, rb<R_P1X>(r), x0);
     const uint32_t pfc = (ctrlpf & 2) ? (right ? rb<R_COLUP1>(r) : rb<R_COLUP0>(r)) : rb<R_COLUPF>(r);
-    const uint32_t c0 = (rb<R_COLUP0>(r) & 0xFE) * 0x01010101u, c1 = (rb<R_COLUP1>(r) & 0xFE) * 0x01010101u;
-    const uint32_t cp = (pfc & 0xFE) * 0x01010101u, cb = (rb<R_COLUBK>(r) & 0xFE) * 0x01010101u;
+    const uint32_t c0 = pal(rb<R_COLUP0>(r)), c1 = pal(rb<R_COLUP1>(r));
+    const uint32_t cp = pal(pfc), cb = pal(rb<R_COLUBK>(r));
     const bool pf_first = (ctrlpf & 4) != 0;
     uint32_t w[4];
 #pragma unroll
@@ -64,19 +77,20 @@ __device__ __forceinline__ uint4 draw16_plain(const Regs& r, uint32_t x0) {
 }
 
 // the 16 pixels x0 .. x0+15 of row `row` drawn with registers r
-__device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0, uint32_t row) {
+template <class Pal>
+__device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0, uint32_t row, const Pal& pal) {
     // ENAM0/1, ENABL and its copy, the VDEL bits clear, both NUSIZ modes 0, no blank
     if (!(rb<R_FLAGS>(r) & 0x7F) && !((rb<R_NUSIZ0>(r) | rb<R_NUSIZ1>(r)) & 7) && rb<R_HMB>(r) == 0)
-        return draw16_plain(r, x0);
+        return draw16_plain(r, x0, pal);
     uint32_t o[6], shown;
     objects16(r, x0, row, o, shown);
     if (!shown) return make_uint4(0, 0, 0, 0);
     const bool right = x0 >= 80;
     const uint32_t ctrlpf = rb<R_CTRLPF>(r);
     const uint32_t pfc = (ctrlpf & 2) ? (right ? rb<R_COLUP1>(r) : rb<R_COLUP0>(r)) : rb<R_COLUPF>(r);
-    const uint32_t c0 = (rb<R_COLUP0>(r) & 0xFE) * 0x01010101u, c1 = (rb<R_COLUP1>(r) & 0xFE) * 0x01010101u;
-    const uint32_t cp = (pfc & 0xFE) * 0x01010101u, cf = (rb<R_COLUPF>(r) & 0xFE) * 0x01010101u;
-    const uint32_t cb = (rb<R_COLUBK>(r) & 0xFE) * 0x01010101u;
+    const uint32_t c0 = pal(rb<R_COLUP0>(r)), c1 = pal(rb<R_COLUP1>(r));
+    const uint32_t cp = pal(pfc), cf = pal(rb<R_COLUPF>(r));
+    const uint32_t cb = pal(rb<R_COLUBK>(r));
     const uint32_t m0 = o[2] | o[4], m1 = o[3] | o[5], mf = o[0] | o[1];   // P0/M0, P1/M1, PF/BL
     const bool pf_first = (ctrlpf & 4) != 0;
     uint32_t w[4];
@@ -95,8 +109,12 @@ __device__ __forceinline__ uint4 draw16(const Regs& r, uint32_t x0, uint32_t row
 // Row `row` drawn left to right, 16 pixels at a time: the row snapshot, then
 // each logged write from its x position on, every write applied once.
 // emit(seg, q) receives pixels 16 seg .. 16 seg + 15 packed little-endian.
-template <class Emit>
-__device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, Emit&& emit) {
+// The row's first kPre entries are loaded together, before any is needed (one
+// memory round trip instead of one per entry); later ones as they come.
+constexpr uint32_t kPre = 8;
+
+template <class Pal, class Emit>
+__device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, const Pal& pal, Emit&& emit) {
     const uint8_t* rec = frame_log + row * kSnapBytes;
     const uint4 s = *reinterpret_cast<const uint4*>(rec);
     const uint4 s2 = *reinterpret_cast<const uint4*>(rec + 16);
@@ -108,21 +126,34 @@ __device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, Em
         for (int seg = 0; seg < kCols / 16; ++seg) emit(seg, make_uint4(0, 0, 0, 0));
         return;
     }
+    // Eight unconditional loads issued back to back: the entry stream holds
+    // 5,280 entries and a frame logs at most 5,251, so the words past a row's
+    // last entry are still inside the log (their values are never used).
+    // They form a queue in eight registers (no indexing, which would put them
+    // in scratch memory): q0 is the next entry; popping shifts the others
+    // down and loads the entry after them, if the row has one.
+    uint32_t q0 = ents[0], q1 = ents[1], q2 = ents[2], q3 = ents[3];
+    uint32_t q4 = ents[4], q5 = ents[5], q6 = ents[6], q7 = ents[7];
     uint32_t ei = 0;
-    uint32_t e = cnt ? ents[0] : 0;
+    auto next_entry = [&]() -> uint32_t {
+        ++ei;
+        q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
+        q7 = ei + (kPre - 1) < cnt ? ents[ei + (kPre - 1)] : 0u;
+        return ei < cnt ? q0 : 0u;
+    };
+    uint32_t e = cnt ? q0 : 0u;
     for (int seg = 0; seg < kCols / 16; ++seg) {
         const uint32_t x0 = 16u * (uint32_t)seg;
         while (ei < cnt && (e & 0xFF) <= x0) {      // writes that take effect before the segment
             apply(r, e);
-            ++ei;
-            e = ei < cnt ? ents[ei] : 0;
+            e = next_entry();
         }
         uint4 out = make_uint4(0, 0, 0, 0);
         uint32_t start = 0;                         // first pixel of the current run
         for (;;) {
             const bool more = ei < cnt && (e & 0xFF) < x0 + 16;
             const uint32_t end = more ? (e & 0xFF) - x0 : 16;
-            const uint4 px = draw16(r, x0, (uint32_t)row);
+            const uint4 px = draw16(r, x0, (uint32_t)row, pal);
             const uint32_t run = ((1u << end) - 1) & ~((1u << start) - 1);
             out.x = pick(byte_masks(run & 0xF), px.x, out.x);
             out.y = pick(byte_masks((run >> 4) & 0xF), px.y, out.y);
@@ -132,8 +163,7 @@ __device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, Em
             const uint32_t xe = e & 0xFF;
             while (ei < cnt && (e & 0xFF) == xe) {  // every write at this pixel, in order
                 apply(r, e);
-                ++ei;
-                e = ei < cnt ? ents[ei] : 0;
+                e = next_entry();
             }
             start = end;
         }
@@ -141,15 +171,15 @@ __device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, Em
     }
 }
 
-// bytewise maximum of two packed 4 x u8 words
+// bytewise maximum of two packed 4 x u8 words: the even and the odd bytes
+// as two pairs of 16-bit lanes, one packed maximum each
 __device__ __forceinline__ uint32_t max4u8(uint32_t a, uint32_t b) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t x = (a >> (8 * k)) & 0xFF, y = (b >> (8 * k)) & 0xFF;
-        r |= (x > y ? x : y) << (8 * k);
-    }
-    return r;
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    const uint32_t ae = a & 0x00FF00FFu, be = b & 0x00FF00FFu;
+    const uint32_t ao = (a >> 8) & 0x00FF00FFu, bo = (b >> 8) & 0x00FF00FFu;
+    const u16x2 me = __builtin_elementwise_max(__builtin_bit_cast(u16x2, ae), __builtin_bit_cast(u16x2, be));
+    const u16x2 mo = __builtin_elementwise_max(__builtin_bit_cast(u16x2, ao), __builtin_bit_cast(u16x2, bo));
+    return __builtin_bit_cast(uint32_t, me) | (__builtin_bit_cast(uint32_t, mo) << 8);
 }
 
 constexpr int kSegs = kCols / 16;            // 10 segments per row
@@ -167,7 +197,7 @@ __global__ void __launch_bounds__(512) k_render_frames(RenderArgs A) {
     if (valid) {
         const uint8_t* lg = A.logs + ((size_t)i * A.n_slots + slot) * kFrameLogBytes;
         for (int row = threadIdx.x; row < kRows; row += blockDim.x)
-            render_row(lg, row, [&](int seg, const uint4 q) { s_f[row * kSegs + seg] = q; });
+            render_row(lg, row, ColourPal{}, [&](int seg, const uint4 q) { s_f[row * kSegs + seg] = q; });
     }
     __syncthreads();
     for (int c = threadIdx.x; c < kFrameBytes / 16; c += blockDim.x) dst[c] = valid ? s_f[c] : make_uint4(0, 0, 0, 0);
@@ -196,8 +226,22 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
         uint8_t* dst = A.frames ? A.frames + ((size_t)i * A.n_slots + slot) * kFrameBytes : nullptr;
         if (!valid && !dst) continue;
         for (int row = threadIdx.x; row < kRows; row += blockDim.x) {
+            if (!dst) {        // observation only: the row drawn in gray levels straight away
+                if (want_obs && valid) {
+                    render_row(lg, row, GrayPal{s_lut}, [&](int seg, const uint4 g) {
+                        uint4* mq = reinterpret_cast<uint4*>(s_m + (row * kCols + seg * 16) / 4);
+                        if (first) {
+                            *mq = g;
+                        } else {
+                            const uint4 o = *mq;
+                            *mq = make_uint4(max4u8(o.x, g.x), max4u8(o.y, g.y), max4u8(o.z, g.z), max4u8(o.w, g.w));
+                        }
+                    });
+                }
+                continue;
+            }
             auto emit = [&](int seg, const uint4 q) {
-                if (dst) s_f[row * kSegs + seg] = q;
+                s_f[row * kSegs + seg] = q;
                 if (want_obs && valid) {
                     const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
                     uint32_t* mrow = s_m + (row * kCols + seg * 16) / 4;
@@ -211,7 +255,7 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
                 }
             };
             if (valid) {
-                render_row(lg, row, emit);
+                render_row(lg, row, ColourPal{}, emit);
             } else {
                 for (int seg = 0; seg < kSegs; ++seg) emit(seg, make_uint4(0, 0, 0, 0));
             }

@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import itertools
 import time
 
 import numpy as np
@@ -64,6 +65,7 @@ class Request:
     seq: int = 0
     t_done: float = 0.0
     sched: np.ndarray | None = None   # env-steps already put into a batch
+    unsched: int = 0                  # env-steps not put into a batch yet
     left: int = 0                     # env-steps not finished yet
     out: tuple | None = None          # (obs, reward, done) buffers of the request
 
@@ -150,7 +152,7 @@ class EnvServer:
         self.num_envs = num_envs
         self.on_result = on_result
         self.clock = clock
-        self.pending = []                               # requests with unscheduled env-steps
+        self.pending = collections.deque()              # requests with unscheduled env-steps, in arrival order
         self.inflight = [None] * backend.pipelines      # parts (request, positions, lo, hi)
         self.busy = np.zeros(num_envs, dtype=bool)      # env in a batch on the device
         self.stamp = np.zeros(num_envs, dtype=np.int64) # merge pass that last claimed the env
@@ -173,9 +175,14 @@ class EnvServer:
         req.seq = self.seq
         self.seq += 1
         req.sched = np.zeros(k, dtype=bool)
+        req.unsched = k
         req.left = k
         req.out = self.backend.alloc(k)
         self.pending.append(req)
+
+    # a merge looks at most this many pending requests from the head of the
+    # queue, so its cost stays bounded when requests pile up (overload)
+    SCAN_REQUESTS = 256
 
     def _merge(self):
         """One batch of env-steps that may run now, in arrival order."""
@@ -183,9 +190,11 @@ class EnvServer:
         stamp = self.passes
         parts, ids, acts = [], [], []
         size = 0
-        for r in self.pending:
+        for r in itertools.islice(self.pending, self.SCAN_REQUESTS):
             if size == self.max_batch:
                 break
+            if r.unsched == 0:
+                continue
             un = np.flatnonzero(~r.sched)
             e = r.ids[un]
             ok = ~self.busy[e] & (self.stamp[e] != stamp)
@@ -194,12 +203,14 @@ class EnvServer:
             self.stamp[e] = stamp                      # later requests may not pass these envs
             if pos.size:
                 r.sched[pos] = True
+                r.unsched -= pos.size
                 self.busy[r.ids[pos]] = True
                 parts.append((r, pos, size, size + pos.size))
                 ids.append(r.ids[pos])
                 acts.append(r.actions[pos])
                 size += pos.size
-        self.pending = [r for r in self.pending if not r.sched.all()]
+        while self.pending and self.pending[0].unsched == 0:
+            self.pending.popleft()
         if not parts:
             return None
         return parts, np.concatenate(ids).astype(np.int32), np.concatenate(acts).astype(np.uint8)
@@ -327,8 +338,8 @@ def run_served(server, actors, seconds, clock=time.perf_counter, record=None):
     if actors.open_loop:
         # an overloaded open loop never catches up: finish what is on the
         # device, count the rest as backlog and drop it
-        backlog = int(sum(int((~r.sched).sum()) for r in server.pending))
-        server.pending = []
+        backlog = int(sum(r.unsched for r in server.pending))
+        server.pending = collections.deque()
     server.drain()
     t1 = clock()
     server.on_result = user_cb

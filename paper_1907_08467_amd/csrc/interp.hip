@@ -1046,6 +1046,9 @@ __device__ __forceinline__ uint32_t store_class(uint32_t a) {
 // registers (the other player's graphics; with GRP1, ENABL), which the
 // renderer repeats from its own state.  Returns 0, before changing anything,
 // when the row's entries are full (the per-lane path then records the error).
+// PLAIN: `sc` is known to be SC_TIA | code (a register stored as is); the
+// code may then differ between lanes.
+template <int PLAIN = 0>
 __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F, uint32_t sc, uint32_t v,
                                                   uint32_t t) {
     const uint32_t ln = (t + 1) / 76;
@@ -1053,7 +1056,7 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
     uint8_t* R = W.tia + c.tia_off;
     uint32_t code = sc & 0x1F;
     uint32_t v0 = v, full = 0;
-    if (sc >= SC_TIAS && sc < SC_TIAG) {
+    if (!PLAIN && sc >= SC_TIAS && sc < SC_TIAG) {
         if (code == R_P0X || code == R_P1X) {
             v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
         } else if (code >= R_M0X && code <= R_BLX) {
@@ -1100,7 +1103,7 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
             }
         }
     }
-    if (sc >= SC_TIAG) {
+    if (!PLAIN && sc >= SC_TIAG) {
         if (code == R_GRP0) {
             R[R_GRP1_OLD] = R[R_GRP1];
         } else {
@@ -1597,6 +1600,202 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
 #undef VCS_FAST_4
 #undef VCS_FAST_CASE
 
+// ------------------------------------------------- two-bank group runs
+//
+// On bank-switched cartridges, lanes can stand at the same address and cycle
+// in two different banks.  Where the instruction there has the same opcode
+// in both banks (operands may differ), the lanes still run it as one group:
+// the predecoded words of both banks come from two scalar loads, dispatch,
+// store class and timing stay scalar, and each lane takes its bank's
+// operand bytes.  Covered: implied and accumulator instructions, immediates,
+// zero-page reads of RAM, zero-page stores whose target class agrees (RAM,
+// WSYNC, a TIA register stored as is, or one with no emulated effect),
+// relative branches and absolute jumps (the lanes part where their targets
+// differ), and absolute reads of the cartridge at one address in both banks
+// (a bank hotspot among them: the run ends after it).  Anything else ends
+// the run before executing it.
+
+// One instruction with opcode OP; qa / qb: its predecoded word in bank A /
+// bank B; in_b: the lane is in bank B.
+template <int OP>
+__device__ __forceinline__ uint32_t mop(Cpu& c, const Wave& W, Fast& F, bool in_b, uint32_t qa, uint32_t qb) {
+    constexpr OpInfo I = decode(OP);
+    constexpr int MD = I.md, MN = I.mn;
+    constexpr uint32_t N = (uint32_t)I.cyc;
+    const uint32_t next = (F.pc + (uint32_t)op_len(MD)) & 0xFFFF;
+    const uint32_t a1 = (qa >> 8) & 0xFF, a2 = (qa >> 16) & 0xFF;   // bank A's operand bytes
+    const uint32_t x1 = (qb >> 8) & 0xFF, x2 = (qb >> 16) & 0xFF;   // bank B's
+    const uint32_t b1 = in_b ? x1 : a1;                              // the lane's
+    if constexpr (MN == ILL || MN == BRK || MN == RTI || MN >= SLO || (MN == NOP && MD != IMP)) {
+        return FS_EXIT;
+    } else if constexpr (MD == IMP || MD == ACC) {
+        return fop<OP, false>(c, W, F, 0, 0, 0);   // no operand bytes; memory only through the stack
+    } else if constexpr (MD == IMM) {
+        uint32_t dm = 0;
+        if constexpr (MN == ADC || MN == SBC) {
+            dm = dec_mode(c);
+            if (dm == 2) return FS_EXIT;
+        }
+        fast_alu(c, MN, b1, dm);
+        F.pc = next;
+        F.cyc += N;
+        return FS_NEXT;
+    } else if constexpr (MD == ZP && read_mn(MN)) {
+        if (!(a1 & x1 & 0x80)) return FS_EXIT;    // RAM in both banks' operands
+        uint32_t dm = 0;
+        if constexpr (MN == ADC || MN == SBC) {
+            dm = dec_mode(c);
+            if (dm == 2) return FS_EXIT;
+        }
+        fast_alu(c, MN, W.ram[c.ram_off + (b1 & 0x7F)], dm);
+        F.pc = next;
+        F.cyc += N;
+        return FS_NEXT;
+    } else if constexpr (MD == ZP && store_mn(MN)) {
+        const uint32_t auxa = qa >> 24, auxb = qb >> 24;      // store classes
+        const uint32_t cat = auxa < SC_TIA ? auxa : (auxa & 0xE0);
+        if (cat != (auxb < SC_TIA ? auxb : (auxb & 0xE0))) return FS_EXIT;
+        const uint32_t t = F.cyc + N - 1;
+        const uint32_t v = store_value<MN>(c);
+        if (cat == SC_RAM) {
+            W.ram[c.ram_off + (b1 & 0x7F)] = (uint8_t)v;
+        } else if (cat == SC_TIA) {
+            if (!fast_tia_code<1>(c, W, F, in_b ? auxb : auxa, v & 0xFF, t)) return FS_EXIT;
+        } else if (cat == SC_WSYNC) {
+            return fast_finish(F, next, t, 1);
+        } else if (cat != SC_IGNORE) {
+            return FS_EXIT;
+        }
+        F.pc = next;
+        F.cyc += N;
+        return FS_NEXT;
+    } else if constexpr (MD == REL) {
+        bool taken;
+        if constexpr (MN == BPL) taken = !(c.p & FN);
+        else if constexpr (MN == BMI) taken = (c.p & FN) != 0;
+        else if constexpr (MN == BVC) taken = !(c.p & FV);
+        else if constexpr (MN == BVS) taken = (c.p & FV) != 0;
+        else if constexpr (MN == BCC) taken = !(c.p & FC);
+        else if constexpr (MN == BCS) taken = (c.p & FC) != 0;
+        else if constexpr (MN == BNE) taken = !(c.p & FZ);
+        else taken = (c.p & FZ) != 0;
+        const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
+        const uint32_t npc = taken ? tgt : next;
+        const uint32_t ncyc = F.cyc + N + (taken ? 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0) : 0);
+        const uint32_t p0 = rfl(npc), c0 = rfl(ncyc);
+        if (all_lanes(npc == p0 && ncyc == c0)) {
+            F.pc = p0;
+            F.cyc = c0;
+            return FS_NEXT;
+        }
+        c.pc = npc;                           // the lanes part here
+        c.cyc = ncyc;
+        return FS_LANE;
+    } else if constexpr (MN == JMP && MD == ABS) {
+        const uint32_t ta = a1 | (a2 << 8), tb = x1 | (x2 << 8);
+        if (ta == tb) {
+            F.pc = ta;
+            F.cyc += N;
+            return FS_NEXT;
+        }
+        c.pc = in_b ? tb : ta;
+        c.cyc = F.cyc + N;
+        return FS_LANE;
+    } else if constexpr (MD == ABS && read_mn(MN)) {
+        const uint32_t a = (a1 | (a2 << 8)) & 0x1FFF;
+        if (a1 != x1 || a2 != x2 || !(a & 0x1000) || cm_sc(W)) return FS_EXIT;
+        uint32_t dm = 0;
+        if constexpr (MN == ADC || MN == SBC) {
+            dm = dec_mode(c);
+            if (dm == 2) return FS_EXIT;
+        }
+        // each lane reads its own bank, after the access's bank switch
+        c.bank = hotspot(W, c.bank, a);
+        fast_alu(c, MN, W.rom[rom_off(W, c.bank, a)], dm);
+        F.pc = next;
+        F.cyc += N;
+        F.stop = 1;                           // the banks may have changed: regroup
+        return FS_NEXT;
+    } else {
+        return FS_EXIT;
+    }
+}
+
+#define VCS_MB_CASE(o) \
+    case (o): st = mop<(o)>(c, W, F, in_b, qa, qb); break;
+#define VCS_MB_4(o) VCS_MB_CASE(o) VCS_MB_CASE((o) + 1) VCS_MB_CASE((o) + 2) VCS_MB_CASE((o) + 3)
+#define VCS_MB_16(o) VCS_MB_4(o) VCS_MB_4((o) + 4) VCS_MB_4((o) + 8) VCS_MB_4((o) + 12)
+#define VCS_MB_64(o) VCS_MB_16(o) VCS_MB_16((o) + 16) VCS_MB_16((o) + 32) VCS_MB_16((o) + 48)
+
+// Runs the lanes in exec (same address, cycle, frame line and row-log
+// position; each in bank `ba` or `bb` of a linearly mapped cartridge, both
+// present) while the opcode agrees and mop covers it.  Same contract as
+// run_fast; `in_b`: the lane is in bank bb.
+__device__ __forceinline__ bool run_mb(Cpu& c, const Wave& W, const uint32_t* pre, bool& ended, uint32_t& end_t,
+                                       uint32_t partial, uint32_t ba, uint32_t bb, bool in_b) {
+    Fast F;
+    F.partial = partial;
+    F.stop = 0;
+    F.pc = rfl(c.pc);
+    F.bank = ba;
+    F.cyc = rfl(c.cyc);
+    F.cap = rfl(c.cap);
+    F.fl = rfl(c.fl);
+    F.orow = (uint32_t)(rfl(c.open_row) + 1);
+    F.ocnt = rfl(c.open_cnt);
+    F.obase = rfl(c.open_base);
+    F.logon = rfl(c.log != nullptr ? 1u : 0u);
+    uint32_t done_n = 0;
+    uint32_t st = FS_EXIT;
+    uint32_t capped = 0;
+    for (;;) {
+        if (F.cyc >= F.cap) {
+            capped = 1;
+            break;
+        }
+        if ((F.pc & 0x1FFF) - 0x1000u > 0xFFDu) {
+            st = FS_EXIT;
+            break;
+        }
+        const uint32_t qa = pre[(ba << 12) | (F.pc & 0xFFF)];
+        const uint32_t qb = pre[(bb << 12) | (F.pc & 0xFFF)];
+        const uint32_t op = qa & 0xFF;
+        if ((qb & 0xFF) != op) {
+            st = FS_EXIT;
+            break;
+        }
+        switch (op) {
+            VCS_MB_64(0x00)
+            VCS_MB_64(0x40)
+            VCS_MB_64(0x80)
+            VCS_MB_64(0xC0)
+        }
+        if (st != FS_NEXT) break;
+        ++done_n;
+        if (F.stop) break;
+    }
+    if (capped) {
+        c.err |= ERR_FRAME_CAP;
+        ended = true;
+        end_t = F.cyc - 1;
+    }
+    if (st == FS_LANE) ++done_n;
+    if (st != FS_LANE) {
+        c.pc = F.pc;
+        c.cyc = F.cyc;
+    }
+    c.icount += done_n;
+    c.ucount += done_n;
+    c.open_row = (int32_t)F.orow - 1;
+    c.open_cnt = F.ocnt;
+    c.open_base = F.obase;
+    return done_n > 0 || capped;
+}
+#undef VCS_MB_64
+#undef VCS_MB_16
+#undef VCS_MB_4
+#undef VCS_MB_CASE
+
 __device__ __forceinline__ uint32_t bcd_value(uint32_t b) { return 10 * (b >> 4) + (b & 15); }
 
 // Minimum of v over the 64 lanes (call with every lane active): DPP swaps
@@ -1790,14 +1989,32 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                 const int32_t fl0 = rdl(c.fl, lead), or0 = rdl(c.open_row, lead);
                 const uint32_t oc0 = rdl(c.open_cnt, lead), ob0 = rdl(c.open_base, lead);
                 const uint32_t lg0 = rdl(c.log != nullptr ? 1u : 0u, lead);
-                const bool same = c.pc == pc0 && c.bank == bk0 && c.cyc == tmin && c.fl == fl0 &&
-                                  c.open_row == or0 && c.open_cnt == oc0 && c.open_base == ob0 &&
-                                  (c.log != nullptr ? 1u : 0u) == lg0;
-                const uint32_t partial = __builtin_amdgcn_ballot_w64(!same) != 0 ? 1u : 0u;
-                if (same) {
-                    const uint32_t ic0 = c.icount;
-                    uni = run_fast<TRACK>(c, W, W.pre, ended, end_t, partial);
-                    ran = c.icount - ic0;
+                const bool here = c.pc == pc0 && c.cyc == tmin && c.fl == fl0 && c.open_row == or0 &&
+                                  c.open_cnt == oc0 && c.open_base == ob0 && (c.log != nullptr ? 1u : 0u) == lg0;
+                const bool same = here && c.bank == bk0;
+                bool mixed_ran = false;
+                if constexpr (!TRACK) {
+                    // lanes at the same place in a second bank: one group while the opcode agrees
+                    const uint64_t other = __builtin_amdgcn_ballot_w64(here && !same);
+                    if (cm_kind(W) == CART_LINEAR && other != 0) {
+                        const uint32_t bb = rdl(c.bank, (int)__builtin_ctzll(other));
+                        const bool grp = here && (c.bank == bk0 || c.bank == bb);
+                        const uint32_t partial_grp = __builtin_amdgcn_ballot_w64(!grp) != 0 ? 1u : 0u;
+                        if (grp) {
+                            const uint32_t ic0 = c.icount;
+                            uni = run_mb(c, W, W.pre, ended, end_t, partial_grp, bk0, bb, c.bank == bb);
+                            ran = c.icount - ic0;
+                        }
+                        mixed_ran = __builtin_amdgcn_ballot_w64(uni) != 0;
+                    }
+                }
+                if (!mixed_ran) {
+                    const uint32_t partial = __builtin_amdgcn_ballot_w64(!same) != 0 ? 1u : 0u;
+                    if (same) {
+                        const uint32_t ic0 = c.icount;
+                        uni = run_fast<TRACK>(c, W, W.pre, ended, end_t, partial);
+                        ran = c.icount - ic0;
+                    }
                 }
             }
             passes += (uint32_t)__builtin_amdgcn_readlane((int)ran, lead);

@@ -41,11 +41,11 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 # ones they were taken on (sha256 prefix of the files concatenated), otherwise
 # null.
 MEASURED_TRAFFIC = {
-    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "c39579adf9bdd30d", (1334.2 * 2.0 + 206888.6) * 1024),
-    "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "70d4c62ee9a7fa24",
-                        (123909.9 * 2.0 + 268800.0) * 1024),
-    "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "70d4c62ee9a7fa24",
-                     (107924.7 * 2.0 + 297252.9) * 1024),
+    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "a50655f3e74469e7", (1281.5 * 2.0 + 162348.0) * 1024),
+    "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "1c55aa47cd4db54e",
+                        (41150.3 * 2.0 + 268800.0) * 1024),
+    "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "1c55aa47cd4db54e",
+                     (41131.2 * 2.0 + 297206.0) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
@@ -437,17 +437,24 @@ def bench_divergent(args, noop_after_copy=False, keep_step_ms=False):
     done = torch.empty(n, dtype=torch.uint8, device=dev)
     frames = torch.empty((n, w.frameskip, 210, 160), dtype=torch.uint8, device=dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    pts = sorted(set([0, 1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, 2000, 3000, 4000, K - 1]) & set(range(K)))
+    util = {}
     torch.cuda.synchronize()
     ev[0].record()
     for s in range(K):
         env.step(acts[s], out=(obs, rew, done, frames))
         ev[s + 1].record()
+        if s in pts:     # the step's counters (read after it: a sync at these few steps only)
+            instr, _, passes, rounds = env.last_step_counts()
+            util[str(s)] = {"lane_utilisation": lane_util(instr, passes), "instr": instr, "passes": passes,
+                            "rounds": rounds}
+        if s % 500 == 499:
+            print(f"divergent: step {s + 1} of {K}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(K)]
     total = sum(ms) * 1e-3
     value = n * w.frameskip * K / total
     bits = env.poll_errors()[1]
-    pts = sorted(set([0, 1, 2, 5, 10, 20, 50, 100, 200, 500, K - 1]) & set(range(K)))
     return {
         "metric": "raw emulated frames/s on 1 MI355X (p50/p99 step latency in served mode)",
         "value": value, "unit": "raw frames/s", "n_gpus": 1, "steps": K, "warmup": 0,
@@ -458,6 +465,7 @@ def bench_divergent(args, noop_after_copy=False, keep_step_ms=False):
                                "rendered + obs, eager steps from a fresh reset", "num_envs": n,
                    "launch": launch, "launch_from": launch_from},
         "fps_by_step": {str(s): n * w.frameskip / (ms[s] * 1e-3) for s in pts},
+        "interp_by_step": util,
         "errors": bits, "roofline": None, "cpu_baseline": None,
         **({"step_ms": ms} if keep_step_ms else {}),
     }

@@ -49,6 +49,7 @@ MEASURED_TRAFFIC = {
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+CLOCK_HZ = 2.4e9
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # policy CNN: output positions per env, output channels, reduction length
@@ -204,6 +205,21 @@ def interp_roofline(kern, instr, n, frameskip):
             "work_per_launch": f"{instr} emulated 6502 instructions ({n} envs x {frameskip} frames)"}
 
 
+def interp_latency(kern, passes, rounds, env_rom, tile=64):
+    """The interpreter's own bound, the latency of each wave's instruction
+    stream: cycles per wave instruction pass if every wave lived the whole
+    launch (an upper bound: waves that end early leave their SIMDs idle),
+    next to the cost of a pass for a wave on the plain step (SQ counters:
+    570 cycles, half of them issuing) and the scheduling rounds."""
+    t = kern["k_interp"]["mean_ms"] * 1e-3
+    counts = np.bincount(np.asarray(env_rom, dtype=np.int64))
+    waves = int(sum((int(c) + tile - 1) // tile for c in counts if c))
+    cyc = t * CLOCK_HZ * waves / passes if passes else None
+    return {"bound": "latency", "waves": waves, "wave_passes": passes, "scheduling_rounds": rounds,
+            "passes_per_round": passes / rounds if rounds else None,
+            "cycles_per_pass_if_all_waves_lived_the_launch": cyc, "cycles_per_pass_plain_step_counters": 570}
+
+
 def lane_util(instr, passes):
     """Active-lane utilisation of the interpreter: emulated instructions
     (summed over envs) over the lanes its waves' instruction passes offer."""
@@ -323,6 +339,7 @@ def bench_plain(args, c=2):
         "emulated_instr_per_step": instr_last,
         "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
         "lane_utilisation": lane_util(instr_last, passes), "wave_passes": passes, "wave_rounds": rounds,
+        "interp_latency": interp_latency(kern, passes, rounds, env_rom, launch["tile_envs"]),
         "errors": bits,
         "cpu_baseline": cpu,
     }
@@ -391,6 +408,7 @@ def bench_batching(args):
                      "uniform_mode_fraction": instr_uniform / instr_last if instr_last else 0.0,
                      "lane_utilisation": lane_util(instr_last, passes), "wave_passes": passes,
                      "wave_rounds": rounds,
+                     "interp_latency": interp_latency(kern, passes, rounds, env_rom, launch["tile_envs"]),
                      "launch_from": launch_from, "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
                      "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
                      "render_roofline": render_roofline(kern, n, 2, False), "errors": bits}

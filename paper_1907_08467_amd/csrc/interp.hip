@@ -1993,8 +1993,10 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
                                   c.open_cnt == oc0 && c.open_base == ob0 && (c.log != nullptr ? 1u : 0u) == lg0;
                 const bool same = here && c.bank == bk0;
                 bool mixed_ran = false;
-                if constexpr (!TRACK) {
+                if constexpr (!TRACK && RC > 0) {
                     // lanes at the same place in a second bank: one group while the opcode agrees
+                    // (launches with the cartridge staged in LDS: the 4 KB and 8 KB schemes; the
+                    // instantiation for larger cartridges keeps its code without it)
                     const uint64_t other = __builtin_amdgcn_ballot_w64(here && !same);
                     if (cm_kind(W) == CART_LINEAR && other != 0) {
                         const uint32_t bb = rdl(c.bank, (int)__builtin_ctzll(other));

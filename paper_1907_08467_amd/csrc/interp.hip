@@ -2021,6 +2021,11 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
             }
             passes += (uint32_t)__builtin_amdgcn_readlane((int)ran, lead);
             const bool ran_uniform = __any(uni);
+            // A group ran and no lane's frame ended: nothing else happens this
+            // round (no per-lane pass, no frame change), so the next round
+            // starts at once; the short path back spares the common round
+            // most of its bookkeeping.
+            if (ran_uniform && !__any(ended)) continue;
             const bool go = !ran_uniform && active && c.cyc <= tmin + kSchedWindow;
             if (go) {
                 if (c.cyc >= c.cap) {

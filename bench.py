@@ -41,11 +41,11 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 # ones they were taken on (sha256 prefix of the files concatenated), otherwise
 # null.
 MEASURED_TRAFFIC = {
-    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "a50655f3e74469e7", (1281.5 * 2.0 + 162348.0) * 1024),
+    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "57d7416b978beaff", (1302.9 * 2.0 + 162348.0) * 1024),
     "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "1c55aa47cd4db54e",
-                        (41150.3 * 2.0 + 268800.0) * 1024),
+                        (41150.4 * 2.0 + 268800.0) * 1024),
     "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "1c55aa47cd4db54e",
-                     (41131.2 * 2.0 + 297206.0) * 1024),
+                     (41130.9 * 2.0 + 297205.0) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
@@ -429,7 +429,8 @@ def bench_batching(args):
                    "num_envs": n, "frameskip": w.frameskip, "render": "last two", "launch": b["launch"],
                    "launch_from": b["launch_from"], "graph_steps": G},
         "roofline": b["roofline"], "render_roofline": b["render_roofline"], "kernels_ms": b["kernels_ms"],
-        "uniform_mode_fraction": b["uniform_mode_fraction"],
+        "uniform_mode_fraction": b["uniform_mode_fraction"], "lane_utilisation": b["lane_utilisation"],
+        "wave_passes": b["wave_passes"], "wave_rounds": b["wave_rounds"], "interp_latency": b["interp_latency"],
         "plain_kernel": res["plain"], "speedup_vs_plain": b["value"] / res["plain"]["value"],
         "last_step_identical_to_plain": bool(same), "errors": b["errors"] | res["plain"]["errors"],
         "cpu_baseline": None,

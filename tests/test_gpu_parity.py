@@ -93,6 +93,25 @@ def test_divergent_mix_reduced():
     compare_states(o, g, range(len(env_rom)), "c3 end")
 
 
+def test_two_bank_groups():
+    """Full 64-lane tiles of F8 cartridges whose bank swaps sit on random
+    paths (the same skeleton in both banks, other operands): lanes at one
+    address in two banks run as one group with per-lane operand bytes.
+    Every state is compared every 5 steps, frames every 10."""
+    w = config(3)
+    specs = [r for r in w.roms() if r.scheme == 1][:2]
+    assert len(specs) == 2
+    roms = [(r.data, r.scheme) for r in specs]
+    env_rom = np.repeat(np.arange(2, dtype=np.uint16), 128)
+    say("case: two-bank groups, 2 F8 ROMs x 128 envs")
+    o, g = make_pair(roms, env_rom, seed=w.rng_seed, sticky_threshold=w.sticky_threshold)
+    rng = np.random.default_rng(11)
+    for s in range(40):
+        step_both(o, g, rng.integers(0, 18, len(env_rom)), want_frames=(s % 10 == 0), tag=f"f8 step {s}")
+        if s % 5 == 4:
+            compare_states(o, g, range(len(env_rom)), f"f8 step {s}")
+
+
 def test_batching_mix_last2_reduced():
     """16 ROMs, Zipf populations, render of the last two frames only."""
     w = config(4)

@@ -39,12 +39,76 @@ __device__ __forceinline__ uint32_t pick(uint32_t m, uint32_t a, uint32_t b) { r
 // gray directly takes one table read per colour register instead of one per
 // pixel).
 struct ColourPal {
-    __device__ __forceinline__ uint32_t operator()(uint32_t c) const { return (c & 0xFE) * 0x01010101u; }
+    __device__ __forceinline__ uint32_t byte(uint32_t c) const { return c & 0xFE; }
+    __device__ __forceinline__ uint32_t operator()(uint32_t c) const { return byte(c) * 0x01010101u; }
 };
 struct GrayPal {
     const uint8_t* lut;       // 128 entries in LDS
-    __device__ __forceinline__ uint32_t operator()(uint32_t c) const { return (uint32_t)lut[(c & 0xFE) >> 1] * 0x01010101u; }
+    __device__ __forceinline__ uint32_t byte(uint32_t c) const { return lut[(c & 0xFE) >> 1]; }
+    __device__ __forceinline__ uint32_t operator()(uint32_t c) const { return byte(c) * 0x01010101u; }
 };
+
+// The common case's per-row state (what only a register write changes),
+// computed when a row starts and again after its writes: whether the common
+// case holds, the blank, the two sprites as drawn, and the colour of each
+// combination of objects as a byte table, index P0 << 2 | P1 << 1 | PF, for
+// the left and the right half (score mode colours the playfield by half).
+struct PlainRow {
+    uint32_t plain, blank;
+    uint32_t s0, s1, p0x, p1x;
+    uint32_t lo_l, hi_l, lo_r, hi_r;      // table bytes 0-3 / 4-7
+};
+
+template <class Pal>
+__device__ __forceinline__ void plain_row(PlainRow& ps, const Regs& r, const Pal& pal) {
+    ps.plain = (!(rb<R_FLAGS>(r) & 0x7F) && !((rb<R_NUSIZ0>(r) | rb<R_NUSIZ1>(r)) & 7) && rb<R_HMB>(r) == 0) ? 1u : 0u;
+    ps.blank = (r.outside || (rb<R_VBLANK>(r) & 2)) ? 1u : 0u;
+    const uint32_t g0 = rb<R_GRP0>(r), g1 = rb<R_GRP1>(r);
+    ps.s0 = (rb<R_REFP0>(r) & 8) ? g0 : (__builtin_bitreverse32(g0) >> 24);
+    ps.s1 = (rb<R_REFP1>(r) & 8) ? g1 : (__builtin_bitreverse32(g1) >> 24);
+    ps.p0x = rb<R_P0X>(r);
+    ps.p1x = rb<R_P1X>(r);
+    const uint32_t ctrlpf = rb<R_CTRLPF>(r);
+    const uint32_t c0 = pal.byte(rb<R_COLUP0>(r)), c1 = pal.byte(rb<R_COLUP1>(r));
+    const uint32_t cf = pal.byte(rb<R_COLUPF>(r)), cb = pal.byte(rb<R_COLUBK>(r));
+    const uint32_t cl = (ctrlpf & 2) ? c0 : cf, cr = (ctrlpf & 2) ? c1 : cf;
+    if (ctrlpf & 4) {        // PF above the players: indices with PF set take the playfield colour
+        ps.lo_l = cb | (cl << 8) | (c1 << 16) | (cl << 24);
+        ps.hi_l = c0 | (cl << 8) | (c0 << 16) | (cl << 24);
+        ps.lo_r = cb | (cr << 8) | (c1 << 16) | (cr << 24);
+        ps.hi_r = c0 | (cr << 8) | (c0 << 16) | (cr << 24);
+    } else {                 // P0 > P1 > PF > BK
+        ps.lo_l = cb | (cl << 8) | (c1 << 16) | (c1 << 24);
+        ps.lo_r = cb | (cr << 8) | (c1 << 16) | (c1 << 24);
+        ps.hi_l = ps.hi_r = c0 * 0x01010101u;
+    }
+}
+
+// bit j of the 4-bit n -> bit 0 of byte j
+__device__ __forceinline__ uint32_t spread4(uint32_t n) { return (n * 0x00204081u) & 0x01010101u; }
+
+// the 16 pixels x0 .. x0+15 of the common case from the per-row state: per
+// 4 pixels, each byte's table index from the three masks, then one byte
+// permute through the table
+__device__ __forceinline__ uint4 draw16_row(const PlainRow& ps, const Regs& r, uint32_t x0) {
+    if (ps.blank) return make_uint4(0, 0, 0, 0);
+    const bool right = x0 >= 80;
+    uint32_t n;
+    if (!right) n = (r.pfm >> (x0 >> 2)) & 0xF;
+    else if (!(rb<R_CTRLPF>(r) & 1)) n = (r.pfm >> ((x0 - 80) >> 2)) & 0xF;
+    else n = rev4((r.pfm >> (16 - ((x0 - 80) >> 2))) & 0xF);
+    const uint32_t mpf = ((n & 1) | ((n & 2) << 3) | ((n & 4) << 6) | ((n & 8) << 9)) * 0xF;
+    const uint32_t m0 = window16s(ps.s0, 8, ps.p0x, x0), m1 = window16s(ps.s1, 8, ps.p1x, x0);
+    const uint32_t lo = right ? ps.lo_r : ps.lo_l, hi = right ? ps.hi_r : ps.hi_l;
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t sel = spread4((mpf >> (4 * k)) & 0xF) | (spread4((m1 >> (4 * k)) & 0xF) << 1) |
+                             (spread4((m0 >> (4 * k)) & 0xF) << 2);
+        w[k] = __builtin_amdgcn_perm(hi, lo, sel);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
 
 // the 16 pixels of the common case: one copy of each player at normal width,
 // no missile, no ball, no vertical delay, no HMOVE blank
@@ -142,18 +206,23 @@ __device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, co
         return ei < cnt ? q0 : 0u;
     };
     uint32_t e = cnt ? q0 : 0u;
+    PlainRow ps;
+    plain_row(ps, r, pal);
     for (int seg = 0; seg < kCols / 16; ++seg) {
         const uint32_t x0 = 16u * (uint32_t)seg;
-        while (ei < cnt && (e & 0xFF) <= x0) {      // writes that take effect before the segment
-            apply(r, e);
-            e = next_entry();
+        if (ei < cnt && (e & 0xFF) <= x0) {
+            do {                                    // writes that take effect before the segment
+                apply(r, e);
+                e = next_entry();
+            } while (ei < cnt && (e & 0xFF) <= x0);
+            plain_row(ps, r, pal);
         }
         uint4 out = make_uint4(0, 0, 0, 0);
         uint32_t start = 0;                         // first pixel of the current run
         for (;;) {
             const bool more = ei < cnt && (e & 0xFF) < x0 + 16;
             const uint32_t end = more ? (e & 0xFF) - x0 : 16;
-            const uint4 px = draw16(r, x0, (uint32_t)row, pal);
+            const uint4 px = ps.plain ? draw16_row(ps, r, x0) : draw16(r, x0, (uint32_t)row, pal);
             const uint32_t run = ((1u << end) - 1) & ~((1u << start) - 1);
             out.x = pick(byte_masks(run & 0xF), px.x, out.x);
             out.y = pick(byte_masks((run >> 4) & 0xF), px.y, out.y);
@@ -165,6 +234,7 @@ __device__ __forceinline__ void render_row(const uint8_t* frame_log, int row, co
                 apply(r, e);
                 e = next_entry();
             }
+            plain_row(ps, r, pal);
             start = end;
         }
         emit(seg, out);

@@ -344,22 +344,31 @@ __global__ void __launch_bounds__(512) k_render_obs(RenderArgs A) {
         return;
     }
     if (!want_obs) return;                // the reset kernel writes the cache observation
-    // exact-area 210x160 -> 84x84
-    for (int o = threadIdx.x; o < kObsBytes; o += blockDim.x) {
-        const int oi = o / kObs, oj = o - oi * kObs;
-        const int mrow = oi >> 1;
-        const int r0 = (oi & 1) ? 5 * mrow + 2 : 5 * mrow;
-        const uint32_t wr0 = (oi & 1) ? 1 : 2, wr1 = 2, wr2 = (oi & 1) ? 2 : 1;
+    // Exact-area 210x160 -> 84x84.  Output rows 2k and 2k+1 cover source rows
+    // 5k .. 5k+4 (weights 2,2,1 and 1,2,2 in half rows); output column j covers
+    // source columns 40j/21 .. (40j+39)/21, at most three, weighted by their
+    // overlap in 1/21 pixels; the total weight is 200.  A work item is one
+    // (row pair, column): the column sums of its five source rows, then both
+    // outputs (integer sums in another grouping, so the same values).
+    for (int w = threadIdx.x; w < (kObs / 2) * kObs; w += blockDim.x) {
+        const int k = w / kObs, oj = w - k * kObs;
         const int c0 = (40 * oj) / 21, c1 = (40 * oj + 39) / 21;
-        uint32_t sum = 0;
-        for (int cc = c0; cc <= c1; ++cc) {
-            const int lo = max(40 * oj, 21 * cc), hi = min(40 * oj + 40, 21 * cc + 21);
-            const uint32_t wc = (uint32_t)(hi - lo);
-            const uint32_t col = wr0 * m[r0 * kCols + cc] + wr1 * m[(r0 + 1) * kCols + cc] +
-                                 wr2 * m[(r0 + 2) * kCols + cc];
-            sum += wc * col;
+        uint32_t wc[3], cc[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int c = c0 + j;
+            wc[j] = c <= c1 ? (uint32_t)(min(40 * oj + 40, 21 * c + 21) - max(40 * oj, 21 * c)) : 0u;
+            cc[j] = (uint32_t)min(c, kCols - 1);      // a weight-0 column is read in range
         }
-        A.obs[(size_t)i * kObsBytes + o] = (uint8_t)((sum + 100) / 200);
+        uint32_t s5[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const uint8_t* src = m + (5 * k + r) * kCols;
+            s5[r] = wc[0] * src[cc[0]] + wc[1] * src[cc[1]] + wc[2] * src[cc[2]];
+        }
+        uint8_t* out = A.obs + (size_t)i * kObsBytes + 2 * k * kObs + oj;
+        out[0] = (uint8_t)((2 * s5[0] + 2 * s5[1] + s5[2] + 100) / 200);
+        out[kObs] = (uint8_t)((s5[2] + 2 * s5[3] + 2 * s5[4] + 100) / 200);
     }
 }
 

@@ -979,6 +979,7 @@ struct Fast {
     uint32_t logon;
     uint32_t partial;   // 1: other running lanes are elsewhere; stop at the next line start
     uint32_t stop;
+    uint32_t lim;       // cap, or 0 once the run must stop: one compare ends the run for either
 };
 
 __device__ __forceinline__ bool all_lanes(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
@@ -1265,7 +1266,9 @@ __device__ __forceinline__ uint32_t store_value(const Cpu& c) {
 __device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t t, uint32_t wsync) {
     F.pc = next;
     F.cyc = wsync ? 76 * (t / 76 + 1) : t + 1;
-    F.stop = wsync & F.partial;
+    const uint32_t s = wsync & F.partial;
+    F.stop = s;
+    F.lim &= s - 1u;
     return FS_NEXT;
 }
 
@@ -1517,6 +1520,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
     F.bank = rfl(c.bank);
     F.cyc = rfl(c.cyc);
     F.cap = rfl(c.cap);
+    F.lim = F.cap;
     F.fl = rfl(c.fl);
     F.orow = (uint32_t)(rfl(c.open_row) + 1);
     F.ocnt = rfl(c.open_cnt);
@@ -1528,26 +1532,35 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
     // Two loops: the inner one handles only the most frequent opcodes of
     // typical cartridge code, so few values merge at its back edge and the
     // compiler keeps the state in place; any other opcode goes through the
-    // full dispatch once, then the inner loop resumes.
+    // full dispatch once, then the inner loop resumes.  The pc is checked
+    // against the cartridge window only on entry and after a full-dispatch
+    // instruction: an instruction the inner loop runs is marked in the
+    // predecoded word (bit 31) when it could leave the window (it ends
+    // within 2 bytes of the bank's end, or is a branch whose target is
+    // outside), and a marked word never matches a frequent opcode.
     for (;;) {
         uint32_t op = 0, b1 = 0, b2 = 0, aux = 0;
         uint32_t cold = 0;
+        if (F.cyc >= F.lim) {
+            capped = F.lim != 0;
+            break;
+        }
+        if ((F.pc & 0x1FFF) - 0x1000u > 0xFFDu) {   // outside the cartridge, or too close to its end
+            st = FS_EXIT;
+            break;
+        }
         for (;;) {
-            if (F.cyc >= F.cap) {
-                capped = 1;
-                break;
-            }
-            if ((F.pc & 0x1FFF) - 0x1000u > 0xFFDu) {   // outside the cartridge, or too close to its end
-                st = FS_EXIT;
+            if (F.cyc >= F.lim) {      // the frame's last cycle, or a stop
+                capped = F.lim != 0;
                 break;
             }
             const uint32_t q = pre[(F.bank << 12) | (F.pc & 0xFFF)];
-            op = q & 0xFF;
+            const uint32_t hq = q & 0x800000FFu;   // the opcode, or no frequent one when marked
             b1 = (q >> 8) & 0xFF;
             b2 = (q >> 16) & 0xFF;
-            aux = q >> 24;
+            aux = (q >> 24) & 0x7F;
 #define VCS_HOT(o)                                            \
-    if (op == (o)) {                                          \
+    if (hq == (o)) {                                          \
         if ((st = fop<(o), TRACK>(c, W, F, b1, b2, aux)) != FS_NEXT) break; \
     }
             VCS_HOT(0x85)                    // STA zp
@@ -1559,12 +1572,12 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
             else VCS_HOT(0x45)               // EOR zp
             else VCS_HOT(0xA9)               // LDA #
             else {
+                op = q & 0xFF;
                 cold = 1;
                 break;
             }
 #undef VCS_HOT
             ++done_n;
-            if (F.stop) break;
         }
         if (!cold) break;
         switch (op) {
@@ -1575,7 +1588,6 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
         }
         if (st != FS_NEXT) break;
         ++done_n;
-        if (F.stop) break;
     }
     if (capped) {
         c.err |= ERR_FRAME_CAP;
@@ -1652,7 +1664,7 @@ __device__ __forceinline__ uint32_t mop(Cpu& c, const Wave& W, Fast& F, bool in_
         F.cyc += N;
         return FS_NEXT;
     } else if constexpr (MD == ZP && store_mn(MN)) {
-        const uint32_t auxa = qa >> 24, auxb = qb >> 24;      // store classes
+        const uint32_t auxa = (qa >> 24) & 0x7F, auxb = (qb >> 24) & 0x7F;      // store classes
         const uint32_t cat = auxa < SC_TIA ? auxa : (auxa & 0xE0);
         if (cat != (auxb < SC_TIA ? auxb : (auxb & 0xE0))) return FS_EXIT;
         const uint32_t t = F.cyc + N - 1;
@@ -1740,6 +1752,7 @@ __device__ __forceinline__ bool run_mb(Cpu& c, const Wave& W, const uint32_t* pr
     F.bank = ba;
     F.cyc = rfl(c.cyc);
     F.cap = rfl(c.cap);
+    F.lim = F.cap;
     F.fl = rfl(c.fl);
     F.orow = (uint32_t)(rfl(c.open_row) + 1);
     F.ocnt = rfl(c.open_cnt);
@@ -2210,8 +2223,11 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
 // (which also selects a slice) is SC_3F when the TIA register it reaches is
 // not emulated, else SC_EXIT (left to the per-lane path); on Superchip
 // cartridges an absolute access to the RAM window is SC_XRAM; with tracked
-// collisions a zero-page / absolute read of a latch register is SC_EXIT.
-// Entries past offset $FFD are never used.
+// collisions a zero-page / absolute read of a latch register is SC_EXIT
+// (aux takes 7 bits).  Bit 31 marks an instruction after which the pc may
+// leave the window $000-$FFD of the bank: one that ends past $FFD, or a
+// branch whose target is outside it.  Entries past offset $FFD are never
+// used.
 __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre, uint32_t track) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R.n_vbanks * 4096u) return;
@@ -2234,7 +2250,12 @@ __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre, uint32
     const uint32_t ra = md == ZP ? b1 : abs_addr;
     if (track && (md == ZP || md == ABS) && ((d >> DW_RD) & 1) && !((d >> DW_WR) & 1) && !(ra & 0x1080) && (ra & 0xF) < 8)
         aux = SC_EXIT;
-    pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24);
+    bool edge = off + ((d >> DW_LEN) & 3) > 0xFFD;
+    if ((op & 0x1F) == 0x10) {             // conditional branch: its target
+        const int32_t t = (int32_t)off + 2 + (int32_t)(int8_t)b1;
+        edge = edge || t < 0 || t > 0xFFD;
+    }
+    pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24) | ((edge ? 1u : 0u) << 31);
 }
 
 void launch_predecode(const uint8_t* rom, const RomInfo& info, uint32_t* pre, uint32_t track, hipStream_t s) {

@@ -41,11 +41,11 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 # ones they were taken on (sha256 prefix of the files concatenated), otherwise
 # null.
 MEASURED_TRAFFIC = {
-    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "57d7416b978beaff", (1306.0 * 2.0 + 162348.0) * 1024),
+    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "8ec161d2d4567826", (1277.3 * 2.0 + 162348.0) * 1024),
     "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "cf7f1f1949ac57e7",
                         (41151.0 * 2.0 + 268800.0) * 1024),
     "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "cf7f1f1949ac57e7",
-                     (41135.7 * 2.0 + 297219.0) * 1024),
+                     (41136.4 * 2.0 + 297220.0) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9

@@ -210,14 +210,14 @@ def interp_latency(kern, passes, rounds, env_rom, tile=64):
     stream: cycles per wave instruction pass if every wave lived the whole
     launch (an upper bound: waves that end early leave their SIMDs idle),
     next to the cost of a pass for a wave on the plain step (SQ counters:
-    570 cycles, half of them issuing) and the scheduling rounds."""
+    536 cycles, half of them issuing) and the scheduling rounds."""
     t = kern["k_interp"]["mean_ms"] * 1e-3
     counts = np.bincount(np.asarray(env_rom, dtype=np.int64))
     waves = int(sum((int(c) + tile - 1) // tile for c in counts if c))
     cyc = t * CLOCK_HZ * waves / passes if passes else None
     return {"bound": "latency", "waves": waves, "wave_passes": passes, "scheduling_rounds": rounds,
             "passes_per_round": passes / rounds if rounds else None,
-            "cycles_per_pass_if_all_waves_lived_the_launch": cyc, "cycles_per_pass_plain_step_counters": 570}
+            "cycles_per_pass_if_all_waves_lived_the_launch": cyc, "cycles_per_pass_plain_step_counters": 536}
 
 
 def lane_util(instr, passes):

@@ -1274,13 +1274,16 @@ __device__ __forceinline__ uint32_t fast_finish(Fast& F, uint32_t next, uint32_t
 
 // One instruction with opcode OP (a compile-time constant, so addressing
 // mode, operation and base cycles are folded) for every lane in exec;
-// TRACK: collision latches tracked.
-template <int OP, bool TRACK>
+// TRACK: collision latches tracked.  HOT: run from the hot loop, so the
+// instruction is unmarked (it and a branch target stay inside the bank's
+// window, and the pc needs no 16-bit wrap).
+template <int OP, bool TRACK, bool HOT = false>
 __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t b1, uint32_t b2, uint32_t aux) {
     constexpr OpInfo I = decode(OP);
     constexpr int MD = I.md, MN = I.mn;
     constexpr uint32_t N = (uint32_t)I.cyc;
-    const uint32_t next = (F.pc + (uint32_t)op_len(MD)) & 0xFFFF;
+    constexpr uint32_t kPcMask = HOT ? 0xFFFFFFFFu : 0xFFFFu;
+    const uint32_t next = (F.pc + (uint32_t)op_len(MD)) & kPcMask;
     if constexpr (MN == ILL || MN == BRK || MN == RTI || MD == IZX || MD == IZY || MD == IND || MN >= SLO ||
                   (MN == NOP && MD != IMP)) {
         return FS_EXIT;   // left to the per-lane path (undocumented opcodes included)
@@ -1477,7 +1480,7 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
         else if constexpr (MN == BCS) taken = (c.p & FC) != 0;
         else if constexpr (MN == BNE) taken = !(c.p & FZ);
         else taken = (c.p & FZ) != 0;
-        const uint32_t tgt = (next + (uint32_t)sext8(b1)) & 0xFFFF;
+        const uint32_t tgt = (next + (uint32_t)sext8(b1)) & kPcMask;
         const uint32_t extra = 1 + (((tgt ^ next) & 0xFF00) ? 1 : 0);
         const uint64_t tk = __builtin_amdgcn_ballot_w64(taken);
         if (tk == 0) {
@@ -1561,7 +1564,7 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
             aux = (q >> 24) & 0x7F;
 #define VCS_HOT(o)                                            \
     if (hq == (o)) {                                          \
-        if ((st = fop<(o), TRACK>(c, W, F, b1, b2, aux)) != FS_NEXT) break; \
+        if ((st = fop<(o), TRACK, true>(c, W, F, b1, b2, aux)) != FS_NEXT) break; \
     }
             VCS_HOT(0x85)                    // STA zp
             else VCS_HOT(0xA5)               // LDA zp

@@ -41,7 +41,7 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 # ones they were taken on (sha256 prefix of the files concatenated), otherwise
 # null.
 MEASURED_TRAFFIC = {
-    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "8ec161d2d4567826", (1277.3 * 2.0 + 162348.0) * 1024),
+    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "2791e2b134ff97d9", (1275.0 * 2.0 + 162348.0) * 1024),
     "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "cf7f1f1949ac57e7",
                         (41151.0 * 2.0 + 268800.0) * 1024),
     "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "cf7f1f1949ac57e7",
@@ -210,14 +210,14 @@ def interp_latency(kern, passes, rounds, env_rom, tile=64):
     stream: cycles per wave instruction pass if every wave lived the whole
     launch (an upper bound: waves that end early leave their SIMDs idle),
     next to the cost of a pass for a wave on the plain step (SQ counters:
-    536 cycles, half of them issuing) and the scheduling rounds."""
+    533 cycles, half of them issuing) and the scheduling rounds."""
     t = kern["k_interp"]["mean_ms"] * 1e-3
     counts = np.bincount(np.asarray(env_rom, dtype=np.int64))
     waves = int(sum((int(c) + tile - 1) // tile for c in counts if c))
     cyc = t * CLOCK_HZ * waves / passes if passes else None
     return {"bound": "latency", "waves": waves, "wave_passes": passes, "scheduling_rounds": rounds,
             "passes_per_round": passes / rounds if rounds else None,
-            "cycles_per_pass_if_all_waves_lived_the_launch": cyc, "cycles_per_pass_plain_step_counters": 536}
+            "cycles_per_pass_if_all_waves_lived_the_launch": cyc, "cycles_per_pass_plain_step_counters": 533}
 
 
 def lane_util(instr, passes):

@@ -35,17 +35,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
-# HBM bytes per launch on the plain 4096-env step, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by a 256 MiB copy's readings (read x2.000, write x1.000);
-# reported only while the kernel source and the headers it includes are the
-# ones they were taken on (sha256 prefix of the files concatenated), otherwise
-# null.
+# HBM bytes per launch, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
+# 256 MiB copy's readings (read x2.000, write x1.000), on the plain 4096-env
+# step and on the 65,536-env batching workload; reported only while the
+# kernel source and the headers it includes are the ones they were taken on
+# (sha256 prefix of the files concatenated), otherwise null.
+_INTERP_SRC = ("interp.hip", "tia_draw.h", "vcs_device.h")
+_RENDER_SRC = ("render.hip", "tia_draw.h", "vcs_device.h")
 MEASURED_TRAFFIC = {
-    "k_interp": (("interp.hip", "tia_draw.h", "vcs_device.h"), "2791e2b134ff97d9", (1275.0 * 2.0 + 162348.0) * 1024),
-    "k_render_frames": (("render.hip", "tia_draw.h", "vcs_device.h"), "cf7f1f1949ac57e7",
-                        (41151.0 * 2.0 + 268800.0) * 1024),
-    "k_render_obs": (("render.hip", "tia_draw.h", "vcs_device.h"), "cf7f1f1949ac57e7",
-                     (41136.4 * 2.0 + 297220.0) * 1024),
+    ("k_interp", "plain_4096"): (_INTERP_SRC, "2791e2b134ff97d9", (1275.0 * 2.0 + 162348.0) * 1024),
+    ("k_render_frames", "plain_4096"): (_RENDER_SRC, "cf7f1f1949ac57e7", (41151.0 * 2.0 + 268800.0) * 1024),
+    ("k_render_obs", "plain_4096"): (_RENDER_SRC, "cf7f1f1949ac57e7", (41136.4 * 2.0 + 297220.0) * 1024),
+    ("k_interp", "batching_65536"): (_INTERP_SRC, "2791e2b134ff97d9", (17063.9 * 2.0 + 1655140.0) * 1024),
+    ("k_render_obs", "batching_65536"): (_RENDER_SRC, "cf7f1f1949ac57e7", (606482.0 * 2.0 + 452608.0) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
@@ -150,9 +152,9 @@ def cpu_baseline(w, roms, env_rom, steps):
             "cpu_model": cpu_model, "host_cpus": os.cpu_count()}
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload="plain_4096"):
     import hashlib
-    srcs, sha, nbytes = MEASURED_TRAFFIC[kernel]
+    srcs, sha, nbytes = MEASURED_TRAFFIC[(kernel, workload)]
     h = hashlib.sha256()
     for src in srcs:
         path = os.path.join(ROOT, "paper_1907_08467_amd", "csrc", src)
@@ -329,7 +331,7 @@ def bench_plain(args, c=2):
         "eager": {"value": eager_value, "ms_per_step": eager_ms, "steps": f"{W}..{W + K - 1}",
                   "episodes_ended": None if ep0 is None else ep1 - ep0},
         "graph": graph_res,
-        # counter figures exist for the plain 4096-env step only
+        # counter figures of this workload exist for the 4096-env step
         "roofline": dict(interp_roofline(kern, instr_last, n, w.frameskip),
                          traffic=measured_traffic("k_interp") if (n == 4096 and c == 2) else None),
         "render_roofline": dict(render_roofline(kern, n, w.frameskip, True),
@@ -410,8 +412,12 @@ def bench_batching(args):
                      "wave_rounds": rounds,
                      "interp_latency": interp_latency(kern, passes, rounds, env_rom, launch["tile_envs"]),
                      "launch_from": launch_from, "kernels_ms": {k: v["mean_ms"] for k, v in kern.items()},
-                     "roofline": interp_roofline(kern, instr_last, n, w.frameskip),
-                     "render_roofline": render_roofline(kern, n, 2, False), "errors": bits}
+                     "roofline": dict(interp_roofline(kern, instr_last, n, w.frameskip),
+                                      traffic=measured_traffic("k_interp", "batching_65536") if n == 65536 else None),
+                     "render_roofline": dict(render_roofline(kern, n, 2, False),
+                                             traffic={"k_render_obs": measured_traffic("k_render_obs", "batching_65536")
+                                                      if n == 65536 else None}),
+                     "errors": bits}
         print(f"{form}: {res[form]['value']:.4g} raw frames/s", file=sys.stderr, flush=True)
         del env
         torch.cuda.empty_cache()

@@ -1375,12 +1375,17 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
                 dm = dec_mode(c);
                 if (dm == 2) return FS_EXIT;
             }
-            if (TRACK && aux == SC_EXIT) return FS_EXIT;   // a latch read: the per-lane path scans the log
             uint32_t v;
-            if (MD == ABS && aux == SC_XRAM)      // Superchip RAM: read port, or the write port (0)
-                v = (a & 0x80) ? (uint32_t)c.xram[a & 0x7F] : 0u;
-            else
-                v = fast_rd(c, W, F, a, t);
+            if constexpr (HOT && MD == ZP) {
+                // unmarked zero-page read: RAM (reads below $80 are marked)
+                v = W.ram[c.ram_off + (a & 0x7F)];
+            } else {
+                if (TRACK && aux == SC_EXIT) return FS_EXIT;   // a latch read: the per-lane path scans the log
+                if (MD == ABS && aux == SC_XRAM)      // Superchip RAM: read port, or the write port (0)
+                    v = (a & 0x80) ? (uint32_t)c.xram[a & 0x7F] : 0u;
+                else
+                    v = fast_rd(c, W, F, a, t);
+            }
             fast_alu(c, MN, v, dm);
             F.pc = next;
             F.cyc += N;
@@ -1540,7 +1545,9 @@ __device__ __forceinline__ bool run_fast(Cpu& c, const Wave& W, const uint32_t* 
     // instruction: an instruction the inner loop runs is marked in the
     // predecoded word (bit 31) when it could leave the window (it ends
     // within 2 bytes of the bank's end, or is a branch whose target is
-    // outside), and a marked word never matches a frequent opcode.
+    // outside), and a marked word never matches a frequent opcode.  Zero-
+    // page reads below $80 (TIA) are marked too, so the inner loop's reads
+    // are RAM reads.
     for (;;) {
         uint32_t op = 0, b1 = 0, b2 = 0, aux = 0;
         uint32_t cold = 0;
@@ -2227,10 +2234,11 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
 // not emulated, else SC_EXIT (left to the per-lane path); on Superchip
 // cartridges an absolute access to the RAM window is SC_XRAM; with tracked
 // collisions a zero-page / absolute read of a latch register is SC_EXIT
-// (aux takes 7 bits).  Bit 31 marks an instruction after which the pc may
-// leave the window $000-$FFD of the bank: one that ends past $FFD, or a
-// branch whose target is outside it.  Entries past offset $FFD are never
-// used.
+// (aux takes 7 bits).  Bit 31 marks an instruction the scalar hot loop
+// leaves to the full dispatch: one after which the pc may leave the window
+// $000-$FFD of the bank (it ends past $FFD, or is a branch whose target is
+// outside), or a zero-page read below $80 (a TIA read, not RAM).  Entries
+// past offset $FFD are never used.
 __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre, uint32_t track) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R.n_vbanks * 4096u) return;
@@ -2258,6 +2266,7 @@ __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre, uint32
         const int32_t t = (int32_t)off + 2 + (int32_t)(int8_t)b1;
         edge = edge || t < 0 || t > 0xFFD;
     }
+    if (md == ZP && ((d >> DW_RD) & 1) && b1 < 0x80) edge = true;   // a TIA read
     pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24) | ((edge ? 1u : 0u) << 31);
 }
 

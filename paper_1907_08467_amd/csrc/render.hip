@@ -97,13 +97,13 @@ __device__ __forceinline__ uint4 draw16_row(const PlainRow& ps, const Regs& r, u
     if (!right) n = (r.pfm >> (x0 >> 2)) & 0xF;
     else if (!(rb<R_CTRLPF>(r) & 1)) n = (r.pfm >> ((x0 - 80) >> 2)) & 0xF;
     else n = rev4((r.pfm >> (16 - ((x0 - 80) >> 2))) & 0xF);
-    const uint32_t mpf = ((n & 1) | ((n & 2) << 3) | ((n & 4) << 6) | ((n & 8) << 9)) * 0xF;
     const uint32_t m0 = window16s(ps.s0, 8, ps.p0x, x0), m1 = window16s(ps.s1, 8, ps.p1x, x0);
     const uint32_t lo = right ? ps.lo_r : ps.lo_l, hi = right ? ps.hi_r : ps.hi_l;
     uint32_t w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t sel = spread4((mpf >> (4 * k)) & 0xF) | (spread4((m1 >> (4 * k)) & 0xF) << 1) |
+        // a playfield bit covers one 4-pixel word: its index bit in all four bytes
+        const uint32_t sel = (((n >> k) & 1) * 0x01010101u) | (spread4((m1 >> (4 * k)) & 0xF) << 1) |
                              (spread4((m0 >> (4 * k)) & 0xF) << 2);
         w[k] = __builtin_amdgcn_perm(hi, lo, sel);
     }

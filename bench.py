@@ -43,11 +43,11 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 _INTERP_SRC = ("interp.hip", "tia_draw.h", "vcs_device.h")
 _RENDER_SRC = ("render.hip", "tia_draw.h", "vcs_device.h")
 MEASURED_TRAFFIC = {
-    ("k_interp", "plain_4096"): (_INTERP_SRC, "128b09130dc593d2", (1354.2 * 2.0 + 162348.0) * 1024),
-    ("k_render_frames", "plain_4096"): (_RENDER_SRC, "cf7f1f1949ac57e7", (41151.0 * 2.0 + 268800.0) * 1024),
-    ("k_render_obs", "plain_4096"): (_RENDER_SRC, "cf7f1f1949ac57e7", (41135.8 * 2.0 + 297217.0) * 1024),
-    ("k_interp", "batching_65536"): (_INTERP_SRC, "128b09130dc593d2", (17238.1 * 2.0 + 1655920.0) * 1024),
-    ("k_render_obs", "batching_65536"): (_RENDER_SRC, "cf7f1f1949ac57e7", (606482.0 * 2.0 + 452608.0) * 1024),
+    ("k_interp", "plain_4096"): (_INTERP_SRC, "128b09130dc593d2", (1353.7 * 2.0 + 162348.0) * 1024),
+    ("k_render_frames", "plain_4096"): (_RENDER_SRC, "f7363e502d223ad4", (41151.0 * 2.0 + 268800.0) * 1024),
+    ("k_render_obs", "plain_4096"): (_RENDER_SRC, "f7363e502d223ad4", (41137.2 * 2.0 + 297222.0) * 1024),
+    ("k_interp", "batching_65536"): (_INTERP_SRC, "128b09130dc593d2", (17204.1 * 2.0 + 1655990.0) * 1024),
+    ("k_render_obs", "batching_65536"): (_RENDER_SRC, "f7363e502d223ad4", (606480.0 * 2.0 + 452608.0) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
 ALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9

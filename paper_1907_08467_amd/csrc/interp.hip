@@ -1047,8 +1047,9 @@ __device__ __forceinline__ uint32_t store_class(uint32_t a) {
 // registers (the other player's graphics; with GRP1, ENABL), which the
 // renderer repeats from its own state.  Returns 0, before changing anything,
 // when the row's entries are full (the per-lane path then records the error).
-// PLAIN: `sc` is known to be SC_TIA | code (a register stored as is); the
-// code may then differ between lanes.
+// PLAIN 1: `sc` is known to be SC_TIA | code (a register stored as is); the
+// code may then differ between lanes.  PLAIN 2: `sc` is SC_TIA or SC_TIAG |
+// code (no object reset, enable or vertical-delay register).
 template <int PLAIN = 0>
 __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F, uint32_t sc, uint32_t v,
                                                   uint32_t t) {
@@ -1057,7 +1058,7 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
     uint8_t* R = W.tia + c.tia_off;
     uint32_t code = sc & 0x1F;
     uint32_t v0 = v, full = 0;
-    if (!PLAIN && sc >= SC_TIAS && sc < SC_TIAG) {
+    if (PLAIN == 0 && sc >= SC_TIAS && sc < SC_TIAG) {
         if (code == R_P0X || code == R_P1X) {
             v0 = h < 68 ? 3u : (h - 68 + 5) % 160;
         } else if (code >= R_M0X && code <= R_BLX) {
@@ -1104,7 +1105,7 @@ __device__ __forceinline__ uint32_t fast_tia_code(Cpu& c, const Wave& W, Fast& F
             }
         }
     }
-    if (!PLAIN && sc >= SC_TIAG) {
+    if (PLAIN != 1 && sc >= SC_TIAG) {
         if (code == R_GRP0) {
             R[R_GRP1_OLD] = R[R_GRP1];
         } else {
@@ -1396,7 +1397,8 @@ __device__ __forceinline__ uint32_t fop(Cpu& c, const Wave& W, Fast& F, uint32_t
             if (aux == SC_RAM) {
                 W.ram[c.ram_off + (a & 0x7F)] = (uint8_t)v;
             } else if (aux >= SC_TIA) {
-                if (!fast_tia_code(c, W, F, aux, v & 0xFF, t)) return FS_EXIT;
+                // from the hot loop a zero-page store is not an object reset or enable (marked)
+                if (!fast_tia_code<(HOT && MD == ZP) ? 2 : 0>(c, W, F, aux, v & 0xFF, t)) return FS_EXIT;
             } else if (aux == SC_WSYNC) {
                 return fast_finish(F, next, t, 1);
             } else if (aux == SC_EXIT) {
@@ -2237,8 +2239,9 @@ __global__ void __launch_bounds__(kLanes) k_interp(InterpArgs A, const uint32_t*
 // (aux takes 7 bits).  Bit 31 marks an instruction the scalar hot loop
 // leaves to the full dispatch: one after which the pc may leave the window
 // $000-$FFD of the bank (it ends past $FFD, or is a branch whose target is
-// outside), or a zero-page read below $80 (a TIA read, not RAM).  Entries
-// past offset $FFD are never used.
+// outside), a zero-page read below $80 (a TIA read, not RAM), or a
+// zero-page store to an object reset, enable or vertical-delay register.
+// Entries past offset $FFD are never used.
 __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre, uint32_t track) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R.n_vbanks * 4096u) return;
@@ -2267,6 +2270,7 @@ __global__ void k_predecode(const uint8_t* rom, RomInfo R, uint32_t* pre, uint32
         edge = edge || t < 0 || t > 0xFFD;
     }
     if (md == ZP && ((d >> DW_RD) & 1) && b1 < 0x80) edge = true;   // a TIA read
+    if (md == ZP && st && aux >= SC_TIAS && aux < SC_TIAG) edge = true;   // an object reset or enable
     pre[i] = op | (b1 << 8) | (b2 << 16) | (aux << 24) | ((edge ? 1u : 0u) << 31);
 }
 

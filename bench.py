@@ -43,10 +43,10 @@ KERNELS = {0: "k_interp", 1: "k_render_frames", 2: "k_render_obs", 3: "k_reset"}
 _INTERP_SRC = ("interp.hip", "tia_draw.h", "vcs_device.h")
 _RENDER_SRC = ("render.hip", "tia_draw.h", "vcs_device.h")
 MEASURED_TRAFFIC = {
-    ("k_interp", "plain_4096"): (_INTERP_SRC, "a23885e1c56a84e8", (1271.5 * 2.0 + 162348.0) * 1024),
+    ("k_interp", "plain_4096"): (_INTERP_SRC, "437de748e86a04c8", (1273.0 * 2.0 + 162348.0) * 1024),
     ("k_render_frames", "plain_4096"): (_RENDER_SRC, "f7363e502d223ad4", (41151.0 * 2.0 + 268800.0) * 1024),
     ("k_render_obs", "plain_4096"): (_RENDER_SRC, "f7363e502d223ad4", (41137.2 * 2.0 + 297222.0) * 1024),
-    ("k_interp", "batching_65536"): (_INTERP_SRC, "a23885e1c56a84e8", (17158.1 * 2.0 + 1669280.0) * 1024),
+    ("k_interp", "batching_65536"): (_INTERP_SRC, "437de748e86a04c8", (17241.2 * 2.0 + 1648190.0) * 1024),
     ("k_render_obs", "batching_65536"): (_RENDER_SRC, "f7363e502d223ad4", (606480.0 * 2.0 + 452608.0) * 1024),
 }
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer VALU lane-ops
@@ -212,14 +212,14 @@ def interp_latency(kern, passes, rounds, env_rom, tile=64):
     stream: cycles per wave instruction pass if every wave lived the whole
     launch (an upper bound: waves that end early leave their SIMDs idle),
     next to the cost of a pass for a wave on the plain step (SQ counters:
-    493 cycles, half of them issuing) and the scheduling rounds."""
+    471 cycles, half of them issuing) and the scheduling rounds."""
     t = kern["k_interp"]["mean_ms"] * 1e-3
     counts = np.bincount(np.asarray(env_rom, dtype=np.int64))
     waves = int(sum((int(c) + tile - 1) // tile for c in counts if c))
     cyc = t * CLOCK_HZ * waves / passes if passes else None
     return {"bound": "latency", "waves": waves, "wave_passes": passes, "scheduling_rounds": rounds,
             "passes_per_round": passes / rounds if rounds else None,
-            "cycles_per_pass_if_all_waves_lived_the_launch": cyc, "cycles_per_pass_plain_step_counters": 493}
+            "cycles_per_pass_if_all_waves_lived_the_launch": cyc, "cycles_per_pass_plain_step_counters": 471}
 
 
 def lane_util(instr, passes):
